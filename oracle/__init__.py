@@ -1,0 +1,132 @@
+"""The oracle: a plain, sequential FP64 CPU Kalman filter + RTS smoother.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library (``paper_1905_13002_amd``) and imports nothing from it.
+
+* :func:`kf_rts` / :func:`kf_rts_batched` wrap ``kfrts.c`` (plain C, FP64,
+  built with ``gcc -O3 -ffp-contract=off``): the textbook recursions that the
+  paper's parallel method reproduces exactly (Theorems 1 and 2).
+* :mod:`oracle.elements` restates the paper's linear/Gaussian elements and
+  associative operators (Lemmas 1-4) in numpy FP64, for operator-level checks.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kfrts.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``kfrts.c`` into ``liboracle.so`` next to it (gcc, FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O3", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
+               "-shared", "-pthread", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_kf_rts.restype = ctypes.c_int
+        lib.oracle_kf_rts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long] + [dp] * 15
+        lib.oracle_kf_rts_batched.restype = ctypes.c_int
+        lib.oracle_kf_rts_batched.argtypes = (
+            [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long), ctypes.c_int]
+            + [dp] * 13 + [ctypes.c_int])
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False):
+    """Run the sequential Kalman filter and (optionally) the RTS smoother.
+
+    ``y`` is ``[T, ny]``; returns a dict with ``m [T,nx]``, ``P [T,nx,nx]`` and,
+    when ``smooth``, ``ms``, ``Ps``; with ``predicted`` also ``mp``, ``Pp``
+    (the one-step predictions m^-_k, P^-_k).
+    """
+    lib = _load()
+    F, Q, H, R, m0, P0, y = map(_f64, (F, Q, H, R, m0, P0, y))
+    u, d = _f64(u), _f64(d)
+    nx, ny = F.shape[0], H.shape[0]
+    y = y.reshape(-1, ny)
+    T = y.shape[0]
+    m = np.empty((T, nx))
+    P = np.empty((T, nx, nx))
+    ms = np.empty((T, nx)) if smooth else None
+    Ps = np.empty((T, nx, nx)) if smooth else None
+    mp = np.empty((T, nx)) if predicted else None
+    Pp = np.empty((T, nx, nx)) if predicted else None
+    st = lib.oracle_kf_rts(nx, ny, T, _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0),
+                           _p(y), _p(m), _p(P), _p(ms), _p(Ps), _p(mp), _p(Pp))
+    if st:
+        raise OracleError("oracle: Cholesky failed (code %d)" % st)
+    out = {"m": m, "P": P}
+    if smooth:
+        out.update(ms=ms, Ps=Ps)
+    if predicted:
+        out.update(mp=mp, Pp=Pp)
+    return out
+
+
+def kf_rts_batched(F, Q, H, R, m0, P0, y, offsets, u=None, d=None, per_sequence=False,
+                   threads=None, smooth=True):
+    """Independent sequences packed back to back; see ``oracle_kf_rts_batched``."""
+    lib = _load()
+    F, Q, H, R, m0, P0, y = map(_f64, (F, Q, H, R, m0, P0, y))
+    u, d = _f64(u), _f64(d)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    nx = F.shape[-1]
+    ny = H.shape[-2]
+    B = offsets.shape[0] - 1
+    total = int(offsets[-1])
+    y = y.reshape(total, ny)
+    m = np.empty((total, nx))
+    P = np.empty((total, nx, nx))
+    ms = np.empty((total, nx)) if smooth else None
+    Ps = np.empty((total, nx, nx)) if smooth else None
+    if threads is None:
+        threads = os.cpu_count() or 1
+    st = lib.oracle_kf_rts_batched(
+        nx, ny, B, offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), 1 if per_sequence else 0,
+        _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0), _p(y), _p(m), _p(P),
+        _p(ms), _p(Ps), int(threads))
+    if st:
+        raise OracleError("oracle: Cholesky failed in sequence %d" % (st - 1))
+    out = {"m": m, "P": P}
+    if smooth:
+        out.update(ms=ms, Ps=Ps)
+    return out
+
+
+if __name__ == "__main__":  # pragma: no cover
+    print(build(force=True), file=sys.stderr)

@@ -1,0 +1,65 @@
+"""Dense joint-Gaussian (batch least-squares) posterior of a linear/Gaussian model.
+
+An independent check of the sequential oracle: all states x_1..x_T are an
+affine map of (x_0, q_0, ..., q_{T-1}), so X and Y = H X + d + r are jointly
+Gaussian and the smoothed moments are the conditional moments E[X | Y],
+Cov[X | Y] computed with one dense solve.  The filtered moment at step k is
+the same computation restricted to y_1..y_k, read at its last block.
+Works with singular Q.  No recursion, no Kalman gain, no element or operator.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _stack_maps(F, T):
+    nx = F.shape[0]
+    # X = Phi x0 + G w,  w = (q_0, ..., q_{T-1})
+    Phi = np.zeros((T * nx, nx))
+    G = np.zeros((T * nx, T * nx))
+    Fp = [np.eye(nx)]
+    for _ in range(T):
+        Fp.append(F @ Fp[-1])
+    for k in range(T):                 # block k holds x_{k+1}
+        Phi[k * nx:(k + 1) * nx] = Fp[k + 1]
+        for i in range(k + 1):         # q_i enters x_{i+1} and later
+            G[k * nx:(k + 1) * nx, i * nx:(i + 1) * nx] = Fp[k - i]
+    return Phi, G
+
+
+def joint_moments(F, Q, H, R, m0, P0, T, u=None, d=None):
+    nx, ny = F.shape[0], H.shape[0]
+    u = np.zeros(nx) if u is None else np.asarray(u, float)
+    d = np.zeros(ny) if d is None else np.asarray(d, float)
+    Phi, G = _stack_maps(F, T)
+    muX = Phi @ m0 + G @ np.tile(u, T)
+    SigW = np.kron(np.eye(T), Q)
+    SigX = Phi @ P0 @ Phi.T + G @ SigW @ G.T
+    Hb = np.kron(np.eye(T), H)
+    muY = Hb @ muX + np.tile(d, T)
+    SigY = Hb @ SigX @ Hb.T + np.kron(np.eye(T), R)
+    SigXY = SigX @ Hb.T
+    return muX, SigX, muY, SigY, SigXY
+
+
+def posterior(F, Q, H, R, m0, P0, y, u=None, d=None):
+    """Returns (ms [T,nx], Ps [T,nx,nx]) = smoothed and (m, P) = filtered moments."""
+    y = np.asarray(y, float)
+    nx, ny = F.shape[0], H.shape[0]
+    T = y.shape[0]
+    muX, SigX, muY, SigY, SigXY = joint_moments(F, Q, H, R, m0, P0, T, u, d)
+    Yv = y.reshape(-1)
+    mean = muX + SigXY @ np.linalg.solve(SigY, Yv - muY)
+    cov = SigX - SigXY @ np.linalg.solve(SigY, SigXY.T)
+    ms = mean.reshape(T, nx)
+    Ps = np.stack([cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] for k in range(T)])
+    m = np.empty((T, nx))
+    P = np.empty((T, nx, nx))
+    for k in range(T):
+        n = (k + 1) * ny
+        sl = slice(k * nx, (k + 1) * nx)
+        SY = SigY[:n, :n]
+        SXY = SigXY[sl, :n]
+        m[k] = muX[sl] + SXY @ np.linalg.solve(SY, Yv[:n] - muY[:n])
+        P[k] = SigX[sl, sl] - SXY @ np.linalg.solve(SY, SXY.T)
+    return m, P, ms, Ps
