@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark: parallel Kalman filter + RTS smoother on one MI355X.
+
+Default workload: the 2-D constant-velocity tracking model (Section V of the
+paper), one sequence of T = 2**20 steps, nx = 4, ny = 2.  One "step" of the
+benchmark is one full pass of the hot path: model precompute, the forward
+filtering scan (Lemmas 1-2) and the reverse smoothing scan (Lemmas 3-4) over
+all T time steps, through the C ABI (pks_filter_smooth) on device-resident
+inputs.  The headline value is FP64 smoothed time steps per second; the mixed
+FP32 mode is measured the same way and reported beside it, with the maximum
+per-step relative error of every result against the sequential FP64 oracle.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2|4]
+
+Prints exactly one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (= 256 CU x 2.4 GHz x 128 flop/clk)
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector, published
+
+# Algorithmic work per time step and kernel at nx = 4 (flop counts of the
+# operators: full filtering combine 1238, combine with an A = 0 prefix 638,
+# filtering element 40; smoothing element 637, full smoothing combine 436,
+# combine with an E = 0 suffix 308).  Bytes: the method's own traffic
+# (y in, filtered moments out; filtered moments in, smoothed moments out).
+def kernel_model(nx, ny, rs):
+    mom = (nx + nx * nx) * rs
+    return {
+        "k_filter_reduce": dict(bytes=ny * rs, flops=1238 + 40),
+        "k_filter_down": dict(bytes=ny * rs + mom, flops=638 + 40),
+        "k_smoother_reduce": dict(bytes=mom, flops=637 + 436),
+        "k_smoother_down": dict(bytes=2 * mom, flops=637 + 308),
+    }
+
+
+KERNEL_SOURCES = ["paper_1905_13002_amd/csrc/small_ops.hpp", "paper_1905_13002_amd/csrc/scan_small_impl.hpp"]
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, precision, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload_name)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("sources_sha") != sources_sha():
+        return None
+    ent = rec.get("kernels", {}).get("%s/%s" % (precision, kernel))
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 4])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU (the scan of one GPU's share); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1905_13002_amd import pks, workloads as wl
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    w = wl.workload(args.workload)
+    T = w.total
+    nx, ny = w.model.nx, w.model.ny
+    batched = w.B > 1
+    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence)
+    off = torch.as_tensor(w.offsets).to(dev) if batched else None
+
+    results = {}
+    for prec in ("fp64", "mixed"):
+        rdt = torch.float64 if prec == "fp64" else torch.float32
+        y = torch.as_tensor(w.y).to(dev, rdt)
+        m = torch.empty((T, nx), dtype=rdt, device=dev)
+        P = torch.empty((T, nx, nx), dtype=rdt, device=dev)
+        ms = torch.empty_like(m)
+        Ps = torch.empty_like(P)
+        ws = pks.workspace(nx, ny, T, w.B, prec, dev)
+        if batched:
+            plan = pks.Plan(dm, y, off, prec)
+            m, P, ms, Ps = plan.m, plan.P, plan.ms, plan.Ps
+            step = plan.launch
+        else:
+            step = lambda: pks.filter_smooth(dm, y, prec, ws=ws, out=(m, P, ms, Ps))
+        sec = time_steps(step, args.steps, args.warmup, torch)
+        # per-kernel durations: HIP events around every launch, same workload
+        pks.profile_start()
+        for _ in range(args.steps):
+            if batched:
+                # graph replays hide individual launches: time the eager path
+                mm, PP = pks.filter_batched(dm, off, y, prec, ws=ws, out=(m, P))
+                pks.smooth_batched(dm, off, mm, PP, prec, ws=ws, out=(ms, Ps))
+            else:
+                step()
+        prof = pks.profile_stop()
+        torch.cuda.synchronize()
+        if batched:
+            step()
+            torch.cuda.synchronize()
+        out = {k: v.double().cpu().numpy() for k, v in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps))}
+        results[prec] = dict(sec=sec, prof=prof, out=out)
+
+    # accuracy against the oracle (FP64; the mixed reference uses the float32-rounded y)
+    def ref_for(prec):
+        yy = w.y if prec == "fp64" else w.y.astype(np.float32).astype(np.float64)
+        if batched:
+            return oracle.kf_rts_batched(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0,
+                                         yy, w.offsets, per_sequence=w.per_sequence)
+        return oracle.kf_rts(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, yy)
+
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        ref = ref_for(prec)
+        errs[prec] = {k: wl.max_rel_err(results[prec]["out"][k], ref[k]) for k in ("m", "P", "ms", "Ps")}
+
+    # roofline of the dominant kernel (FP64 headline)
+    def roofline(prec):
+        rs = 8 if prec == "fp64" else 4
+        model = kernel_model(nx, ny, rs)
+        prof = results[prec]["prof"]
+        per_launch = {k: tot / max(1, n) for k, (tot, n) in prof.items()}
+        dom = max(per_launch, key=per_launch.get)
+        dur_s = per_launch[dom] * 1e-3
+        km = model.get(dom)
+        if km is None:
+            return dom, per_launch, None
+        t_mem = km["bytes"] * T / (HBM_PEAK_GBS * 1e9)
+        peak_f = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+        t_alu = km["flops"] * T / (peak_f * 1e12)
+        tr = measured_traffic(w.name, prec, dom)
+        if t_mem >= t_alu:
+            ach = km["bytes"] * T / dur_s / 1e9
+            rl = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(ach / HBM_PEAK_GBS, 4), traffic=tr)
+        else:
+            ach = km["flops"] * T / dur_s / 1e12
+            rl = dict(bound="alu", achieved=round(ach, 3), peak=peak_f, unit="TFLOP/s",
+                      frac=round(ach / peak_f, 4), traffic=tr)
+        rl.update(kernel=dom, kernel_ms=round(per_launch[dom], 4),
+                  algorithmic_bytes_per_launch=km["bytes"] * T, algorithmic_flops_per_launch=km["flops"] * T)
+        return dom, per_launch, rl
+
+    dom64, kern64, rl64 = roofline("fp64")
+    domm, kernm, rlm = roofline("mixed")
+
+    # CPU baseline: the oracle as it stands, one host thread, on the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        if batched:
+            # a bounded sample of sequences, run one after another on one thread
+            idx = list(range(0, w.B, max(1, w.B // 64)))
+            steps_s = sum(int(w.offsets[b + 1] - w.offsets[b]) for b in idx)
+            t0 = time.perf_counter()
+            for b in idx:
+                mo = w.model_of(b)
+                s = w.seq(b)
+                oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y[s])
+            dt = time.perf_counter() - t0
+            cpu = dict(value=steps_s / dt, unit="smoothed time steps/s", cores=1, kind="oracle",
+                       sample="%d of %d sequences (%d steps), sequential C FP64 KF+RTS, 1 thread"
+                       % (len(idx), w.B, steps_s))
+        else:
+            times = []
+            t_start = time.perf_counter()
+            while True:
+                t0 = time.perf_counter()
+                oracle.kf_rts(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, w.y)
+                times.append(time.perf_counter() - t0)
+                if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 50:
+                    break
+            med = statistics.median(times)
+            cpu = dict(value=T / med, unit="smoothed time steps/s", cores=1, kind="oracle",
+                       sample="full workload (T=%d), %d runs, median; sequential C FP64 KF+RTS, 1 thread"
+                       % (T, len(times)))
+
+    sec64 = results["fp64"]["sec"]
+    secm = results["mixed"]["sec"]
+    line = {
+        "metric": "smoothed time steps/sec (filter+smoother) vs FP64 scan; max rel err vs oracle",
+        "value": T / sec64,
+        "unit": "smoothed time steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded simulation of the model)",
+        "config": {"workload": w.name, "T": T, "B": w.B, "nx": nx, "ny": ny,
+                   "path": "plan (hipGraph)" if batched else "pks_filter_smooth"},
+        "max_rel_err": {k: float("%.3e" % v) for k, v in errs["fp64"].items()},
+        "roofline": rl64,
+        "kernels_ms": {k: round(v, 4) for k, v in kern64.items()},
+        "mixed": {
+            "value": T / secm, "ms_per_step": secm * 1e3, "dtype": "f32 storage/products, f64 solves",
+            "speedup_vs_fp64": sec64 / secm,
+            "max_rel_err": {k: float("%.3e" % v) for k, v in errs["mixed"].items()},
+            "roofline": rlm,
+            "kernels_ms": {k: round(v, 4) for k, v in kernm.items()},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * pks.h -- temporally parallel Kalman filter and Rauch-Tung-Striebel smoother
+ *          for AMD MI355X (gfx950).  C ABI of libpks.so.
+ *
+ * Method: Sarkka & Garcia-Fernandez, "Temporal Parallelization of Bayesian
+ * Smoothers".  The filter turns every time step into an element
+ * (A_k, b_k, C_k, eta_k, J_k) (Lemma 1) and combines them with the
+ * associative operator of Lemma 2 in a forward all-prefix-sums scan
+ * (Definition of all-prefix-sums, Theorem 1): the prefix a_1 (x) ... (x) a_k
+ * carries the filtering density N(x_k; m_k, P_k).  The smoother turns every
+ * step into (E_k, g_k, L_k) (Lemma 3), combined with the operator of Lemma 4
+ * in a reverse (suffix) scan (Theorem 2): a_k (x) ... (x) a_n carries the
+ * smoothing density N(x_k; ms_k, Ps_k).
+ *
+ * Model (Section IV, time-invariant case):
+ *     x_0 ~ N(m0, P0),
+ *     x_k = F x_{k-1} + u + q_{k-1},  q ~ N(0, Q),
+ *     y_k = H x_k + d + r_k,          r ~ N(0, R).
+ * The first measurement is y_1; the prior sits on x_0 (Lemma 1, k = 1).
+ *
+ * Conventions for every entry point
+ *  - Pointers marked "device" address GPU memory the caller owns (allocated
+ *    with hipMalloc or by a framework); "host" pointers address CPU memory.
+ *  - Arrays are C-contiguous, row-major.  Row k-1 holds time step k:
+ *    y [T][ny], m/ms [T][nx], P/Ps [T][nx][nx] (full symmetric matrices).
+ *  - Element type of y and of every output: double for PKS_FP64, float for
+ *    PKS_MIXED_FP32.  Model matrices are always double.
+ *  - Calls are stream-ordered and asynchronous: they validate their
+ *    arguments on the host, enqueue kernels on `stream` (a hipStream_t;
+ *    NULL = the default stream) and return.  They allocate no device memory:
+ *    all scratch lives in the caller's workspace `ws` of `ws_bytes` bytes,
+ *    sized with pks_workspace_bytes().  Two calls that run concurrently need
+ *    distinct workspaces.
+ *  - Errors: invalid arguments return PKS_E_ARG / PKS_E_UNSUPPORTED /
+ *    PKS_E_WORKSPACE and enqueue nothing; a failed HIP launch returns
+ *    PKS_E_HIP.  pks_last_error() describes the last failure of the calling
+ *    thread.  Numerical failures found on the device (a Cholesky factor of
+ *    H Q H^T + R, of H P^-_1 H^T + R, or of F P_k F^T + Q that does not
+ *    exist) do not fail the call: they set a flag in `ws` that
+ *    pks_read_numeric_status() reports, and the outputs of the affected
+ *    sequence are NaN.  NaN or Inf in y propagate into the outputs.
+ *  - No exception crosses this interface; the library keeps no state
+ *    between calls except a plan (pks_plan_*) and the tuning cache.
+ */
+#ifndef PKS_H
+#define PKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PKS_OK = 0,
+    PKS_E_ARG = 1,          /* null pointer, bad size, aliasing, bad enum   */
+    PKS_E_UNSUPPORTED = 2,  /* valid request this library does not handle   */
+    PKS_E_WORKSPACE = 3,    /* ws_bytes smaller than pks_workspace_bytes()   */
+    PKS_E_HIP = 4,          /* a HIP runtime call or kernel launch failed    */
+    PKS_E_NUMERIC = 5       /* reported by pks_read_numeric_status only      */
+} pks_status;
+
+typedef enum {
+    PKS_FP64 = 0,        /* all arithmetic, inputs and outputs in double              */
+    PKS_MIXED_FP32 = 1   /* float storage and products; the (I + C_i J_j) solves of
+                            Lemma 2, the Cholesky solves of Lemmas 1 and 3 and the
+                            covariance symmetrisation run in double                  */
+} pks_precision;
+
+/*
+ * Time-invariant linear/Gaussian model (Section IV).  All matrix pointers
+ * are DEVICE pointers to double arrays:
+ *   F [nx][nx], Q [nx][nx] symmetric PSD (Q = 0 allowed),
+ *   H [ny][nx], R [ny][ny] symmetric positive definite,
+ *   m0 [nx], P0 [nx][nx] symmetric PSD (prior on x_0),
+ *   u [nx] and d [ny] may be NULL (zero).
+ * per_sequence = 1 (batched calls only): every array holds B models stacked
+ * along a leading axis (model b at offset b * size); 0: one shared model.
+ * 1 <= nx <= 64 and 1 <= ny <= 64.
+ */
+typedef struct {
+    int32_t nx, ny;
+    const double *F, *u, *Q;
+    const double *H, *d, *R;
+    const double *m0, *P0;
+    int32_t per_sequence;
+} pks_model;
+
+/*
+ * Bytes of device workspace needed by any call on problems with these
+ * sizes (an upper bound over every tile configuration the library or the
+ * autotuner may pick).  total_steps = T for single-sequence calls, the sum
+ * of lengths for batched calls; B = number of sequences (1 for single).
+ * Returns 0 for invalid sizes.  Host-only; touches no device.
+ */
+size_t pks_workspace_bytes(int32_t nx, int32_t ny, int64_t total_steps, int32_t B,
+                           pks_precision prec);
+
+/*
+ * Parallel Kalman filter (Lemmas 1-2, Theorem 1): writes the filtered means
+ * m [T][nx] and covariances P [T][nx][nx] of a single sequence y [T][ny].
+ * y, m, P, ws: device.  T = 0 is a no-op.  m and P must not overlap y or
+ * each other.
+ */
+pks_status pks_filter(const pks_model *model, int64_t T, const void *y, void *m, void *P,
+                      pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Parallel RTS smoother (Lemmas 3-4, Theorem 2): from filtered moments
+ * m [T][nx], P [T][nx][nx] (the output of pks_filter, symmetric P) writes the
+ * smoothed moments ms [T][nx], Ps [T][nx][nx].  Uses F, u, Q of the model.
+ * All arrays and ws: device.  Outputs must not overlap the inputs.
+ */
+pks_status pks_smooth(const pks_model *model, int64_t T, const void *m, const void *P,
+                      void *ms, void *Ps, pks_precision prec, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* pks_filter followed by pks_smooth on the same stream, in one call. */
+pks_status pks_filter_smooth(const pks_model *model, int64_t T, const void *y, void *m, void *P,
+                             void *ms, void *Ps, pks_precision prec, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/*
+ * Batched forms: B independent sequences packed back to back.  offsets is a
+ * DEVICE int64 array [B+1] with offsets[0] = 0, non-decreasing, offsets[B] =
+ * total; sequence b occupies rows offsets[b] .. offsets[b+1]-1 of y/m/P/ms/Ps.
+ * Zero-length sequences are allowed.  With model->per_sequence = 1 sequence b
+ * uses model b.  The k = 1 element of Lemma 1 and the k = n element of
+ * Lemma 3 are applied at every sequence start and end, which separates the
+ * sequences inside one scan.  Offsets that break the rules above give
+ * undefined (but memory-safe) results.
+ */
+pks_status pks_filter_batched(const pks_model *model, int32_t B, const int64_t *offsets,
+                              int64_t total, const void *y, void *m, void *P,
+                              pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+pks_status pks_smooth_batched(const pks_model *model, int32_t B, const int64_t *offsets,
+                              int64_t total, const void *m, const void *P, void *ms, void *Ps,
+                              pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Plans: the whole filter + smoother of a (batched) problem, with its tile
+ * configuration taken from the tuning cache, captured once into a HIP graph
+ * bound to these pointers; pks_plan_launch replays it with one
+ * hipGraphLaunch.  `tune_cache` names the JSON cache file (NULL: environment
+ * variable PKS_TUNE_CACHE, else built-in defaults).  B = 1 with offsets =
+ * NULL plans a single sequence of `total` steps.  *plan receives an opaque
+ * handle owned by the caller, released with pks_plan_destroy.
+ */
+pks_status pks_plan_create(const pks_model *model, int32_t B, const int64_t *offsets,
+                           int64_t total, const void *y, void *m, void *P, void *ms, void *Ps,
+                           pks_precision prec, void *ws, size_t ws_bytes,
+                           const char *tune_cache, void *stream, void **plan);
+pks_status pks_plan_launch(void *plan, void *stream);
+pks_status pks_plan_destroy(void *plan);
+
+/*
+ * Autotuner: times the available tile configurations (elements per thread,
+ * scan levels) for problems of this shape on the current device with HIP
+ * events, using synthetic data in the caller's workspace plus a temporary
+ * allocation it frees before returning, and stores the fastest in the JSON
+ * cache `cache_path` (NULL: PKS_TUNE_CACHE).  Synchronises `stream`.
+ */
+pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_precision prec,
+                        const char *cache_path, void *stream);
+
+/*
+ * Synchronises `stream` and reads the numeric flag of `ws`: PKS_OK, or
+ * PKS_E_NUMERIC with *first_bad_sequence (host pointer, may be NULL) set to
+ * the smallest sequence index whose Cholesky factorisation failed.  Clears
+ * the flag.
+ */
+pks_status pks_read_numeric_status(void *ws, int32_t *first_bad_sequence, void *stream);
+
+/*
+ * Diagnostics: per-kernel timing.  After pks_profile_start(), every call made
+ * by this thread brackets each kernel it launches with HIP events recorded on
+ * the launch stream.  pks_profile_stop() synchronises the device, stops the
+ * recording and reports up to max_kernels distinct kernel names in first-
+ * launch order: names (host buffer of max_kernels * 64 chars, NUL-terminated
+ * entries), total_ms (host, summed event-to-event milliseconds), launches
+ * (host, launch counts) and *n_kernels (host).  Any output pointer may be NULL.
+ */
+pks_status pks_profile_start(void);
+pks_status pks_profile_stop(int32_t max_kernels, char *names, float *total_ms, int32_t *launches,
+                            int32_t *n_kernels);
+
+/* Description of the calling thread's last failure ("" if none). */
+const char *pks_last_error(void);
+
+/* Library version string. */
+const char *pks_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PKS_H */

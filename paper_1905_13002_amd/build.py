@@ -1,0 +1,65 @@
+"""Build libpks.so (HIP for gfx950) in-tree.
+
+    python -m paper_1905_13002_amd.build
+
+Every translation unit is compiled with hipcc for gfx950 only, with packed
+FP32 instructions disabled (``-Xclang -target-feature -Xclang
+-packed-fp32-ops``), then linked into ``paper_1905_13002_amd/libpks.so``.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libpks.so")
+BUILD = os.path.join(os.path.dirname(HERE), "_build")
+
+SOURCES = (["api.cpp", "plan.cpp", "precompute.hip", "scan_small.hip", "scan_large.hip"]
+           + ["scan_small_n%d_%s.hip" % (n, t) for n in (4, 3, 2, 1) for t in ("f64", "f32")])
+
+ARCH = os.environ.get("PKS_OFFLOAD_ARCH", "gfx950")
+HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas",
+          "-Wno-unused-result", "-Wno-unused-value", "-I" + os.path.join(os.path.dirname(HERE), "include")]
+
+
+def _compile(src: str, extra) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC] + COMMON + list(extra) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stdout))
+    msgs = [l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+    if msgs:
+        sys.stderr.write("\n".join(msgs[-40:]) + "\n")
+    return obj
+
+
+def build(extra=(), jobs=None, verbose=True) -> str:
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 2)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, extra), srcs))
+    tmp = OUT + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stdout))
+    os.replace(tmp, OUT)
+    if verbose:
+        print("built", OUT, file=sys.stderr)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(extra=sys.argv[1:])

@@ -1,0 +1,384 @@
+// api.cpp -- the C ABI of libpks.so (declared in include/pks.h): argument
+// validation, workspace layout, tile configuration and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pks_internal.h"
+#include "plan.h"
+
+namespace pks {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pks_status fail(pks_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+pks_status hip_fail(hipError_t e, const char* what) {
+    return fail(PKS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+constexpr int kMinEpt = 4;          // smallest elements-per-thread any configuration uses
+constexpr int kMaxDim = 64;
+
+int felem_words(int nx) { return nx * nx + nx + nx * (nx + 1) / 2 + nx + nx * (nx + 1) / 2; }
+int moment_words(int nx) { return nx + nx * (nx + 1) / 2; }
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+pks_status check_model(const pks_model* model) {
+    if (!model) return fail(PKS_E_ARG, "model is NULL");
+    if (model->nx < 1 || model->nx > kMaxDim) return fail(PKS_E_ARG, "nx = %d outside [1, 64]", model->nx);
+    if (model->ny < 1 || model->ny > kMaxDim) return fail(PKS_E_ARG, "ny = %d outside [1, 64]", model->ny);
+    if (!model->F || !model->Q || !model->H || !model->R || !model->m0 || !model->P0)
+        return fail(PKS_E_ARG, "model matrix pointer is NULL (F, Q, H, R, m0 and P0 are required)");
+    return PKS_OK;
+}
+
+pks_status check_prec(pks_precision prec) {
+    if (prec != PKS_FP64 && prec != PKS_MIXED_FP32) return fail(PKS_E_ARG, "unknown precision %d", (int)prec);
+    return PKS_OK;
+}
+
+size_t rsize(pks_precision prec) { return prec == PKS_FP64 ? sizeof(double) : sizeof(float); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision prec) {
+    WsLayout L{};
+    const size_t rs = rsize(prec);
+    const ConstLayout CL = const_layout(nx, ny);
+    size_t o = 0;
+    L.status = o; o += 256;
+    L.consts64 = o; o = align256(o + sizeof(double) * (size_t)CL.words * nmodels);
+    L.consts32 = o; o = align256(o + sizeof(float) * (size_t)CL.words * nmodels);
+    L.scratch = o; o = align256(o + sizeof(double) * (size_t)precompute_scratch_words(nx, ny) * nmodels);
+    L.model_fail = o; o = align256(o + sizeof(int32_t) * (size_t)nmodels);
+    // small-state scan: level 0 over steps, level 1 over level-0 wave aggregates
+    const int64_t waves0 = round_up(std::max<int64_t>(1, ceil_div(total, 64 * kMinEpt)), 4);
+    const int64_t thr0 = waves0 * 64;
+    const int64_t waves1 = round_up(std::max<int64_t>(1, ceil_div(waves0, 64)), 4);   // >= 1 item per thread
+    const int64_t thr1 = waves1 * 64;
+    const int fw = felem_words(nx), mw = moment_words(nx);
+    L.cap_thr = thr0;
+    L.cap_waves = waves0;
+    L.cap_thr1 = thr1;
+    L.cap_waves1 = waves1;
+    L.thr = o; o = align256(o + rs * fw * (size_t)thr0);
+    L.agg = o; o = align256(o + rs * fw * (size_t)waves0);
+    L.carry = o; o = align256(o + rs * mw * (size_t)waves0);
+    L.thr1 = o; o = align256(o + rs * fw * (size_t)thr1);
+    L.agg1 = o; o = align256(o + rs * fw * (size_t)waves1);
+    L.carry1 = o; o = align256(o + rs * mw * (size_t)waves1);
+    L.large = o;
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// scan argument assembly
+// ---------------------------------------------------------------------------
+ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
+                        pks_precision prec, void* ws, const WsLayout& L, TileConfig cfg) {
+    ScanArgs a{};
+    char* base = static_cast<char*>(ws);
+    const ConstLayout CL = const_layout(model.nx, model.ny);
+    a.nx = model.nx;
+    a.ny = model.ny;
+    a.total = total;
+    a.B = B;
+    a.offsets = offsets;
+    a.model_stride = model.per_sequence ? CL.words : 0;
+    a.consts = prec == PKS_FP64 ? (const void*)(base + L.consts64) : (const void*)(base + L.consts32);
+    a.thr = base + L.thr;
+    a.agg = base + L.agg;
+    a.carry = base + L.carry;
+    a.ept = cfg.ept;
+    a.nwaves = round_up(std::max<int64_t>(1, ceil_div(total, 64 * cfg.ept)), 4);
+    a.nthr = a.nwaves * 64;
+    a.ept1 = cfg.ept1;
+    if (cfg.ept1 > 0) {
+        a.thr1 = base + L.thr1;
+        a.agg1 = base + L.agg1;
+        a.carry1 = base + L.carry1;
+        a.nwaves1 = round_up(std::max<int64_t>(1, ceil_div(a.nwaves, 64 * cfg.ept1)), 4);
+        a.nthr1 = a.nwaves1 * 64;
+    }
+    a.status = reinterpret_cast<int*>(base + L.status);
+    a.model_fail = reinterpret_cast<const int*>(base + L.model_fail);
+    a.nmodels = model.per_sequence ? B : 1;
+    return a;
+}
+
+// Enqueue the requested passes.  passes: 1 = filter, 2 = smoother, 3 = both.
+pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
+                   const void* y, void* m, void* P, void* ms, void* Ps, pks_precision prec,
+                   void* ws, size_t ws_bytes, int passes, const TileConfig* forced, hipStream_t s) {
+    const int nmodels = model.per_sequence ? B : 1;
+    const WsLayout L = ws_layout(model.nx, model.ny, total, B, prec);
+    if (ws_bytes < L.total)
+        return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    ws_bytes, L.total);
+    if (!small_supported(model.nx))
+        return fail(PKS_E_UNSUPPORTED, "nx = %d is not supported by this build", model.nx);
+    if (total == 0) return PKS_OK;
+    const bool mixed = prec == PKS_MIXED_FP32;
+    TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
+    if (cfg.ept < kMinEpt) cfg.ept = kMinEpt;
+    hipError_t e = launch_precompute(model.nx, model.ny, nmodels, model, ws, L, mixed, passes,
+                                     (passes & 1) != 0, s);
+    if (e != hipSuccess) return hip_fail(e, "precompute kernel");
+    ScanArgs a = make_scan_args(model, B, offsets, total, prec, ws, L, cfg);
+    a.y = y;
+    a.m = m;
+    a.P = P;
+    a.ms = ms;
+    a.Ps = Ps;
+    if (a.nthr > L.cap_thr || a.nwaves > L.cap_waves || a.nthr1 > L.cap_thr1 || a.nwaves1 > L.cap_waves1)
+        return fail(PKS_E_ARG, "tile configuration (ept %d, ept1 %d) does not fit the workspace", cfg.ept, cfg.ept1);
+    if (passes & 1) {
+        e = launch_small_filter(a, mixed, s);
+        if (e != hipSuccess) return hip_fail(e, "filter kernels");
+    }
+    if (passes & 2) {
+        e = launch_small_smoother(a, mixed, s);
+        if (e != hipSuccess) return hip_fail(e, "smoother kernels");
+    }
+    return PKS_OK;
+}
+
+pks_status validate_io(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
+                       const void* y, const void* m, const void* P, const void* ms, const void* Ps,
+                       pks_precision prec, void* ws, int passes, bool batched) {
+    pks_status st = check_model(model);
+    if (st) return st;
+    st = check_prec(prec);
+    if (st) return st;
+    if (total < 0) return fail(PKS_E_ARG, "negative number of steps");
+    if (batched) {
+        if (B < 1) return fail(PKS_E_ARG, "B = %d must be >= 1", B);
+        if (!offsets) return fail(PKS_E_ARG, "offsets is NULL");
+    } else if (model->per_sequence) {
+        return fail(PKS_E_ARG, "per_sequence models need a batched call");
+    }
+    if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
+    if (total == 0) return PKS_OK;
+    const size_t rs = rsize(prec);
+    const size_t ny = model->ny, nx = model->nx, T = (size_t)total;
+    const size_t by = T * ny * rs, bm = T * nx * rs, bP = T * nx * nx * rs;
+    if ((passes & 1) && (!y || !m || !P)) return fail(PKS_E_ARG, "y, m and P must not be NULL");
+    if ((passes & 2) && (!m || !P || !ms || !Ps)) return fail(PKS_E_ARG, "m, P, ms and Ps must not be NULL");
+    if (passes & 1) {
+        if (overlaps(y, by, m, bm) || overlaps(y, by, P, bP) || overlaps(m, bm, P, bP))
+            return fail(PKS_E_ARG, "filter outputs overlap the input or each other");
+    }
+    if (passes & 2) {
+        if (overlaps(ms, bm, Ps, bP) || overlaps(ms, bm, m, bm) || overlaps(ms, bm, P, bP) ||
+            overlaps(Ps, bP, m, bm) || overlaps(Ps, bP, P, bP))
+            return fail(PKS_E_ARG, "smoother outputs overlap the inputs or each other");
+        if (passes & 1) {
+            if (overlaps(y, by, ms, bm) || overlaps(y, by, Ps, bP))
+                return fail(PKS_E_ARG, "smoother outputs overlap y");
+        }
+    }
+    return PKS_OK;
+}
+
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfMark {
+    std::string name;
+    hipEvent_t start, stop;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfMark> marks;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+thread_local Profiler g_prof;
+}  // namespace
+
+void prof_begin(const char* kernel, hipStream_t s) {
+    if (!g_prof.on) return;
+    ProfMark m;
+    m.name = kernel;
+    m.start = g_prof.get();
+    m.stop = g_prof.get();
+    if (m.start) (void)hipEventRecord(m.start, s);
+    g_prof.marks.push_back(m);
+}
+
+void prof_end(hipStream_t s) {
+    if (!g_prof.on || g_prof.marks.empty()) return;
+    if (g_prof.marks.back().stop) (void)hipEventRecord(g_prof.marks.back().stop, s);
+}
+
+}  // namespace pks
+
+using namespace pks;
+
+extern "C" {
+
+size_t pks_workspace_bytes(int32_t nx, int32_t ny, int64_t total_steps, int32_t B, pks_precision prec) {
+    if (nx < 1 || nx > 64 || ny < 1 || ny > 64 || total_steps < 0 || B < 1) return 0;
+    if (prec != PKS_FP64 && prec != PKS_MIXED_FP32) return 0;
+    return ws_layout(nx, ny, total_steps, B, prec).total;
+}
+
+pks_status pks_filter(const pks_model* model, int64_t T, const void* y, void* m, void* P,
+                      pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_status st = validate_io(model, 1, nullptr, T, y, m, P, nullptr, nullptr, prec, ws, 1, false);
+    if (st) return st;
+    return enqueue(*model, 1, nullptr, T, y, m, P, nullptr, nullptr, prec, ws, ws_bytes, 1, nullptr,
+                   (hipStream_t)stream);
+}
+
+pks_status pks_smooth(const pks_model* model, int64_t T, const void* m, const void* P, void* ms, void* Ps,
+                      pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_status st = validate_io(model, 1, nullptr, T, nullptr, m, P, ms, Ps, prec, ws, 2, false);
+    if (st) return st;
+    return enqueue(*model, 1, nullptr, T, nullptr, const_cast<void*>(m), const_cast<void*>(P), ms, Ps, prec, ws,
+                   ws_bytes, 2, nullptr, (hipStream_t)stream);
+}
+
+pks_status pks_filter_smooth(const pks_model* model, int64_t T, const void* y, void* m, void* P, void* ms,
+                             void* Ps, pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_status st = validate_io(model, 1, nullptr, T, y, m, P, ms, Ps, prec, ws, 3, false);
+    if (st) return st;
+    return enqueue(*model, 1, nullptr, T, y, m, P, ms, Ps, prec, ws, ws_bytes, 3, nullptr, (hipStream_t)stream);
+}
+
+pks_status pks_filter_batched(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
+                              const void* y, void* m, void* P, pks_precision prec, void* ws, size_t ws_bytes,
+                              void* stream) {
+    g_last_error.clear();
+    pks_status st = validate_io(model, B, offsets, total, y, m, P, nullptr, nullptr, prec, ws, 1, true);
+    if (st) return st;
+    return enqueue(*model, B, offsets, total, y, m, P, nullptr, nullptr, prec, ws, ws_bytes, 1, nullptr,
+                   (hipStream_t)stream);
+}
+
+pks_status pks_smooth_batched(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
+                              const void* m, const void* P, void* ms, void* Ps, pks_precision prec, void* ws,
+                              size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_status st = validate_io(model, B, offsets, total, nullptr, m, P, ms, Ps, prec, ws, 2, true);
+    if (st) return st;
+    return enqueue(*model, B, offsets, total, nullptr, const_cast<void*>(m), const_cast<void*>(P), ms, Ps, prec,
+                   ws, ws_bytes, 2, nullptr, (hipStream_t)stream);
+}
+
+pks_status pks_read_numeric_status(void* ws, int32_t* first_bad_sequence, void* stream) {
+    g_last_error.clear();
+    if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int host[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(host, ws, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading the numeric flag");
+    const bool prepared = host[1] == kStatusMagic;
+    const int bad = prepared ? host[0] : kStatusOk;
+    const int clean[2] = {kStatusOk, kStatusMagic};
+    e = hipMemcpyAsync(ws, clean, sizeof clean, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "clearing the numeric flag");
+    if (bad != kStatusOk) {
+        if (first_bad_sequence) *first_bad_sequence = bad;
+        return fail(PKS_E_NUMERIC, "a Cholesky factorisation failed in sequence %d", bad);
+    }
+    if (first_bad_sequence) *first_bad_sequence = -1;
+    return PKS_OK;
+}
+
+pks_status pks_profile_start(void) {
+    g_last_error.clear();
+    g_prof.on = true;
+    return PKS_OK;
+}
+
+pks_status pks_profile_stop(int32_t max_kernels, char* names, float* total_ms, int32_t* launches,
+                            int32_t* n_kernels) {
+    g_last_error.clear();
+    g_prof.on = false;
+    hipError_t e = hipDeviceSynchronize();
+    std::vector<std::string> order;
+    std::vector<double> tot;
+    std::vector<int> cnt;
+    for (auto& m : g_prof.marks) {
+        float ms = 0.f;
+        if (e == hipSuccess && m.start && m.stop) e = hipEventElapsedTime(&ms, m.start, m.stop);
+        size_t i = 0;
+        while (i < order.size() && order[i] != m.name) ++i;
+        if (i == order.size()) {
+            order.push_back(m.name);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[i] += ms;
+        cnt[i] += 1;
+        if (m.start) g_prof.pool.push_back(m.start);
+        if (m.stop) g_prof.pool.push_back(m.stop);
+    }
+    g_prof.marks.clear();
+    if (e != hipSuccess) return hip_fail(e, "kernel timing");
+    const int n = (int)std::min<size_t>(order.size(), max_kernels > 0 ? (size_t)max_kernels : 0);
+    for (int i = 0; i < n; ++i) {
+        if (names) {
+            strncpy(names + 64 * i, order[i].c_str(), 63);
+            names[64 * i + 63] = 0;
+        }
+        if (total_ms) total_ms[i] = (float)tot[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    if (n_kernels) *n_kernels = n;
+    return PKS_OK;
+}
+
+const char* pks_last_error(void) { return g_last_error.c_str(); }
+
+const char* pks_version(void) { return "pks 0.1 (gfx950)"; }
+
+}  // extern "C"

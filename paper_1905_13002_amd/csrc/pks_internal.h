@@ -1,0 +1,129 @@
+// pks_internal.h -- shared between the C-ABI layer and the kernel translation
+// units: per-model constant layout, workspace layout and launch arguments.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pks.h"
+
+namespace pks {
+
+// ---------------------------------------------------------------------------
+// Per-model constants written by the model-precompute kernel (Lemma 1 for a
+// time-invariant model: A, C, J are the same for every k > 1 and b_k, eta_k
+// are affine in y_k; the k = 1 element has its own K_1, C_1), followed by
+// copies of F, Q, u for the smoothing elements (Lemma 3).
+//   b_k   = c  + K  y_k,   c  = u - K (H u + d)
+//   eta_k = w  + W  y_k,   w  = -W (H u + d),    W = F^T H^T S^-1
+//   b_1   = c1 + K1 y_1,   c1 = m1 - K1 (H m1 + d), m1 = F m0 + u
+// All matrices row-major, full (not packed).
+// ---------------------------------------------------------------------------
+struct ConstLayout {
+    int A, C, J, K, W, c, w, K1, c1, C1, F, Q, u, words;
+};
+__host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
+    ConstLayout L;
+    int o = 0;
+    const int n2 = nx * nx, nm = nx * ny;
+    L.A = o; o += n2;
+    L.C = o; o += n2;
+    L.J = o; o += n2;
+    L.K = o; o += nm;
+    L.W = o; o += nm;
+    L.c = o; o += nx;
+    L.w = o; o += nx;
+    L.K1 = o; o += nm;
+    L.c1 = o; o += nx;
+    L.C1 = o; o += n2;
+    L.F = o; o += n2;
+    L.Q = o; o += n2;
+    L.u = o; o += nx;
+    L.words = (o + 15) & ~15;
+    return L;
+}
+
+// scratch words per model used by the precompute kernel (double)
+__host__ __device__ inline int precompute_scratch_words(int nx, int ny) {
+    const int n2 = nx * nx, nm = nx * ny, m2 = ny * ny;
+    return (6 * n2 + 8 * nm + 4 * m2 + 4 * nx + 4 * ny + 15) & ~15;
+}
+
+constexpr int kStatusOk = 0x7fffffff;     // "no failure" value of the numeric flag
+constexpr int kStatusMagic = 0x504b5331;  // marks a prepared status word
+
+// ---------------------------------------------------------------------------
+// Workspace layout (byte offsets from ws), computed on the host.
+// ---------------------------------------------------------------------------
+struct WsLayout {
+    size_t status;        // int32 first failing sequence (kStatusOk = none)
+    size_t consts64;      // [nmodels][CW] double
+    size_t consts32;      // [nmodels][CW] float
+    size_t scratch;       // [nmodels][SW] double (precompute temporaries)
+    size_t model_fail;    // [nmodels] int32
+    size_t thr;           // per-thread exclusive prefixes, SoA (level 0)
+    size_t agg;           // per-wave aggregates, SoA (level 0)
+    size_t carry;         // per-wave incoming moments, SoA (level 0)
+    size_t thr1, agg1, carry1;  // same for level 1 (scan over level-0 aggregates)
+    size_t large;         // large-state path scratch
+    size_t total;
+    // sizes used for capacity checks
+    int64_t cap_thr, cap_waves, cap_thr1, cap_waves1;
+};
+
+WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision prec);
+
+// ---------------------------------------------------------------------------
+// Launch arguments of the small-state scan kernels.
+// ---------------------------------------------------------------------------
+struct ScanArgs {
+    int nx, ny;
+    int64_t total;               // steps (sum over sequences)
+    int32_t B;                   // sequences
+    const int64_t* offsets;      // device [B+1]; nullptr = one sequence [0, total)
+    int64_t model_stride;        // R words between models in consts (0 = shared)
+    const void* consts;          // R-typed constants of model 0
+    const void* y;               // filter input  [total][ny]
+    void* m;                     // filter output [total][nx]  / smoother input
+    void* P;                     // filter output [total][nx][nx] / smoother input
+    void* ms;                    // smoother output
+    void* Ps;
+    // level-0 scan state
+    void* thr;                   // SoA [words][nthr]
+    void* agg;                   // SoA [words][nwaves]
+    void* carry;                 // SoA [mwords][nwaves]
+    int64_t nthr, nwaves;        // padded counts (SoA strides)
+    // level-1 scan state (nwaves1 == 0: single level)
+    void* thr1;
+    void* agg1;
+    void* carry1;
+    int64_t nthr1, nwaves1;
+    int ept, ept1;               // elements per thread at level 0 / 1
+    int* status;
+    const int* model_fail;       // [nmodels] 1 = the model's precompute failed
+    int nmodels;
+};
+
+// Tile configuration chosen for a launch.
+struct TileConfig {
+    int ept;      // elements per thread, level 0 (4, 8, 16)
+    int ept1;     // elements per thread, level 1 (aggregates); 0 = no level 1
+};
+
+// Per-kernel timing (diagnostics).  While enabled on the calling thread,
+// launchers bracket each kernel with prof_begin/prof_end, which record HIP
+// events on the launch stream; both are no-ops otherwise.
+void prof_begin(const char* kernel, hipStream_t s);
+void prof_end(hipStream_t s);
+
+// launchers (scan_small.hip)
+bool small_supported(int nx);
+// Model precompute (one workgroup per model); also prepares the numeric flag
+// (cleared when `reset`, or when the workspace was never prepared).
+hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model,
+                             void* ws, const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s);
+hipError_t launch_small_filter(ScanArgs a, bool mixed, hipStream_t s);
+hipError_t launch_small_smoother(ScanArgs a, bool mixed, hipStream_t s);
+TileConfig small_default_config(int nx, int64_t total, bool mixed);
+
+}  // namespace pks

@@ -1,0 +1,44 @@
+// scan_small.hip -- dispatch of the small-state (nx <= 4) scans to the
+// per-dimension, per-precision kernel instantiations.
+#include "pks_internal.h"
+
+namespace pks {
+
+template <int N, typename R>
+hipError_t small_run(ScanArgs a, bool smoother, hipStream_t s);
+
+namespace {
+
+template <typename R>
+hipError_t dispatch_n(ScanArgs a, bool smoother, hipStream_t s) {
+    switch (a.nx) {
+        case 1: return small_run<1, R>(a, smoother, s);
+        case 2: return small_run<2, R>(a, smoother, s);
+        case 3: return small_run<3, R>(a, smoother, s);
+        case 4: return small_run<4, R>(a, smoother, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool small_supported(int nx) { return nx >= 1 && nx <= 4; }
+
+TileConfig small_default_config(int nx, int64_t total, bool mixed) {
+    (void)nx;
+    (void)mixed;
+    TileConfig c;
+    c.ept = 8;
+    const int64_t waves = (total + 64 * c.ept - 1) / (64 * c.ept);
+    c.ept1 = waves > 4096 ? 8 : 0;
+    return c;
+}
+
+hipError_t launch_small_filter(ScanArgs a, bool mixed, hipStream_t s) {
+    return mixed ? dispatch_n<float>(a, false, s) : dispatch_n<double>(a, false, s);
+}
+hipError_t launch_small_smoother(ScanArgs a, bool mixed, hipStream_t s) {
+    return mixed ? dispatch_n<float>(a, true, s) : dispatch_n<double>(a, true, s);
+}
+
+}  // namespace pks

@@ -1,0 +1,705 @@
+// scan_small_impl.hpp -- the filtering and smoothing scans for nx <= 4, one scan
+// element per lane, elements in registers.
+//
+// The all-prefix-sums of the filtering elements (Theorem 1) and the suffix
+// products of the smoothing elements (Theorem 2) are computed as a
+// reduce-then-scan over block-level elements (the paper's blocks of length l,
+// Section III-C):
+//   reduce : thread t folds its EPT consecutive elements sequentially into one
+//            block element; the 64 block elements of a wave are scanned with a
+//            Kogge-Stone pattern over cross-lane shuffles (six combines); each
+//            thread stores its in-wave exclusive prefix and lane 63 the wave
+//            aggregate (struct-of-arrays in the workspace).
+//   top    : one workgroup scans the wave aggregates (sequential chunk fold,
+//            wave Kogge-Stone, cross-wave through LDS) and stores, per wave,
+//            the moments of everything before it.  Optionally one more level
+//            (the same reduce over the wave aggregates) is inserted when the
+//            number of waves is large.
+//   down   : thread t applies the wave's incoming moments to its exclusive
+//            prefix and then re-folds its EPT elements one by one; every
+//            step of that fold is Lemma 2 (or 4) with a left prefix whose A
+//            is zero (a right suffix whose E is zero), i.e. an exact Kalman
+//            update+prediction (RTS step) in element form, whose moments are
+//            the outputs.
+// Every prefix that starts at a sequence's first step has A = 0 (Lemma 1,
+// A_1 = 0) and every suffix that ends at a sequence's last step has E = 0
+// (Lemma 3, E_n = 0); these exact zeros also separate sequences that are
+// packed back to back, so batched scans need no segment flags.
+#pragma once
+#include "pks_internal.h"
+#include "small_ops.hpp"
+
+namespace pks {
+
+namespace {
+
+constexpr int kBlock = 256;     // threads per workgroup (4 waves)
+
+// ---------------------------------------------------------------------------
+// struct-of-arrays helpers: record word w of item i lives at base[w*stride+i]
+// ---------------------------------------------------------------------------
+template <int W, typename R>
+__device__ __forceinline__ void soa_store_words(R* __restrict__ base, int64_t stride, int64_t i, const R* w) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) base[k * stride + i] = w[k];
+}
+template <int W, typename R>
+__device__ __forceinline__ void soa_load_words(const R* __restrict__ base, int64_t stride, int64_t i, R* w) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) w[k] = base[k * stride + i];
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void store_f(void* base, int64_t stride, int64_t i, const FElem<N, R>& e) {
+    soa_store_words<Words<N>::F>(static_cast<R*>(base), stride, i, reinterpret_cast<const R*>(&e));
+}
+template <int N, typename R>
+__device__ __forceinline__ void load_f(const void* base, int64_t stride, int64_t i, FElem<N, R>& e) {
+    soa_load_words<Words<N>::F>(static_cast<const R*>(base), stride, i, reinterpret_cast<R*>(&e));
+}
+template <int N, typename R>
+__device__ __forceinline__ void store_s(void* base, int64_t stride, int64_t i, const SElem<N, R>& e) {
+    soa_store_words<Words<N>::S>(static_cast<R*>(base), stride, i, reinterpret_cast<const R*>(&e));
+}
+template <int N, typename R>
+__device__ __forceinline__ void load_s(const void* base, int64_t stride, int64_t i, SElem<N, R>& e) {
+    soa_load_words<Words<N>::S>(static_cast<const R*>(base), stride, i, reinterpret_cast<R*>(&e));
+}
+template <int N, typename R>
+__device__ __forceinline__ void store_m(void* base, int64_t stride, int64_t i, const Moments<N, R>& x) {
+    soa_store_words<Words<N>::M>(static_cast<R*>(base), stride, i, reinterpret_cast<const R*>(&x));
+}
+template <int N, typename R>
+__device__ __forceinline__ void load_m(const void* base, int64_t stride, int64_t i, Moments<N, R>& x) {
+    soa_load_words<Words<N>::M>(static_cast<const R*>(base), stride, i, reinterpret_cast<R*>(&x));
+}
+
+// cross-lane moves of whole records
+template <int W, typename R>
+__device__ __forceinline__ void shfl_up_words(R* w, unsigned d) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) w[k] = __shfl_up(w[k], d, 64);
+}
+template <int W, typename R>
+__device__ __forceinline__ void shfl_down_words(R* w, unsigned d) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) w[k] = __shfl_down(w[k], d, 64);
+}
+
+// ---------------------------------------------------------------------------
+// sequences: which packed sequence holds step k
+// ---------------------------------------------------------------------------
+struct Seq {
+    int b;
+    int64_t start, end;   // [start, end)
+};
+
+template <bool SEG>
+__device__ __forceinline__ Seq seq_find(const ScanArgs& a, int64_t k) {
+    Seq s;
+    if (!SEG) {
+        s.b = 0; s.start = 0; s.end = a.total;
+        return s;
+    }
+    int lo = 0, hi = a.B;               // invariant: offsets[lo] <= k (offsets[0] = 0)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.offsets[mid] <= k) lo = mid; else hi = mid;
+    }
+    s.b = lo;
+    s.start = a.offsets[lo];
+    s.end = a.offsets[lo + 1];
+    return s;
+}
+
+template <bool SEG>
+__device__ __forceinline__ void seq_forward(const ScanArgs& a, Seq& s, int64_t k) {
+    if (!SEG) return;
+    while (k >= s.end && s.b < a.B - 1) {
+        ++s.b;
+        s.start = s.end;
+        s.end = a.offsets[s.b + 1];
+    }
+}
+template <bool SEG>
+__device__ __forceinline__ void seq_backward(const ScanArgs& a, Seq& s, int64_t k) {
+    if (!SEG) return;
+    while (k < s.start && s.b > 0) {
+        --s.b;
+        s.end = s.start;
+        s.start = a.offsets[s.b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element sources
+// ---------------------------------------------------------------------------
+// Lemma 1 element of step k (first = first step of its sequence).
+template <int N, typename R>
+__device__ __forceinline__ void build_felem(const R* __restrict__ cst, const ConstLayout& CL, int ny,
+                                            const R* __restrict__ yk, bool first, FElem<N, R>& e) {
+    if (!first) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) e.A[r * N + c] = cst[CL.A + r * N + c];
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                e.C[sidx(r, c)] = cst[CL.C + r * N + c];
+                e.J[sidx(r, c)] = cst[CL.J + r * N + c];
+            }
+            e.b[r] = cst[CL.c + r];
+            e.eta[r] = cst[CL.w + r];
+        }
+        for (int q = 0; q < ny; ++q) {
+            const R yq = yk[q];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                e.b[r] = fma(cst[CL.K + r * ny + q], yq, e.b[r]);
+                e.eta[r] = fma(cst[CL.W + r * ny + q], yq, e.eta[r]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) e.A[r * N + c] = R(0);
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                e.C[sidx(r, c)] = cst[CL.C1 + r * N + c];
+                e.J[sidx(r, c)] = R(0);
+            }
+            e.b[r] = cst[CL.c1 + r];
+            e.eta[r] = R(0);
+        }
+        for (int q = 0; q < ny; ++q) {
+            const R yq = yk[q];
+#pragma unroll
+            for (int r = 0; r < N; ++r) e.b[r] = fma(cst[CL.K1 + r * ny + q], yq, e.b[r]);
+        }
+    }
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void load_moments_step(const R* __restrict__ m, const R* __restrict__ P, int64_t k,
+                                                  Moments<N, R>& x) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) x.m[r] = m[k * N + r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) x.P[sidx(r, c)] = P[k * N * N + r * N + c];
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void store_moments_step(R* __restrict__ m, R* __restrict__ P, int64_t k,
+                                                   const Moments<N, R>& x) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) m[k * N + r] = x.m[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) P[k * N * N + r * N + c] = x.P[sidx(r, c)];
+}
+
+// Lemma 3 element of step k from its filtered moments (last = last step of its sequence)
+template <int N, typename R>
+__device__ __forceinline__ void make_selem(const R* __restrict__ cst, const ConstLayout& CL, const Moments<N, R>& x,
+                                           bool last, SElem<N, R>& e, int* status, int b) {
+    if (last) {
+#pragma unroll
+        for (int i = 0; i < N * N; ++i) e.E[i] = R(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) e.g[i] = x.m[i];
+#pragma unroll
+        for (int i = 0; i < tri(N); ++i) e.L[i] = x.P[i];
+    } else {
+        const bool ok = build_selem<N, R>(cst + CL.F, cst + CL.Q, cst + CL.u, x, e);
+        if (!ok) atomicMin(status, b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wave-level scans (Kogge-Stone over shuffles).  Lanes without a partner take
+// the identity as the shuffled operand, so every lane runs the same combine.
+// ---------------------------------------------------------------------------
+template <int N, typename R, bool G>
+__device__ __forceinline__ void wave_inclusive_f(FElem<N, R>& incl, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        FElem<N, R> o = incl;
+        shfl_up_words<Words<N>::F>(reinterpret_cast<R*>(&o), d);
+        if (lane < d) set_identity(o);
+        fcombine<N, R, G>(o, incl, incl);
+    }
+}
+template <int N, typename R>
+__device__ __forceinline__ void wave_exclusive_from_inclusive_f(const FElem<N, R>& incl, FElem<N, R>& ex, int lane) {
+    ex = incl;
+    shfl_up_words<Words<N>::F>(reinterpret_cast<R*>(&ex), 1);
+    if (lane == 0) set_identity(ex);
+}
+template <int N, typename R, bool G>
+__device__ __forceinline__ void wave_inclusive_suffix_s(SElem<N, R>& incl, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        SElem<N, R> o = incl;
+        shfl_down_words<Words<N>::S>(reinterpret_cast<R*>(&o), d);
+        if (lane + d >= 64) set_identity(o);
+        scombine<N, R, G>(incl, o, incl);
+    }
+}
+template <int N, typename R>
+__device__ __forceinline__ void wave_exclusive_suffix_s(const SElem<N, R>& incl, SElem<N, R>& ex, int lane) {
+    ex = incl;
+    shfl_down_words<Words<N>::S>(reinterpret_cast<R*>(&ex), 1);
+    if (lane == 63) set_identity(ex);
+}
+
+// ===========================================================================
+// FILTER
+// ===========================================================================
+// reduce over steps (elements built from y)
+template <int N, typename R, int EPT, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t k0 = gt * EPT;
+    const ConstLayout CL = const_layout(N, a.ny);
+    const R* y = static_cast<const R*>(a.y);
+    FElem<N, R> acc;
+    set_identity(acc);
+    if (k0 < a.total) {
+        Seq s = seq_find<SEG>(a, k0);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int64_t k = k0 + e;
+            if (k < a.total) {
+                seq_forward<SEG>(a, s, k);
+                const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+                FElem<N, R> x;
+                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, k == s.start, x);
+                if (e == 0) acc = x;
+                else fcombine<N, R, SEG>(acc, x, acc);
+            }
+        }
+    }
+    wave_inclusive_f<N, R, SEG>(acc, lane);
+    FElem<N, R> ex;
+    wave_exclusive_from_inclusive_f(acc, ex, lane);
+    store_f(a.thr, a.nthr, gt, ex);
+    if (lane == 63) store_f(a.agg, a.nwaves, gt >> 6, acc);
+}
+
+// reduce over explicit items (level 1: the level-0 wave aggregates)
+template <int N, typename R, int EPT, bool G>
+__global__ __launch_bounds__(kBlock) void k_filter_reduce_items(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = gt * EPT;
+    FElem<N, R> acc;
+    set_identity(acc);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t i = i0 + e;
+        if (i < a.nwaves) {
+            FElem<N, R> x;
+            load_f(a.agg, a.nwaves, i, x);
+            if (e == 0) acc = x;
+            else fcombine<N, R, G>(acc, x, acc);
+        }
+    }
+    wave_inclusive_f<N, R, G>(acc, lane);
+    FElem<N, R> ex;
+    wave_exclusive_from_inclusive_f(acc, ex, lane);
+    store_f(a.thr1, a.nthr1, gt, ex);
+    if (lane == 63) store_f(a.agg1, a.nwaves1, gt >> 6, acc);
+}
+
+// top: one workgroup scans n items, writes carry[i] = moments of items 0..i-1
+// NT threads (64 or 256).  Also reports models whose precompute failed
+// (model_fail[b] != 0) to the numeric flag; this runs after the precompute
+// kernel has finished, so the flag was already prepared.
+template <int N, typename R, bool G, int NT>
+__global__ __launch_bounds__(NT) void k_filter_top(const void* items, int64_t n, void* carry,
+                                                   const int* model_fail, int nmodels, int* status) {
+    __shared__ R sh[NT / 64][Words<N>::F];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int b = tid; b < nmodels; b += NT)
+        if (model_fail[b]) atomicMin(status, b);
+    const int64_t chunk = (n + NT - 1) / NT;
+    const int64_t i0 = tid * chunk;
+    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    FElem<N, R> acc;
+    set_identity(acc);
+    for (int64_t i = i0; i < i1; ++i) {
+        FElem<N, R> x;
+        load_f(items, n, i, x);
+        if (i == i0) acc = x;
+        else fcombine<N, R, G>(acc, x, acc);
+    }
+    wave_inclusive_f<N, R, G>(acc, lane);
+    FElem<N, R> ex;
+    wave_exclusive_from_inclusive_f(acc, ex, lane);
+    if (lane == 63) {
+        const R* w = reinterpret_cast<const R*>(&acc);
+#pragma unroll
+        for (int k = 0; k < Words<N>::F; ++k) sh[wave][k] = w[k];
+    }
+    __syncthreads();
+    if (wave > 0) {
+        FElem<N, R> wp;
+        R* wpw = reinterpret_cast<R*>(&wp);
+#pragma unroll
+        for (int k = 0; k < Words<N>::F; ++k) wpw[k] = sh[0][k];
+        for (int w = 1; w < wave; ++w) {
+            FElem<N, R> x;
+            R* xw = reinterpret_cast<R*>(&x);
+#pragma unroll
+            for (int k = 0; k < Words<N>::F; ++k) xw[k] = sh[w][k];
+            fcombine<N, R, G>(wp, x, wp);
+        }
+        fcombine<N, R, G>(wp, ex, ex);
+    }
+    Moments<N, R> X;
+#pragma unroll
+    for (int r = 0; r < N; ++r) X.m[r] = ex.b[r];
+#pragma unroll
+    for (int r = 0; r < tri(N); ++r) X.P[r] = ex.C[r];
+    for (int64_t i = i0; i < i1; ++i) {
+        store_m(carry, n, i, X);
+        FElem<N, R> x;
+        load_f(items, n, i, x);
+        fcarry<N, R, G>(X, x);
+    }
+}
+
+// level-1 down: carries of the level-0 waves
+template <int N, typename R, int EPT, bool G>
+__global__ __launch_bounds__(kBlock) void k_filter_down_items(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = gt * EPT;
+    if (i0 >= a.nwaves) return;
+    Moments<N, R> X;
+    load_m(a.carry1, a.nwaves1, gt >> 6, X);
+    FElem<N, R> pre;
+    load_f(a.thr1, a.nthr1, gt, pre);
+    fcarry<N, R, G>(X, pre);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t i = i0 + e;
+        if (i < a.nwaves) {
+            store_m(a.carry, a.nwaves, i, X);
+            FElem<N, R> x;
+            load_f(a.agg, a.nwaves, i, x);
+            fcarry<N, R, G>(X, x);
+        }
+    }
+}
+
+// level-0 down: outputs m_k, P_k
+template <int N, typename R, int EPT, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k0 = gt * EPT;
+    if (k0 >= a.total) return;
+    const ConstLayout CL = const_layout(N, a.ny);
+    const R* y = static_cast<const R*>(a.y);
+    R* mo = static_cast<R*>(a.m);
+    R* Po = static_cast<R*>(a.P);
+    Moments<N, R> X;
+    load_m(a.carry, a.nwaves, gt >> 6, X);
+    {
+        FElem<N, R> pre;
+        load_f(a.thr, a.nthr, gt, pre);
+        fcarry<N, R, SEG>(X, pre);
+    }
+    Seq s = seq_find<SEG>(a, k0);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t k = k0 + e;
+        if (k < a.total) {
+            seq_forward<SEG>(a, s, k);
+            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            FElem<N, R> x;
+            build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, k == s.start, x);
+            fcarry<N, R, SEG>(X, x);
+            store_moments_step(mo, Po, k, X);
+        }
+    }
+}
+
+// ===========================================================================
+// SMOOTHER (suffix direction)
+// ===========================================================================
+template <int N, typename R, int EPT, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t k0 = gt * EPT;
+    const ConstLayout CL = const_layout(N, a.ny);
+    const R* m = static_cast<const R*>(a.m);
+    const R* P = static_cast<const R*>(a.P);
+    SElem<N, R> acc;
+    set_identity(acc);
+    if (k0 < a.total) {
+        const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
+        Seq s = seq_find<SEG>(a, klast);
+#pragma unroll
+        for (int e = EPT - 1; e >= 0; --e) {
+            const int64_t k = k0 + e;
+            if (k < a.total) {
+                seq_backward<SEG>(a, s, k);
+                const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+                Moments<N, R> x;
+                load_moments_step(m, P, k, x);
+                SElem<N, R> el;
+                make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
+                if (k == klast) acc = el;
+                else scombine<N, R, SEG>(el, acc, acc);
+            }
+        }
+    }
+    wave_inclusive_suffix_s<N, R, SEG>(acc, lane);
+    SElem<N, R> ex;
+    wave_exclusive_suffix_s(acc, ex, lane);
+    store_s(a.thr, a.nthr, gt, ex);
+    if (lane == 0) store_s(a.agg, a.nwaves, gt >> 6, acc);
+}
+
+template <int N, typename R, int EPT, bool G>
+__global__ __launch_bounds__(kBlock) void k_smoother_reduce_items(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = gt * EPT;
+    SElem<N, R> acc;
+    set_identity(acc);
+#pragma unroll
+    for (int e = EPT - 1; e >= 0; --e) {
+        const int64_t i = i0 + e;
+        if (i < a.nwaves) {
+            SElem<N, R> x;
+            load_s(a.agg, a.nwaves, i, x);
+            scombine<N, R, G>(x, acc, acc);
+        }
+    }
+    wave_inclusive_suffix_s<N, R, G>(acc, lane);
+    SElem<N, R> ex;
+    wave_exclusive_suffix_s(acc, ex, lane);
+    store_s(a.thr1, a.nthr1, gt, ex);
+    if (lane == 0) store_s(a.agg1, a.nwaves1, gt >> 6, acc);
+}
+
+// top: carry[i] = moments of items i+1..n-1 (suffix; E of the product is 0)
+template <int N, typename R, bool G, int NT>
+__global__ __launch_bounds__(NT) void k_smoother_top(const void* items, int64_t n, void* carry) {
+    __shared__ R sh[NT / 64][Words<N>::S];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t chunk = (n + NT - 1) / NT;
+    const int64_t i0 = tid * chunk;
+    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    SElem<N, R> acc;
+    set_identity(acc);
+    for (int64_t i = i1 - 1; i >= i0; --i) {
+        SElem<N, R> x;
+        load_s(items, n, i, x);
+        scombine<N, R, G>(x, acc, acc);
+    }
+    wave_inclusive_suffix_s<N, R, G>(acc, lane);
+    SElem<N, R> ex;
+    wave_exclusive_suffix_s(acc, ex, lane);
+    if (lane == 0) {
+        const R* w = reinterpret_cast<const R*>(&acc);
+#pragma unroll
+        for (int k = 0; k < Words<N>::S; ++k) sh[wave][k] = w[k];
+    }
+    __syncthreads();
+    constexpr int NW = NT / 64;
+    if (wave < NW - 1) {
+        SElem<N, R> ws;   // product of waves wave+1 .. NW-1
+        R* wsw = reinterpret_cast<R*>(&ws);
+#pragma unroll
+        for (int k = 0; k < Words<N>::S; ++k) wsw[k] = sh[NW - 1][k];
+        for (int w = NW - 2; w > wave; --w) {
+            SElem<N, R> x;
+            R* xw = reinterpret_cast<R*>(&x);
+#pragma unroll
+            for (int k = 0; k < Words<N>::S; ++k) xw[k] = sh[w][k];
+            scombine<N, R, G>(x, ws, ws);
+        }
+        scombine<N, R, G>(ex, ws, ex);
+    }
+    Moments<N, R> Y;
+#pragma unroll
+    for (int r = 0; r < N; ++r) Y.m[r] = ex.g[r];
+#pragma unroll
+    for (int r = 0; r < tri(N); ++r) Y.P[r] = ex.L[r];
+    for (int64_t i = i1 - 1; i >= i0; --i) {
+        store_m(carry, n, i, Y);
+        SElem<N, R> x;
+        load_s(items, n, i, x);
+        scarry<N, R, G>(x, Y);
+    }
+}
+
+template <int N, typename R, int EPT, bool G>
+__global__ __launch_bounds__(kBlock) void k_smoother_down_items(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = gt * EPT;
+    if (i0 >= a.nwaves) return;
+    Moments<N, R> Y;
+    load_m(a.carry1, a.nwaves1, gt >> 6, Y);
+    SElem<N, R> pre;
+    load_s(a.thr1, a.nthr1, gt, pre);
+    scarry<N, R, G>(pre, Y);
+#pragma unroll
+    for (int e = EPT - 1; e >= 0; --e) {
+        const int64_t i = i0 + e;
+        if (i < a.nwaves) {
+            store_m(a.carry, a.nwaves, i, Y);
+            SElem<N, R> x;
+            load_s(a.agg, a.nwaves, i, x);
+            scarry<N, R, G>(x, Y);
+        }
+    }
+}
+
+template <int N, typename R, int EPT, bool SEG>
+__global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t k0 = gt * EPT;
+    if (k0 >= a.total) return;
+    const ConstLayout CL = const_layout(N, a.ny);
+    const R* m = static_cast<const R*>(a.m);
+    const R* P = static_cast<const R*>(a.P);
+    R* mso = static_cast<R*>(a.ms);
+    R* Pso = static_cast<R*>(a.Ps);
+    Moments<N, R> Y;
+    load_m(a.carry, a.nwaves, gt >> 6, Y);
+    {
+        SElem<N, R> pre;
+        load_s(a.thr, a.nthr, gt, pre);
+        scarry<N, R, SEG>(pre, Y);
+    }
+    const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
+    Seq s = seq_find<SEG>(a, klast);
+#pragma unroll
+    for (int e = EPT - 1; e >= 0; --e) {
+        const int64_t k = k0 + e;
+        if (k < a.total) {
+            seq_backward<SEG>(a, s, k);
+            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            Moments<N, R> x;
+            load_moments_step(m, P, k, x);
+            SElem<N, R> el;
+            make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
+            scarry<N, R, SEG>(el, Y);
+            store_moments_step(mso, Pso, k, Y);
+        }
+    }
+}
+
+// ===========================================================================
+// launch helpers
+// ===========================================================================
+inline int64_t blocks_for_threads(int64_t nthr) { return (nthr + kBlock - 1) / kBlock; }
+
+template <int N, typename R, bool G>
+void launch_filter_top(const void* items, int64_t n, void* carry, const ScanArgs& a, hipStream_t s) {
+    if (n <= 64) {
+        prof_begin("k_filter_top", s);
+        hipLaunchKernelGGL((k_filter_top<N, R, G, 64>), dim3(1), dim3(64), 0, s, items, n, carry, a.model_fail,
+                           a.nmodels, a.status);
+        prof_end(s);
+    } else {
+        prof_begin("k_filter_top", s);
+        hipLaunchKernelGGL((k_filter_top<N, R, G, kBlock>), dim3(1), dim3(kBlock), 0, s, items, n, carry,
+                           a.model_fail, a.nmodels, a.status);
+        prof_end(s);
+    }
+}
+template <int N, typename R, bool G>
+void launch_smoother_top(const void* items, int64_t n, void* carry, hipStream_t s) {
+    prof_begin("k_smoother_top", s);
+    if (n <= 64) hipLaunchKernelGGL((k_smoother_top<N, R, G, 64>), dim3(1), dim3(64), 0, s, items, n, carry);
+    else hipLaunchKernelGGL((k_smoother_top<N, R, G, kBlock>), dim3(1), dim3(kBlock), 0, s, items, n, carry);
+    prof_end(s);
+}
+
+#define PKS_EPT1_SWITCH(KERNEL, ...)                                                                   \
+    switch (a.ept1) {                                                                                  \
+        case 1: hipLaunchKernelGGL((KERNEL<N, R, 1, SEG>), dim3(nb1), dim3(kBlock), 0, s, a); break;   \
+        case 2: hipLaunchKernelGGL((KERNEL<N, R, 2, SEG>), dim3(nb1), dim3(kBlock), 0, s, a); break;   \
+        case 4: hipLaunchKernelGGL((KERNEL<N, R, 4, SEG>), dim3(nb1), dim3(kBlock), 0, s, a); break;   \
+        case 8: hipLaunchKernelGGL((KERNEL<N, R, 8, SEG>), dim3(nb1), dim3(kBlock), 0, s, a); break;   \
+        default: return hipErrorInvalidValue;                                                          \
+    }
+
+template <int N, typename R, int EPT, bool SEG>
+hipError_t run_filter(ScanArgs a, hipStream_t s) {
+    const int64_t nb0 = a.nthr / kBlock;
+    prof_begin("k_filter_reduce", s);
+    hipLaunchKernelGGL((k_filter_reduce<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    if (a.nwaves1 == 0) {
+        launch_filter_top<N, R, SEG>(a.agg, a.nwaves, a.carry, a, s);
+    } else {
+        const int64_t nb1 = a.nthr1 / kBlock;
+        prof_begin("k_filter_reduce_items", s);
+        PKS_EPT1_SWITCH(k_filter_reduce_items)
+        prof_end(s);
+        launch_filter_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, a, s);
+        prof_begin("k_filter_down_items", s);
+        PKS_EPT1_SWITCH(k_filter_down_items)
+        prof_end(s);
+    }
+    prof_begin("k_filter_down", s);
+    hipLaunchKernelGGL((k_filter_down<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    return hipGetLastError();
+}
+
+template <int N, typename R, int EPT, bool SEG>
+hipError_t run_smoother(ScanArgs a, hipStream_t s) {
+    const int64_t nb0 = a.nthr / kBlock;
+    prof_begin("k_smoother_reduce", s);
+    hipLaunchKernelGGL((k_smoother_reduce<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    if (a.nwaves1 == 0) {
+        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, s);
+    } else {
+        const int64_t nb1 = a.nthr1 / kBlock;
+        prof_begin("k_smoother_reduce_items", s);
+        PKS_EPT1_SWITCH(k_smoother_reduce_items)
+        prof_end(s);
+        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, s);
+        prof_begin("k_smoother_down_items", s);
+        PKS_EPT1_SWITCH(k_smoother_down_items)
+        prof_end(s);
+    }
+    prof_begin("k_smoother_down", s);
+    hipLaunchKernelGGL((k_smoother_down<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    return hipGetLastError();
+}
+#undef PKS_EPT1_SWITCH
+
+template <int N, typename R, bool SEG>
+hipError_t dispatch_ept(ScanArgs a, bool smoother, hipStream_t s) {
+    switch (a.ept) {
+        case 4: return smoother ? run_smoother<N, R, 4, SEG>(a, s) : run_filter<N, R, 4, SEG>(a, s);
+        case 8: return smoother ? run_smoother<N, R, 8, SEG>(a, s) : run_filter<N, R, 8, SEG>(a, s);
+        case 16: return smoother ? run_smoother<N, R, 16, SEG>(a, s) : run_filter<N, R, 16, SEG>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+// All scan kernels of one state dimension and precision (one translation unit each).
+template <int N, typename R>
+hipError_t small_run(ScanArgs a, bool smoother, hipStream_t s) {
+    return a.offsets != nullptr ? dispatch_ept<N, R, true>(a, smoother, s) : dispatch_ept<N, R, false>(a, smoother, s);
+}
+
+}  // namespace pks

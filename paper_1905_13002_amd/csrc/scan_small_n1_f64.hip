@@ -1,0 +1,6 @@
+// Instantiates the small-state scan kernels for nx = 1, double storage.
+#include "scan_small_impl.hpp"
+
+namespace pks {
+template hipError_t small_run<1, double>(ScanArgs, bool, hipStream_t);
+}

@@ -1,0 +1,6 @@
+// Instantiates the small-state scan kernels for nx = 4, float storage.
+#include "scan_small_impl.hpp"
+
+namespace pks {
+template hipError_t small_run<4, float>(ScanArgs, bool, hipStream_t);
+}

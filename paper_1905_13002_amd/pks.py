@@ -1,0 +1,311 @@
+"""Python binding of libpks.so (ctypes).  Argument marshalling only.
+
+Every step of the filter and smoother runs in the HIP kernels of libpks.so;
+this module turns torch tensors (device memory) and torch streams into the
+plain pointers of the C ABI (``include/pks.h``) and raises on error codes.
+Importing it loads the library and fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpks.so")
+
+PKS_OK, PKS_E_ARG, PKS_E_UNSUPPORTED, PKS_E_WORKSPACE, PKS_E_HIP, PKS_E_NUMERIC = range(6)
+PKS_FP64, PKS_MIXED_FP32 = 0, 1
+STATUS_NAMES = {0: "PKS_OK", 1: "PKS_E_ARG", 2: "PKS_E_UNSUPPORTED", 3: "PKS_E_WORKSPACE",
+                4: "PKS_E_HIP", 5: "PKS_E_NUMERIC"}
+
+EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smooth",
+            "pks_filter_batched", "pks_smooth_batched", "pks_plan_create", "pks_plan_launch",
+            "pks_plan_destroy", "pks_autotune", "pks_read_numeric_status", "pks_last_error",
+            "pks_version", "pks_profile_start", "pks_profile_stop"]
+
+
+class PksError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class pks_model(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("F", ctypes.c_void_p), ("u", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("d", ctypes.c_void_p), ("R", ctypes.c_void_p),
+                ("m0", ctypes.c_void_p), ("P0", ctypes.c_void_p),
+                ("per_sequence", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpks.so not found at %s: build it with "
+                          "`python -m paper_1905_13002_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    mp = ctypes.POINTER(pks_model)
+    sig = {
+        "pks_workspace_bytes": (sz, [i32, i32, i64, i32, ctypes.c_int]),
+        "pks_filter": (ctypes.c_int, [mp, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_smooth": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_filter_smooth": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_filter_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_smooth_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_plan_create": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz,
+                                           ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
+        "pks_plan_launch": (ctypes.c_int, [vp, vp]),
+        "pks_plan_destroy": (ctypes.c_int, [vp]),
+        "pks_autotune": (ctypes.c_int, [i32, i32, i32, i64, ctypes.c_int, ctypes.c_char_p, vp]),
+        "pks_read_numeric_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), vp]),
+        "pks_last_error": (ctypes.c_char_p, []),
+        "pks_profile_start": (ctypes.c_int, []),
+        "pks_profile_stop": (ctypes.c_int, [i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "pks_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != PKS_OK:
+        raise PksError(status, lib.pks_last_error().decode())
+
+
+def _prec(precision) -> int:
+    if precision in (PKS_FP64, "fp64", "f64", torch.float64):
+        return PKS_FP64
+    if precision in (PKS_MIXED_FP32, "mixed", "fp32", "f32", torch.float32):
+        return PKS_MIXED_FP32
+    raise ValueError("precision must be 'fp64' or 'mixed'")
+
+
+def _rdtype(prec: int):
+    return torch.float64 if prec == PKS_FP64 else torch.float32
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceModel:
+    """A model's matrices as float64 device tensors (kept alive with the struct)."""
+    F: torch.Tensor
+    Q: torch.Tensor
+    H: torch.Tensor
+    R: torch.Tensor
+    m0: torch.Tensor
+    P0: torch.Tensor
+    u: Optional[torch.Tensor] = None
+    d: Optional[torch.Tensor] = None
+    per_sequence: bool = False
+
+    @property
+    def nx(self):
+        return self.F.shape[-1]
+
+    @property
+    def ny(self):
+        return self.H.shape[-2]
+
+    def struct(self) -> pks_model:
+        s = pks_model()
+        s.nx, s.ny = self.nx, self.ny
+        for f in ("F", "Q", "H", "R", "m0", "P0", "u", "d"):
+            t = getattr(self, f)
+            setattr(s, f, None if t is None else t.data_ptr())
+        s.per_sequence = 1 if self.per_sequence else 0
+        return s
+
+
+def to_device(model, device="cuda", per_sequence: bool = False) -> DeviceModel:
+    """Copy a workloads.Model (numpy) to the device as float64 tensors."""
+    cv = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+    return DeviceModel(cv(model.F), cv(model.Q), cv(model.H), cv(model.R), cv(model.m0), cv(model.P0),
+                       cv(model.u), cv(model.d), per_sequence)
+
+
+def workspace_bytes(nx: int, ny: int, total: int, B: int = 1, precision="fp64") -> int:
+    n = lib.pks_workspace_bytes(nx, ny, int(total), int(B), _prec(precision))
+    if n == 0:
+        raise PksError(PKS_E_ARG, "invalid problem shape")
+    return int(n)
+
+
+def workspace(nx, ny, total, B=1, precision="fp64", device="cuda") -> torch.Tensor:
+    return torch.empty(workspace_bytes(nx, ny, total, B, precision), dtype=torch.uint8, device=device)
+
+
+def _out(shape, prec, device):
+    return torch.empty(shape, dtype=_rdtype(prec), device=device)
+
+
+def filter(model: DeviceModel, y: torch.Tensor, precision="fp64", ws=None, out=None, stream=None):
+    """Parallel Kalman filter: returns (m [T,nx], P [T,nx,nx])."""
+    prec = _prec(precision)
+    T = y.shape[0]
+    m, P = out if out is not None else (_out((T, model.nx), prec, y.device),
+                                         _out((T, model.nx, model.nx), prec, y.device))
+    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, y.device)
+    ms = model.struct()
+    _check(lib.pks_filter(ctypes.byref(ms), T, _ptr(y), _ptr(m), _ptr(P), prec, _ptr(ws), ws.numel(),
+                          _stream(stream)))
+    return m, P
+
+
+def smooth(model: DeviceModel, m: torch.Tensor, P: torch.Tensor, precision="fp64", ws=None, out=None,
+           stream=None):
+    """Parallel RTS smoother from filtered moments: returns (ms, Ps)."""
+    prec = _prec(precision)
+    T = m.shape[0]
+    ms_, Ps_ = out if out is not None else (torch.empty_like(m), torch.empty_like(P))
+    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, m.device)
+    st = model.struct()
+    _check(lib.pks_smooth(ctypes.byref(st), T, _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec, _ptr(ws),
+                          ws.numel(), _stream(stream)))
+    return ms_, Ps_
+
+
+def filter_smooth(model: DeviceModel, y: torch.Tensor, precision="fp64", ws=None, out=None, stream=None):
+    """Filter then smoother in one call: returns (m, P, ms, Ps)."""
+    prec = _prec(precision)
+    T = y.shape[0]
+    nx = model.nx
+    if out is None:
+        out = (_out((T, nx), prec, y.device), _out((T, nx, nx), prec, y.device),
+               _out((T, nx), prec, y.device), _out((T, nx, nx), prec, y.device))
+    m, P, ms_, Ps_ = out
+    ws = ws if ws is not None else workspace(nx, model.ny, T, 1, prec, y.device)
+    st = model.struct()
+    _check(lib.pks_filter_smooth(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec,
+                                 _ptr(ws), ws.numel(), _stream(stream)))
+    return m, P, ms_, Ps_
+
+
+def filter_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, precision="fp64", ws=None,
+                   out=None, stream=None):
+    prec = _prec(precision)
+    B = offsets.shape[0] - 1
+    total = y.shape[0]
+    nx = model.nx
+    m, P = out if out is not None else (_out((total, nx), prec, y.device), _out((total, nx, nx), prec, y.device))
+    ws = ws if ws is not None else workspace(nx, model.ny, total, B, prec, y.device)
+    st = model.struct()
+    _check(lib.pks_filter_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P), prec,
+                                  _ptr(ws), ws.numel(), _stream(stream)))
+    return m, P
+
+
+def smooth_batched(model: DeviceModel, offsets: torch.Tensor, m: torch.Tensor, P: torch.Tensor,
+                   precision="fp64", ws=None, out=None, stream=None):
+    prec = _prec(precision)
+    B = offsets.shape[0] - 1
+    total = m.shape[0]
+    ms_, Ps_ = out if out is not None else (torch.empty_like(m), torch.empty_like(P))
+    ws = ws if ws is not None else workspace(model.nx, model.ny, total, B, prec, m.device)
+    st = model.struct()
+    _check(lib.pks_smooth_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(m), _ptr(P), _ptr(ms_),
+                                  _ptr(Ps_), prec, _ptr(ws), ws.numel(), _stream(stream)))
+    return ms_, Ps_
+
+
+class Plan:
+    """A captured filter + smoother (HIP graph) bound to fixed buffers."""
+
+    def __init__(self, model: DeviceModel, y: torch.Tensor, offsets: Optional[torch.Tensor] = None,
+                 precision="fp64", tune_cache: Optional[str] = None, stream=None):
+        prec = _prec(precision)
+        self.prec = prec
+        self.model = model
+        self.y = y
+        self.offsets = offsets
+        total = y.shape[0]
+        B = 1 if offsets is None else offsets.shape[0] - 1
+        nx = model.nx
+        dev = y.device
+        self.m = _out((total, nx), prec, dev)
+        self.P = _out((total, nx, nx), prec, dev)
+        self.ms = _out((total, nx), prec, dev)
+        self.Ps = _out((total, nx, nx), prec, dev)
+        self.ws = workspace(nx, model.ny, total, B, prec, dev)
+        self._struct = model.struct()
+        h = ctypes.c_void_p()
+        _check(lib.pks_plan_create(ctypes.byref(self._struct), B, _ptr(offsets), total, _ptr(y), _ptr(self.m),
+                                   _ptr(self.P), _ptr(self.ms), _ptr(self.Ps), prec, _ptr(self.ws),
+                                   self.ws.numel(), tune_cache.encode() if tune_cache else None, _stream(stream),
+                                   ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib.pks_plan_launch(self.handle, _stream(stream)))
+        return self.m, self.P, self.ms, self.Ps
+
+    def close(self):
+        if self.handle:
+            lib.pks_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(nx, ny, B, total, precision="fp64", cache_path: Optional[str] = None, stream=None):
+    _check(lib.pks_autotune(nx, ny, B, int(total), _prec(precision),
+                            cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def read_numeric_status(ws: torch.Tensor, stream=None):
+    """Returns (ok, first_bad_sequence or -1); clears the flag."""
+    bad = ctypes.c_int32(-1)
+    st = lib.pks_read_numeric_status(_ptr(ws), ctypes.byref(bad), _stream(stream))
+    if st == PKS_E_NUMERIC:
+        return False, int(bad.value)
+    _check(st)
+    return True, -1
+
+
+def profile_start():
+    _check(lib.pks_profile_start())
+
+
+def profile_stop(max_kernels: int = 64):
+    """Returns {kernel name: (total ms, launches)} recorded since profile_start()."""
+    names = ctypes.create_string_buffer(64 * max_kernels)
+    tot = (ctypes.c_float * max_kernels)()
+    cnt = (ctypes.c_int32 * max_kernels)()
+    n = ctypes.c_int32(0)
+    _check(lib.pks_profile_stop(max_kernels, names, tot, cnt, ctypes.byref(n)))
+    out = {}
+    for i in range(n.value):
+        nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (float(tot[i]), int(cnt[i]))
+    return out
+
+
+def version() -> str:
+    return lib.pks_version().decode()

@@ -303,8 +303,13 @@ def single_sequence(model: Model, T: int, seed: int, keep_states: bool = False) 
 # error metric (per-step normwise relative error, maximised over steps)
 # ---------------------------------------------------------------------------
 
-def max_rel_err(X: np.ndarray, Xref: np.ndarray) -> float:
-    """max_k ||X_k - Xref_k||_F / max(||Xref_k||_F, 1e-300) over the leading axis."""
+def max_rel_err(X: np.ndarray, Xref: np.ndarray, floor: str = "none") -> float:
+    """max_k ||X_k - Xref_k||_F / max(||Xref_k||_F, f) over the leading axis.
+
+    floor = "none": f = 1e-300 (plain per-step normwise relative error);
+    floor = "rms":  f = root-mean-square of ||Xref_k||_F over k (for results
+    that pass through zero, e.g. the mean of a scalar state).
+    """
     X = np.asarray(X, dtype=np.float64)
     Xref = np.asarray(Xref, dtype=np.float64)
     n = X.shape[0]
@@ -313,7 +318,9 @@ def max_rel_err(X: np.ndarray, Xref: np.ndarray) -> float:
     D = (X - Xref).reshape(n, -1)
     num = np.sqrt(np.einsum("ij,ij->i", D, D))
     R = Xref.reshape(n, -1)
-    den = np.maximum(np.sqrt(np.einsum("ij,ij->i", R, R)), 1e-300)
+    nrm = np.sqrt(np.einsum("ij,ij->i", R, R))
+    f = 1e-300 if floor == "none" else max(1e-300, float(np.sqrt(np.mean(nrm ** 2))))
+    den = np.maximum(nrm, f)
     with np.errstate(invalid="ignore"):
         r = num / den
     if np.any(np.isnan(r)):

@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, sizes workspaces, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pks.h")
+
+pks = pytest.importorskip("paper_1905_13002_amd.pks", reason="libpks.so not built")
+lib = pks.lib
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pks_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert "pks_filter" in names and "pks_smooth" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(pks.EXPORTED) == set(names)
+
+
+def test_version():
+    assert "pks" in pks.version()
+
+
+def test_workspace_bytes():
+    n1 = lib.pks_workspace_bytes(4, 2, 1024, 1, 0)
+    n2 = lib.pks_workspace_bytes(4, 2, 1 << 20, 1, 0)
+    n3 = lib.pks_workspace_bytes(4, 2, 1 << 20, 1, 1)
+    assert 0 < n1 < n2 and 0 < n3 < n2
+    assert lib.pks_workspace_bytes(4, 2, 0, 1, 0) > 0
+    for bad in ((0, 2, 10, 1, 0), (65, 2, 10, 1, 0), (4, 0, 10, 1, 0), (4, 65, 10, 1, 0),
+                (4, 2, -1, 1, 0), (4, 2, 10, 0, 0), (4, 2, 10, 1, 7)):
+        assert lib.pks_workspace_bytes(*bad) == 0
+    # batched workspaces hold one constant block per model
+    assert lib.pks_workspace_bytes(4, 2, 10000, 4096, 0) > lib.pks_workspace_bytes(4, 2, 10000, 1, 0)
+
+
+FAKE = 0x10000000   # never dereferenced: every case below fails validation first
+
+
+def fake_model(nx=4, ny=2, per_sequence=0, **null):
+    m = pks.pks_model()
+    m.nx, m.ny = nx, ny
+    for i, f in enumerate(("F", "Q", "H", "R", "m0", "P0")):
+        setattr(m, f, None if null.get(f) else FAKE + 0x100000 * (i + 1))
+    m.u = m.d = None
+    m.per_sequence = per_sequence
+    return m
+
+
+def call_filter(model, T=16, y=FAKE + 0x1000000, m=FAKE + 0x2000000, P=FAKE + 0x3000000, prec=0,
+                ws=FAKE + 0x8000000, ws_bytes=None):
+    if ws_bytes is None:
+        ok = model is not None and 1 <= model.nx <= 64 and 1 <= model.ny <= 64 and prec in (0, 1)
+        ws_bytes = lib.pks_workspace_bytes(model.nx, model.ny, max(T, 0), 1, prec) if ok else 1 << 30
+    mp = ctypes.byref(model) if model is not None else None
+    return lib.pks_filter(mp, T, y, m, P, prec, ws, ws_bytes, None)
+
+
+def test_filter_argument_errors():
+    assert call_filter(None) == pks.PKS_E_ARG
+    assert call_filter(fake_model(nx=0)) == pks.PKS_E_ARG
+    assert call_filter(fake_model(nx=65)) == pks.PKS_E_ARG
+    assert call_filter(fake_model(ny=0)) == pks.PKS_E_ARG
+    assert call_filter(fake_model(F=True)) == pks.PKS_E_ARG
+    assert call_filter(fake_model(R=True)) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), T=-1) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), y=None) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), P=None) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), prec=3) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), ws=None) == pks.PKS_E_ARG
+    assert call_filter(fake_model(per_sequence=1)) == pks.PKS_E_ARG
+    assert "per_sequence" in lib.pks_last_error().decode()
+
+
+def test_filter_aliasing_rejected():
+    # m overlapping y, P overlapping m
+    assert call_filter(fake_model(), y=FAKE + 0x1000000, m=FAKE + 0x1000000 + 8) == pks.PKS_E_ARG
+    assert call_filter(fake_model(), m=FAKE + 0x2000000, P=FAKE + 0x2000000 + 16 * 4 * 8 - 8) == pks.PKS_E_ARG
+
+
+def test_workspace_too_small():
+    need = lib.pks_workspace_bytes(4, 2, 5000, 1, 0)
+    assert call_filter(fake_model(), T=5000, ws_bytes=need - 1) == pks.PKS_E_WORKSPACE
+    assert "workspace" in lib.pks_last_error().decode()
+
+
+def test_smoother_argument_errors():
+    m = fake_model()
+    wsb = lib.pks_workspace_bytes(4, 2, 16, 1, 0)
+    assert lib.pks_smooth(ctypes.byref(m), 16, FAKE, FAKE + 0x1000000, None, FAKE + 0x3000000, 0,
+                          FAKE + 0x8000000, wsb, None) == pks.PKS_E_ARG
+    # output overlapping the filtered input
+    assert lib.pks_smooth(ctypes.byref(m), 16, FAKE, FAKE + 0x1000000, FAKE + 8, FAKE + 0x3000000, 0,
+                          FAKE + 0x8000000, wsb, None) == pks.PKS_E_ARG
+
+
+def test_batched_argument_errors():
+    m = fake_model(per_sequence=1)
+    wsb = lib.pks_workspace_bytes(4, 2, 100, 3, 0)
+    args = (FAKE + 0x1000000, FAKE + 0x2000000, FAKE + 0x3000000, 0, FAKE + 0x8000000, wsb, None)
+    assert lib.pks_filter_batched(ctypes.byref(m), 0, FAKE, 100, *args) == pks.PKS_E_ARG
+    assert lib.pks_filter_batched(ctypes.byref(m), 3, None, 100, *args) == pks.PKS_E_ARG
+    assert lib.pks_filter_batched(ctypes.byref(m), 3, FAKE, -5, *args) == pks.PKS_E_ARG
+
+
+def test_plan_and_tuner_argument_errors():
+    assert lib.pks_plan_destroy(None) == pks.PKS_OK
+    assert lib.pks_plan_launch(None, None) == pks.PKS_E_ARG
+    h = ctypes.c_void_p()
+    m = fake_model()
+    # offsets NULL with B != 1
+    assert lib.pks_plan_create(ctypes.byref(m), 2, None, 10, FAKE, FAKE + 0x1000000, FAKE + 0x2000000,
+                               FAKE + 0x3000000, FAKE + 0x4000000, 0, FAKE + 0x8000000, 1 << 30, None, None,
+                               ctypes.byref(h)) == pks.PKS_E_ARG
+    old = os.environ.pop("PKS_TUNE_CACHE", None)
+    try:
+        assert lib.pks_autotune(4, 2, 1, 1000, 0, None, None) == pks.PKS_E_ARG
+    finally:
+        if old is not None:
+            os.environ["PKS_TUNE_CACHE"] = old
+    assert lib.pks_autotune(0, 2, 1, 1000, 0, b"/tmp/x.json", None) == pks.PKS_E_ARG

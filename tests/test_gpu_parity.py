@@ -1,0 +1,284 @@
+"""GPU parity: the HIP scan path (through the C ABI) against the FP64 oracle.
+
+Bar: per result (filtered mean/cov, smoothed mean/cov), the per-step normwise
+relative error max_k ||X_k - X_k^ref||_F / ||X_k^ref||_F is <= 1e-9 in FP64
+and <= 1e-4 in the mixed mode.  The mixed path reads float32 y, so its
+reference is the oracle run on that rounded y widened to float64.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_13002_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def pks():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_13002_amd import pks as mod
+    return mod
+
+
+def oracle_run(model, y, offsets=None, per_sequence=False):
+    if offsets is None:
+        return oracle.kf_rts(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, u=model.u, d=model.d)
+    return oracle.kf_rts_batched(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, offsets,
+                                 u=model.u, d=model.d, per_sequence=per_sequence)
+
+
+def gpu_run(pks, model, y, precision, offsets=None, per_sequence=False, separate=False):
+    dm = pks.to_device(model, per_sequence=per_sequence)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    yd = torch.as_tensor(np.ascontiguousarray(y)).to("cuda", dt)
+    if offsets is None:
+        if separate:
+            m, P = pks.filter(dm, yd, precision)
+            ms, Ps = pks.smooth(dm, m, P, precision)
+        else:
+            m, P, ms, Ps = pks.filter_smooth(dm, yd, precision)
+    else:
+        od = torch.as_tensor(np.asarray(offsets, dtype=np.int64)).cuda()
+        m, P = pks.filter_batched(dm, od, yd, precision)
+        ms, Ps = pks.smooth_batched(dm, od, m, P, precision)
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in zip(("m", "P", "ms", "Ps"), (m, P, ms, Ps))}
+
+
+def ref_input(y, precision):
+    return y if precision == "fp64" else y.astype(np.float32).astype(np.float64)
+
+
+def assert_parity(out, ref, precision, what="", floor="none"):
+    errs = {k: wl.max_rel_err(out[k], ref[k], floor) for k in ("m", "P", "ms", "Ps")}
+    print(what, precision, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= TOL[precision], (what, k, e)
+    return errs
+
+
+def check(pks, model, y, precision, what="", floor="none", **kw):
+    ref = oracle_run(model, ref_input(y, precision))
+    out = gpu_run(pks, model, y, precision, **kw)
+    return assert_parity(out, ref, precision, what, floor)
+
+
+def storage_floor(model, y):
+    """Smoother error caused by nothing but storing the filtered moments in
+    float32: the exact FP64 smoother (Lemmas 3-4 folded sequentially) run on
+    the oracle's filter output rounded to float32, against the oracle."""
+    from oracle import elements as el
+    ref = oracle_run(model, ref_input(y, "mixed"))
+    r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    els = el.smoother_elements(model.F, model.Q, r32(ref["m"]), r32(ref["P"]), model.u)
+    ms, Ps = el.smoother_suffix_fold(els)
+    return max(wl.max_rel_err(ms, ref["ms"], "rms"), wl.max_rel_err(Ps, ref["Ps"], "rms"))
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cv_T1024(pks, precision):
+    w = wl.workload(1)
+    check(pks, w.model, w.y, precision, "cv T=1024")
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 63, 64, 65, 511, 512, 513, 2047, 2048, 2049, 33333])
+def test_cv_ragged_lengths_fp64(pks, T):
+    w = wl.workload(1, T=T)
+    check(pks, w.model, w.y, "fp64", "cv T=%d" % T)
+
+
+@pytest.mark.parametrize("T", [1, 5, 513, 4099])
+def test_cv_ragged_lengths_mixed(pks, T):
+    w = wl.workload(1, T=T)
+    check(pks, w.model, w.y, "mixed", "cv T=%d" % T)
+
+
+def test_last_step_and_T1(pks):
+    w = wl.workload(1, T=1)
+    out = gpu_run(pks, w.model, w.y, "fp64")
+    assert np.array_equal(out["ms"], out["m"]) and np.array_equal(out["Ps"], out["P"])
+    w = wl.workload(1, T=777)
+    out = gpu_run(pks, w.model, w.y, "fp64")
+    assert np.array_equal(out["ms"][-1], out["m"][-1]) and np.array_equal(out["Ps"][-1], out["P"][-1])
+    for k in ("P", "Ps"):
+        assert np.array_equal(out[k], np.swapaxes(out[k], 1, 2))
+
+
+@pytest.mark.parametrize("nx,ny,singQ", [(1, 1, False), (2, 1, False), (2, 2, True), (3, 1, False),
+                                         (3, 2, True), (3, 3, False), (4, 1, False), (4, 3, True),
+                                         (4, 4, False)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_random_small_models(pks, nx, ny, singQ, precision):
+    rng = np.random.default_rng(500 + 10 * nx + ny)
+    model = wl.random_small_model(nx, ny, rng, singular_Q=singQ)
+    w = wl.single_sequence(model, 3001, seed=nx * 10 + ny)
+    if precision == "fp64":
+        check(pks, model, w.y, precision, "random nx=%d ny=%d" % (nx, ny))
+        return
+    # Mixed mode.  Means of these models pass through zero, so the denominator
+    # is floored at the sequence's RMS norm.  Some of these models make the
+    # smoother ill-conditioned (rank-1 Q: cond(F P F^T + Q) reaches 1e7), where
+    # float32 storage of the filtered moments alone exceeds 1e-4; the bar is
+    # then a fixed multiple of that storage floor.
+    floor = storage_floor(model, w.y)
+    bar = max(TOL["mixed"], 30.0 * floor)
+    ref = oracle_run(model, ref_input(w.y, precision))
+    out = gpu_run(pks, model, w.y, precision)
+    errs = {k: wl.max_rel_err(out[k], ref[k], "rms") for k in ("m", "P", "ms", "Ps")}
+    print("random nx=%d ny=%d mixed" % (nx, ny), errs, "storage floor %.2e" % floor, flush=True)
+    assert errs["m"] <= TOL["mixed"] and errs["P"] <= TOL["mixed"]
+    assert errs["ms"] <= bar and errs["Ps"] <= bar
+
+
+def test_static_model_Q0(pks):
+    rng = np.random.default_rng(77)
+    nx, ny = 3, 2
+    model = wl.Model(np.eye(nx), np.zeros((nx, nx)), rng.standard_normal((ny, nx)), 0.5 * np.eye(ny),
+                     rng.standard_normal(nx), np.eye(nx))
+    w = wl.single_sequence(model, 2000, seed=3)
+    check(pks, model, w.y, "fp64", "static Q=0")
+
+
+def test_separate_calls_match_fused(pks):
+    w = wl.workload(1, T=5000)
+    a = gpu_run(pks, w.model, w.y, "fp64")
+    b = gpu_run(pks, w.model, w.y, "fp64", separate=True)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("ept,ept1", [(4, 0), (8, 0), (16, 0), (4, 1), (8, 2), (16, 1), (4, 4), (8, 8), (16, 4)])
+def test_every_tile_configuration(pks, tmp_path, monkeypatch, ept, ept1):
+    T = 150001
+    cache = tmp_path / "tune.json"
+    key = "nx4_ny2_fp64_T%d_B0" % (T.bit_length() - 1)
+    cache.write_text(json.dumps({key: [ept, ept1]}))
+    monkeypatch.setenv("PKS_TUNE_CACHE", str(cache))
+    w = wl.workload(1, T=T)
+    check(pks, w.model, w.y, "fp64", "cv T=%d ept=%d ept1=%d" % (T, ept, ept1))
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_uneven_cv(pks, precision):
+    w = wl.workload(4, B=97, T=1500)
+    lengths = np.diff(w.offsets).copy()
+    # include very short sequences and an empty one
+    lengths[:6] = [1, 2, 0, 3, 64, 65]
+    offsets = np.zeros(w.B + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(lengths)
+    y = w.y[: offsets[-1]]
+    ref = oracle_run(w.model, ref_input(y, precision), offsets, per_sequence=True)
+    out = gpu_run(pks, w.model, y, precision, offsets=offsets, per_sequence=True)
+    assert_parity(out, ref, precision, "batched B=97")
+
+
+def test_batched_shared_model(pks):
+    rng = np.random.default_rng(4)
+    model = wl.random_small_model(3, 2, rng)
+    lengths = rng.integers(1, 900, size=40)
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    y, _ = wl.simulate(model, int(offsets[-1]), rng)
+    ref = oracle_run(model, y, offsets)
+    out = gpu_run(pks, model, y, "fp64", offsets=offsets)
+    assert_parity(out, ref, "fp64", "batched shared")
+
+
+# ---------------------------------------------------------------------------
+# plans, status, propagation
+# ---------------------------------------------------------------------------
+def test_plan_replays_match_eager(pks):
+    w = wl.workload(4, B=33, T=2000)
+    dm = pks.to_device(w.model, per_sequence=True)
+    yd = torch.as_tensor(w.y).cuda()
+    od = torch.as_tensor(w.offsets).cuda()
+    m, P = pks.filter_batched(dm, od, yd, "fp64")
+    ms, Ps = pks.smooth_batched(dm, od, m, P, "fp64")
+    eager = [t.clone() for t in (m, P, ms, Ps)]
+    plan = pks.Plan(dm, yd, od, "fp64")
+    for rep in range(3):
+        outs = plan.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, eager):
+            assert torch.equal(a, b), rep
+        # unrelated eager work between replays
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+        for o in outs:
+            o.fill_(float("nan"))
+    plan.close()
+
+
+def test_numeric_flag_single_and_batched(pks):
+    mo = wl.cv_model(1.0, 0.25)
+    bad = wl.Model(mo.F, mo.Q, mo.H, -np.eye(2), mo.m0, mo.P0)
+    dm = pks.to_device(bad)
+    y = torch.zeros(100, 2, dtype=torch.float64, device="cuda")
+    ws = pks.workspace(4, 2, 100)
+    pks.filter(dm, y, "fp64", ws=ws)
+    ok, first = pks.read_numeric_status(ws)
+    assert not ok and first == 0
+    ok, first = pks.read_numeric_status(ws)      # cleared by the read
+    assert ok
+    w = wl.workload(4, B=5, T=200)
+    R = w.model.R.copy()
+    R[3] = -np.eye(2)
+    badm = wl.Model(w.model.F, w.model.Q, w.model.H, R, w.model.m0, w.model.P0)
+    dm = pks.to_device(badm, per_sequence=True)
+    od = torch.as_tensor(w.offsets).cuda()
+    yd = torch.as_tensor(w.y).cuda()
+    ws = pks.workspace(4, 2, w.total, w.B)
+    m, P = pks.filter_batched(dm, od, yd, "fp64", ws=ws)
+    ok, first = pks.read_numeric_status(ws)
+    assert not ok and first == 3
+    s = w.seq(3)
+    assert torch.isnan(m[s]).all()
+    assert not torch.isnan(m[w.seq(2)]).any()
+
+
+def test_nan_in_y_propagates(pks):
+    w = wl.workload(1, T=3000)
+    y = w.y.copy()
+    y[1234, 0] = np.nan
+    out = gpu_run(pks, w.model, y, "fp64")
+    assert not np.isnan(out["m"][:1234]).any()
+    assert np.isnan(out["m"][1234:]).all()
+
+
+def test_empty_sequence_is_noop(pks):
+    mo = wl.cv_model()
+    dm = pks.to_device(mo)
+    y = torch.zeros(0, 2, dtype=torch.float64, device="cuda")
+    m, P, ms, Ps = pks.filter_smooth(dm, y, "fp64")
+    assert m.shape == (0, 4)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cv_T2pow20(pks, precision):
+    w = wl.workload(2)
+    check(pks, w.model, w.y, precision, "cv T=2^20")
+
+
+def test_batched_B4096_sampled(pks):
+    """The full batched workload (4096 uneven sequences); the oracle checks a sample of sequences."""
+    w = wl.workload(4)
+    for precision in ("fp64", "mixed"):
+        out = gpu_run(pks, w.model, w.y, precision, offsets=w.offsets, per_sequence=True)
+        rng = np.random.default_rng(0)
+        for b in sorted(set(rng.integers(0, w.B, size=24).tolist()) | {0, w.B - 1}):
+            s = w.seq(b)
+            ref = oracle_run(w.model_of(b), ref_input(w.y[s], precision))
+            assert_parity({k: v[s] for k, v in out.items()}, ref, precision, "B4096 seq %d" % b)
