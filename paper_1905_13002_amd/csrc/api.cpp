@@ -116,6 +116,7 @@ ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offset
     a.offsets = offsets;
     a.model_stride = model.per_sequence ? CL.words : 0;
     a.consts = prec == PKS_FP64 ? (const void*)(base + L.consts64) : (const void*)(base + L.consts32);
+    a.consts64 = reinterpret_cast<const double*>(base + L.consts64);
     a.thr = base + L.thr;
     a.agg = base + L.agg;
     a.carry = base + L.carry;

@@ -17,10 +17,12 @@ namespace pks {
 //   b_k   = c  + K  y_k,   c  = u - K (H u + d)
 //   eta_k = w  + W  y_k,   w  = -W (H u + d),    W = F^T H^T S^-1
 //   b_1   = c1 + K1 y_1,   c1 = m1 - K1 (H m1 + d), m1 = F m0 + u
+// G = H F and S = H Q H^T + R are kept as well: J = F^T H^T S^-1 H F = W G has
+// rank ny, which the single-step combines use.
 // All matrices row-major, full (not packed).
 // ---------------------------------------------------------------------------
 struct ConstLayout {
-    int A, C, J, K, W, c, w, K1, c1, C1, F, Q, u, words;
+    int A, C, J, K, W, c, w, K1, c1, C1, F, Q, u, G, S, words;
 };
 __host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
     ConstLayout L;
@@ -39,6 +41,8 @@ __host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
     L.F = o; o += n2;
     L.Q = o; o += n2;
     L.u = o; o += nx;
+    L.G = o; o += nm;    // H F      [ny][nx]  (J = W G: the rank-ny factors of J)
+    L.S = o; o += ny * ny;  // H Q H^T + R [ny][ny]
     L.words = (o + 15) & ~15;
     return L;
 }
@@ -83,6 +87,7 @@ struct ScanArgs {
     const int64_t* offsets;      // device [B+1]; nullptr = one sequence [0, total)
     int64_t model_stride;        // R words between models in consts (0 = shared)
     const void* consts;          // R-typed constants of model 0
+    const double* consts64;      // the same constants in double (S is always read in double)
     const void* y;               // filter input  [total][ny]
     void* m;                     // filter output [total][nx]  / smoother input
     void* P;                     // filter output [total][nx][nx] / smoother input

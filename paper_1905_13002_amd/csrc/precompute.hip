@@ -185,6 +185,8 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     bmm(G, H, false, F, false, ny, nx, nx);                  // H F
     bcopy(Z, G, nm);
     bsolve(Lc, ny, Z, nx);                                   // S^-1 H F
+    bcopy(out + CL.G, G, nm);                                // H F
+    bcopy(out + CL.S, S, m2);                                // H Q H^T + R
     btranspose(out + CL.K, Kt, ny, nx);                      // K
     btranspose(out + CL.W, Z, ny, nx);                       // W = (S^-1 H F)^T
     bmm(out + CL.J, G, true, Z, false, nx, ny, nx);          // F^T H^T S^-1 H F
@@ -319,6 +321,16 @@ struct SmallPre {
     }
 };
 
+// writes a constant in double and, for the mixed mode, in float
+struct DualOut {
+    double* d;
+    float* f;
+    __device__ __forceinline__ void put(int i, double v) const {
+        d[i] = v;
+        if (f) f[i] = (float)v;
+    }
+};
+
 template <int NX, int NY>
 __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int nmodels) {
     using SP = SmallPre<NX, NY>;
@@ -352,7 +364,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     for (int i = 0; i < NY; ++i) d[i] = a.d ? a.d[(size_t)ps * b * NY + i] : 0.0;
 
     const ConstLayout CL = const_layout(NX, NY);
-    double* out = a.consts64 + (size_t)b * a.cw;
+    DualOut out{a.consts64 + (size_t)b * a.cw, a.mixed ? a.consts32 + (size_t)b * a.cw : nullptr};
     bool ok = true;
     if (a.what & 1) {
         double T1[nm], S[m2], Lc[m2], Kt[nm], G[nm], Z[nm], X[n2], e[NY], v[NX];
@@ -367,37 +379,42 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         SP::template solve<NY, NX>(Lc, Kt);                           // K^T = S^-1 H Q
         SP::template mm<NY, NX, NX, false, false>(G, H, F);           // H F
 #pragma unroll
-        for (int i = 0; i < nm; ++i) Z[i] = G[i];
+        for (int i = 0; i < nm; ++i) {
+            Z[i] = G[i];
+            out.put(CL.G + i, G[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < m2; ++i) out.put(CL.S + i, S[i]);
         SP::template solve<NY, NX>(Lc, Z);                            // S^-1 H F
 #pragma unroll
         for (int i = 0; i < NY; ++i)
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
-                out[CL.K + j * NY + i] = Kt[i * NX + j];
-                out[CL.W + j * NY + i] = Z[i * NX + j];
+                out.put(CL.K + j * NY + i, Kt[i * NX + j]);
+                out.put(CL.W + j * NY + i, Z[i * NX + j]);
             }
         SP::template mm<NX, NY, NX, true, false>(X, G, Z);           // F^T H^T S^-1 H F
         SP::template sym<NX>(X);
 #pragma unroll
-        for (int i = 0; i < n2; ++i) out[CL.J + i] = X[i];
+        for (int i = 0; i < n2; ++i) out.put(CL.J + i, X[i]);
         SP::template mm<NX, NY, NX, true, false>(X, Kt, G);          // K H F
 #pragma unroll
-        for (int i = 0; i < n2; ++i) out[CL.A + i] = F[i] - X[i];
+        for (int i = 0; i < n2; ++i) out.put(CL.A + i, F[i] - X[i]);
         SP::template mm<NX, NY, NX, true, false>(X, Kt, T1);         // K H Q
 #pragma unroll
         for (int i = 0; i < n2; ++i) X[i] = Q[i] - X[i];
         SP::template sym<NX>(X);
 #pragma unroll
-        for (int i = 0; i < n2; ++i) out[CL.C + i] = X[i];
+        for (int i = 0; i < n2; ++i) out.put(CL.C + i, X[i]);
         SP::template mm<NY, NX, 1, false, false>(e, H, u);           // H u + d
 #pragma unroll
         for (int i = 0; i < NY; ++i) e[i] += d[i];
         SP::template mm<NX, NY, 1, true, false>(v, Kt, e);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out[CL.c + i] = u[i] - v[i];
+        for (int i = 0; i < NX; ++i) out.put(CL.c + i, u[i] - v[i]);
         SP::template mm<NX, NY, 1, true, false>(v, Z, e);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out[CL.w + i] = -v[i];
+        for (int i = 0; i < NX; ++i) out.put(CL.w + i, -v[i]);
         // k = 1
         double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm];
         SP::template mm<NX, NX, 1, false, false>(m1, F, m0);
@@ -420,38 +437,35 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
 #pragma unroll
         for (int i = 0; i < NY; ++i)
 #pragma unroll
-            for (int j = 0; j < NX; ++j) out[CL.K1 + j * NY + i] = K1t[i * NX + j];
+            for (int j = 0; j < NX; ++j) out.put(CL.K1 + j * NY + i, K1t[i * NX + j]);
         SP::template mm<NY, NX, 1, false, false>(e1, H, m1);
 #pragma unroll
         for (int i = 0; i < NY; ++i) e1[i] += d[i];
         SP::template mm<NX, NY, 1, true, false>(v, K1t, e1);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out[CL.c1 + i] = m1[i] - v[i];
+        for (int i = 0; i < NX; ++i) out.put(CL.c1 + i, m1[i] - v[i]);
         SP::template mm<NX, NY, NY, true, false>(U, K1t, S1);        // K1 S1
         SP::template mm<NX, NY, NX, false, false>(X, U, K1t);        // K1 S1 K1^T
 #pragma unroll
         for (int i = 0; i < n2; ++i) X[i] = P1[i] - X[i];
         SP::template sym<NX>(X);
 #pragma unroll
-        for (int i = 0; i < n2; ++i) out[CL.C1 + i] = X[i];
+        for (int i = 0; i < n2; ++i) out.put(CL.C1 + i, X[i]);
         a.model_fail[b] = ok ? 0 : 1;
     }
     if (a.what & 2) {
 #pragma unroll
         for (int i = 0; i < n2; ++i) {
-            out[CL.F + i] = F[i];
-            out[CL.Q + i] = Q[i];
+            out.put(CL.F + i, F[i]);
+            out.put(CL.Q + i, Q[i]);
         }
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out[CL.u + i] = u[i];
+        for (int i = 0; i < NX; ++i) out.put(CL.u + i, u[i]);
     }
-    const int lo = (a.what & 1) ? 0 : CL.F;
-    const int hi = (a.what & 2) ? CL.words : CL.F;
-    if (!ok)
-        for (int i = lo; i < hi; ++i) out[i] = __builtin_nan("");
-    if (a.mixed) {
-        float* o32 = a.consts32 + (size_t)b * a.cw;
-        for (int i = lo; i < hi; ++i) o32[i] = (float)out[i];
+    if (!ok) {
+        const int lo = (a.what & 1) ? 0 : CL.F;
+        const int hi = (a.what & 2) ? CL.words : CL.F;
+        for (int i = lo; i < hi; ++i) out.put(i, __builtin_nan(""));
     }
 }
 

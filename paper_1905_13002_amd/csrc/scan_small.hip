@@ -24,13 +24,18 @@ hipError_t dispatch_n(ScanArgs a, bool smoother, hipStream_t s) {
 
 bool small_supported(int nx) { return nx >= 1 && nx <= 4; }
 
+// Defaults measured on MI355X (constant-velocity model, T = 2^20): FP64 is
+// fastest with 16 steps per thread and one scan level, the mixed mode with 8
+// steps per thread and a second level of one aggregate per thread.  Very long
+// inputs always get the second level so the single-workgroup top scan stays
+// short.  pks_autotune overrides these per problem shape.
 TileConfig small_default_config(int nx, int64_t total, bool mixed) {
     (void)nx;
-    (void)mixed;
     TileConfig c;
-    c.ept = 8;
+    c.ept = mixed ? 8 : 16;
     const int64_t waves = (total + 64 * c.ept - 1) / (64 * c.ept);
-    c.ept1 = waves > 4096 ? 8 : 0;
+    if (mixed) c.ept1 = waves > 256 ? 1 : 0;
+    else c.ept1 = waves > 2048 ? (waves > 64 * 1024 ? 2 : 1) : 0;
     return c;
 }
 

@@ -229,8 +229,7 @@ __device__ __forceinline__ void wave_inclusive_f(FElem<N, R>& incl, int lane) {
     for (int d = 1; d < 64; d <<= 1) {
         FElem<N, R> o = incl;
         shfl_up_words<Words<N>::F>(reinterpret_cast<R*>(&o), d);
-        if (lane < d) set_identity(o);
-        fcombine<N, R, G>(o, incl, incl);
+        if (lane >= d) fcombine<N, R, G>(o, incl, incl);
     }
 }
 template <int N, typename R>
@@ -245,8 +244,7 @@ __device__ __forceinline__ void wave_inclusive_suffix_s(SElem<N, R>& incl, int l
     for (int d = 1; d < 64; d <<= 1) {
         SElem<N, R> o = incl;
         shfl_down_words<Words<N>::S>(reinterpret_cast<R*>(&o), d);
-        if (lane + d >= 64) set_identity(o);
-        scombine<N, R, G>(incl, o, incl);
+        if (lane + d < 64) scombine<N, R, G>(incl, o, incl);
     }
 }
 template <int N, typename R>
@@ -259,8 +257,16 @@ __device__ __forceinline__ void wave_exclusive_suffix_s(const SElem<N, R>& incl,
 // ===========================================================================
 // FILTER
 // ===========================================================================
-// reduce over steps (elements built from y)
-template <int N, typename R, int EPT, bool SEG>
+// load G = H F (zero for a sequence's first step, whose J is 0)
+template <int N, int M, typename R>
+__device__ __forceinline__ void load_gz(const R* __restrict__ cst, const ConstLayout& CL, bool first, R (&Gz)[M * N]) {
+#pragma unroll
+    for (int i = 0; i < M * N; ++i) Gz[i] = first ? R(0) : cst[CL.G + i];
+}
+
+// reduce over steps (elements built from y).  M = ny when ny < nx: the
+// single-step elements are folded with the rank-ny form of Lemma 2.
+template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -276,11 +282,21 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
             const int64_t k = k0 + e;
             if (k < a.total) {
                 seq_forward<SEG>(a, s, k);
-                const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+                const int64_t moff = SEG ? s.b * a.model_stride : 0;
+                const R* cst = static_cast<const R*>(a.consts) + moff;
+                const bool first = k == s.start;
                 FElem<N, R> x;
-                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, k == s.start, x);
-                if (e == 0) acc = x;
-                else fcombine<N, R, SEG>(acc, x, acc);
+                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+                if (e == 0) {
+                    acc = x;
+                } else if (M == 0) {
+                    fcombine<N, R, SEG>(acc, x, acc);
+                } else {
+                    constexpr int MM = M > 0 ? M : 1;
+                    R Gz[MM * N];
+                    load_gz<N, MM, R>(cst, CL, first, Gz);
+                    fcombine_fresh<N, MM, R, SEG>(acc, x, Gz, cst + CL.W, a.consts64 + moff + CL.S);
+                }
             }
         }
     }
@@ -398,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_items(ScanArgs a) {
 }
 
 // level-0 down: outputs m_k, P_k
-template <int N, typename R, int EPT, bool SEG>
+template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t k0 = gt * EPT;
@@ -420,10 +436,19 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         const int64_t k = k0 + e;
         if (k < a.total) {
             seq_forward<SEG>(a, s, k);
-            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            const int64_t moff = SEG ? s.b * a.model_stride : 0;
+            const R* cst = static_cast<const R*>(a.consts) + moff;
+            const bool first = k == s.start;
             FElem<N, R> x;
-            build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, k == s.start, x);
-            fcarry<N, R, SEG>(X, x);
+            build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+            if (M == 0) {
+                fcarry<N, R, SEG>(X, x);
+            } else {
+                constexpr int MM = M > 0 ? M : 1;
+                R Gz[MM * N];
+                load_gz<N, MM, R>(cst, CL, first, Gz);
+                fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
+            }
             store_moments_step(mo, Po, k, X);
         }
     }
@@ -635,11 +660,11 @@ void launch_smoother_top(const void* items, int64_t n, void* carry, hipStream_t 
         default: return hipErrorInvalidValue;                                                          \
     }
 
-template <int N, typename R, int EPT, bool SEG>
+template <int N, typename R, int EPT, bool SEG, int M>
 hipError_t run_filter(ScanArgs a, hipStream_t s) {
     const int64_t nb0 = a.nthr / kBlock;
     prof_begin("k_filter_reduce", s);
-    hipLaunchKernelGGL((k_filter_reduce<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_filter_reduce<N, R, EPT, SEG, M>), dim3(nb0), dim3(kBlock), 0, s, a);
     prof_end(s);
     if (a.nwaves1 == 0) {
         launch_filter_top<N, R, SEG>(a.agg, a.nwaves, a.carry, a, s);
@@ -654,7 +679,7 @@ hipError_t run_filter(ScanArgs a, hipStream_t s) {
         prof_end(s);
     }
     prof_begin("k_filter_down", s);
-    hipLaunchKernelGGL((k_filter_down<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_filter_down<N, R, EPT, SEG, M>), dim3(nb0), dim3(kBlock), 0, s, a);
     prof_end(s);
     return hipGetLastError();
 }
@@ -684,12 +709,24 @@ hipError_t run_smoother(ScanArgs a, hipStream_t s) {
 }
 #undef PKS_EPT1_SWITCH
 
+// rank-ny single-step combines when ny < nx (M = ny), the general form otherwise
+template <int N, typename R, int EPT, bool SEG>
+hipError_t run_filter_m(ScanArgs a, hipStream_t s) {
+    if (a.ny >= N || EPT < 8) return run_filter<N, R, EPT, SEG, 0>(a, s);
+    switch (a.ny) {
+        case 1: return run_filter<N, R, EPT, SEG, 1>(a, s);
+        case 2: return run_filter<N, R, EPT, SEG, (N > 2 ? 2 : 0)>(a, s);
+        case 3: return run_filter<N, R, EPT, SEG, (N > 3 ? 3 : 0)>(a, s);
+        default: return run_filter<N, R, EPT, SEG, 0>(a, s);
+    }
+}
+
 template <int N, typename R, bool SEG>
 hipError_t dispatch_ept(ScanArgs a, bool smoother, hipStream_t s) {
     switch (a.ept) {
-        case 4: return smoother ? run_smoother<N, R, 4, SEG>(a, s) : run_filter<N, R, 4, SEG>(a, s);
-        case 8: return smoother ? run_smoother<N, R, 8, SEG>(a, s) : run_filter<N, R, 8, SEG>(a, s);
-        case 16: return smoother ? run_smoother<N, R, 16, SEG>(a, s) : run_filter<N, R, 16, SEG>(a, s);
+        case 4: return smoother ? run_smoother<N, R, 4, SEG>(a, s) : run_filter_m<N, R, 4, SEG>(a, s);
+        case 8: return smoother ? run_smoother<N, R, 8, SEG>(a, s) : run_filter_m<N, R, 8, SEG>(a, s);
+        case 16: return smoother ? run_smoother<N, R, 16, SEG>(a, s) : run_filter_m<N, R, 16, SEG>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

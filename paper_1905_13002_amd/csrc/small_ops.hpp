@@ -65,11 +65,22 @@ template <int N, typename R> __device__ __forceinline__ void set_zero(Moments<N,
     for (int i = 0; i < tri(N); ++i) x.P[i] = R(0);
 }
 
+// Reciprocal in double: hardware estimate refined by two Newton steps
+// (r <- r + r (1 - x r)), accurate to about one unit in the last place.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // ---------------------------------------------------------------------------
 // LU solve with partial pivoting, in double:  X <- M^-1 X  for W right-hand
 // sides.  a[r][0..N) holds M, a[r][N..N+W) the right-hand sides.  Pivot rows
 // are chosen by a running comparison (row k ends up holding the largest
-// |a[.][k]|), rows are exchanged with selects so every index stays static.
+// |a[.][k]|), rows are exchanged with selects so every index stays static;
+// the exchange is skipped when no lane of the wave needs it.
 // ---------------------------------------------------------------------------
 template <int N, int W>
 __device__ __forceinline__ void lu_solve_inplace(double (&a)[N][N + W]) {
@@ -78,14 +89,16 @@ __device__ __forceinline__ void lu_solve_inplace(double (&a)[N][N + W]) {
 #pragma unroll
         for (int r = k + 1; r < N; ++r) {
             const bool sw = fabs(a[r][k]) > fabs(a[k][k]);
+            if (__any(sw)) {
 #pragma unroll
-            for (int c = k; c < N + W; ++c) {
-                const double t = a[k][c];
-                a[k][c] = sw ? a[r][c] : t;
-                a[r][c] = sw ? t : a[r][c];
+                for (int c = k; c < N + W; ++c) {
+                    const double t = a[k][c];
+                    a[k][c] = sw ? a[r][c] : t;
+                    a[r][c] = sw ? t : a[r][c];
+                }
             }
         }
-        const double inv = 1.0 / a[k][k];
+        const double inv = rcp64(a[k][k]);
         a[k][k] = inv;
 #pragma unroll
         for (int r = k + 1; r < N; ++r) {
@@ -470,7 +483,7 @@ __device__ __forceinline__ bool build_selem(const R* __restrict__ F, const R* __
         for (int l = 0; l < j; ++l) dj = fma(-S[sidx(j, l)], S[sidx(j, l)], dj);
         ok = ok && (dj > 0.0);
         const double sq = sqrt(dj);
-        dinv[j] = 1.0 / sq;
+        dinv[j] = rcp64(sq);
         S[sidx(j, j)] = sq;
 #pragma unroll
         for (int i = j + 1; i < N; ++i) {
@@ -541,6 +554,360 @@ __device__ __forceinline__ bool build_selem(const R* __restrict__ F, const R* __
                 e.L[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - 0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])));
     }
     return ok;
+}
+
+}  // namespace pks
+
+namespace pks {
+
+// ---------------------------------------------------------------------------
+// Lemma 2 with a right operand that is a single step k > 1 of Lemma 1
+// ("fresh"): J_j = F^T H^T S^-1 H F = W G with G = H F (M x N, M = ny < N).
+// Then (I + C_i J_j)^-1 = I - Y Sigma^-1 G with Y = C_i G^T and
+// Sigma = S + G C_i G^T (symmetric positive definite, M x M), so the solve is
+// a Cholesky factorisation of Sigma (double) instead of an N x N LU.  The
+// result is the same operator; J_j enters only through W and G.
+// `ej` supplies A, b, C, eta of the step (its J is not read); `Gz` is G, or 0
+// for a sequence's first step (whose J is 0).  S is read in double.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void chol_small(double (&S)[M * M], double (&dinv)[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double d = S[j * M + j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) d = fma(-S[j * M + l], S[j * M + l], d);
+        const double r = sqrt(d);
+        dinv[j] = rcp64(r);
+        S[j * M + j] = r;
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double v = S[i * M + j];
+#pragma unroll
+            for (int l = 0; l < j; ++l) v = fma(-S[i * M + l], S[j * M + l], v);
+            S[i * M + j] = v * dinv[j];
+        }
+    }
+}
+// x <- (L L^T)^-1 x, L lower (strictly lower part of S), dinv = 1 / diag(L)
+template <int M>
+__device__ __forceinline__ void chol_solve_vec(const double (&L)[M * M], const double (&dinv)[M], double (&x)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double s = x[i];
+#pragma unroll
+        for (int l = 0; l < i; ++l) s = fma(-L[i * M + l], x[l], s);
+        x[i] = s * dinv[i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        double s = x[i];
+#pragma unroll
+        for (int l = i + 1; l < M; ++l) s = fma(-L[l * M + i], x[l], s);
+        x[i] = s * dinv[i];
+    }
+}
+
+// Sigma = S + G Y (double), factorised in place
+template <int N, int M, typename R>
+__device__ __forceinline__ void make_sigma(const double* __restrict__ S, const R (&Gz)[M * N], const R (&Y)[N * M],
+                                           double (&Sg)[M * M], double (&dinv)[M]) {
+#pragma unroll
+    for (int r = 0; r < M; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            R q = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) q = fma(Gz[r * N + l], Y[l * M + c], q);
+            Sg[r * M + c] = double(S[r * M + c]) + double(q);
+            Sg[c * M + r] = Sg[r * M + c];
+        }
+    chol_small<M>(Sg, dinv);
+}
+
+template <int N, int M, typename R, bool G>
+__device__ __forceinline__ void fcombine_fresh(FElem<N, R>& ei, const FElem<N, R>& ej, const R (&Gz)[M * N],
+                                               const R* __restrict__ Wm, const double* __restrict__ S) {
+    // Y = C_i G^T   [N x M]
+    R Y[N * M];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            R q = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) q = fma(ei.C[sidx(r, l)], Gz[c * N + l], q);
+            Y[r * M + c] = q;
+        }
+    double Sg[M * M], dinv[M];
+    make_sigma<N, M, R>(S, Gz, Y, Sg, dinv);
+    // v = b_i + C_i eta_j ; Gv = G v ; Gb = G b_i ; GA = G A_i
+    R v[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = ei.b[r];
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(ei.C[sidx(r, l)], ej.eta[l], q);
+        v[r] = q;
+    }
+    R Gb[M], GA[M * N];
+    double t2[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        R q = R(0), qb = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            q = fma(Gz[r * N + l], v[l], q);
+            qb = fma(Gz[r * N + l], ei.b[l], qb);
+        }
+        t2[r] = double(q);
+        Gb[r] = qb;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R a = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) a = fma(Gz[r * N + l], ei.A[l * N + c], a);
+            GA[r * N + c] = a;
+        }
+    }
+    chol_solve_vec<M>(Sg, dinv, t2);
+    // T1 = Sigma^-1 GA, Zt = Sigma^-1 Y^T (column by column, double)
+    R T1[M * N], Zt[M * N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        double x[M], z[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            x[r] = double(GA[r * N + c]);
+            z[r] = double(Y[c * M + r]);
+        }
+        chol_solve_vec<M>(Sg, dinv, x);
+        chol_solve_vec<M>(Sg, dinv, z);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            T1[r * N + c] = R(x[r]);
+            Zt[r * N + c] = R(z[r]);
+        }
+    }
+    // X1 = A_i - Y T1 ; x2 = v - Y t2 ; X3 = sym(C_i - Y Zt)
+    R X1[N * N], x2[N], X3[tri(N)];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = v[r];
+#pragma unroll
+        for (int l = 0; l < M; ++l) q = fma(-Y[r * M + l], R(t2[l]), q);
+        x2[r] = q;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R a = ei.A[r * N + c];
+#pragma unroll
+            for (int l = 0; l < M; ++l) a = fma(-Y[r * M + l], T1[l * N + c], a);
+            X1[r * N + c] = a;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            R p = R(0), q = R(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                p = fma(Y[r * M + l], Zt[l * N + c], p);
+                q = fma(Y[c * M + l], Zt[l * N + r], q);
+            }
+            X3[sidx(r, c)] = R(double(ei.C[sidx(r, c)]) - 0.5 * (double(p) + double(q)));
+        }
+    // J_j b_i = W Gb ; J_j A_i = W GA
+    R w[N], JA[N * N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = ej.eta[r];
+#pragma unroll
+        for (int l = 0; l < M; ++l) q = fma(-Wm[r * M + l], Gb[l], q);
+        w[r] = q;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R a = R(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) a = fma(Wm[r * M + l], GA[l * N + c], a);
+            JA[r * N + c] = a;
+        }
+    }
+    FElem<N, R> t;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = ei.eta[r];
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(X1[l * N + r], w[l], q);
+        t.eta[r] = q;
+    }
+    {
+        R Z[N * N];
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                R q = R(0);
+#pragma unroll
+                for (int l = 0; l < N; ++l) q = fma(X1[l * N + r], JA[l * N + c], q);
+                Z[r * N + c] = q;
+            }
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c)
+                t.J[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ei.J[sidx(r, c)]));
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = ej.b[r];
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], x2[l], q);
+        t.b[r] = q;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R a = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) a = fma(ej.A[r * N + l], X1[l * N + c], a);
+            t.A[r * N + c] = a;
+        }
+    }
+    {
+        R Yj[N * N];   // A_j X3
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                R q = R(0);
+#pragma unroll
+                for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[sidx(l, c)], q);
+                Yj[r * N + c] = q;
+            }
+        R Z[N * N];
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                R q = R(0);
+#pragma unroll
+                for (int l = 0; l < N; ++l) q = fma(Yj[r * N + l], ej.A[c * N + l], q);
+                Z[r * N + c] = q;
+            }
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c)
+                t.C[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
+    }
+    if (G && all_zero<N, R>(ej.A)) {
+#pragma unroll
+        for (int i = 0; i < N * N; ++i) t.A[i] = R(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) t.b[i] = ej.b[i];
+#pragma unroll
+        for (int i = 0; i < tri(N); ++i) t.C[i] = ej.C[i];
+    }
+    ei = t;
+}
+
+// x <- x (x) j for a prefix x with A = 0 and a single step j: the Kalman
+// update with "measurement" G and noise S, then A_j, b_j, C_j.
+template <int N, int M, typename R, bool G>
+__device__ __forceinline__ void fcarry_fresh(Moments<N, R>& x, const FElem<N, R>& ej, const R (&Gz)[M * N],
+                                             const double* __restrict__ S) {
+    const bool pass = G && all_zero<N, R>(ej.A);
+    R Y[N * M];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            R q = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) q = fma(x.P[sidx(r, l)], Gz[c * N + l], q);
+            Y[r * M + c] = q;
+        }
+    double Sg[M * M], dinv[M];
+    make_sigma<N, M, R>(S, Gz, Y, Sg, dinv);
+    R v[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = x.m[r];
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(x.P[sidx(r, l)], ej.eta[l], q);
+        v[r] = q;
+    }
+    double t2[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        R q = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(Gz[r * N + l], v[l], q);
+        t2[r] = double(q);
+    }
+    chol_solve_vec<M>(Sg, dinv, t2);
+    R Zt[M * N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        double z[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) z[r] = double(Y[c * M + r]);
+        chol_solve_vec<M>(Sg, dinv, z);
+#pragma unroll
+        for (int r = 0; r < M; ++r) Zt[r * N + c] = R(z[r]);
+    }
+    R x2[N], X3[tri(N)];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = v[r];
+#pragma unroll
+        for (int l = 0; l < M; ++l) q = fma(-Y[r * M + l], R(t2[l]), q);
+        x2[r] = q;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            R p = R(0), q = R(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                p = fma(Y[r * M + l], Zt[l * N + c], p);
+                q = fma(Y[c * M + l], Zt[l * N + r], q);
+            }
+            X3[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - 0.5 * (double(p) + double(q)));
+        }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        R q = ej.b[r];
+#pragma unroll
+        for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], x2[l], q);
+        x.m[r] = pass ? ej.b[r] : q;
+    }
+    R Yj[N * N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R q = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[sidx(l, c)], q);
+            Yj[r * N + c] = q;
+        }
+    R Z[N * N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            R q = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) q = fma(Yj[r * N + l], ej.A[c * N + l], q);
+            Z[r * N + c] = q;
+        }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c)
+            x.P[sidx(r, c)] = pass ? ej.C[sidx(r, c)]
+                                   : R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
 }
 
 }  // namespace pks
