@@ -85,7 +85,8 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     const int64_t thr0 = waves0 * 64;
     const int64_t waves1 = round_up(std::max<int64_t>(1, ceil_div(waves0, 64)), 4);   // >= 1 item per thread
     const int64_t thr1 = waves1 * 64;
-    const int fw = felem_words(nx), mw = moment_words(nx);
+    const bool small = small_supported(nx);
+    const int fw = small ? felem_words(nx) : 0, mw = small ? moment_words(nx) : 0;
     L.cap_thr = thr0;
     L.cap_waves = waves0;
     L.cap_thr1 = thr1;
@@ -97,6 +98,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.agg1 = o; o = align256(o + rs * fw * (size_t)waves1);
     L.carry1 = o; o = align256(o + rs * mw * (size_t)waves1);
     L.large = o;
+    if (!small) o = align256(o + large_ws_bytes(nx, ny, total, prec));
     L.total = o;
     return L;
 }
@@ -146,9 +148,8 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     if (ws_bytes < L.total)
         return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
                     ws_bytes, L.total);
-    if (!small_supported(model.nx))
-        return fail(PKS_E_UNSUPPORTED, "nx = %d is not supported by this build", model.nx);
     if (total == 0) return PKS_OK;
+    const bool small = small_supported(model.nx);
     const bool mixed = prec == PKS_MIXED_FP32;
     TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
     if (cfg.ept < kMinEpt) cfg.ept = kMinEpt;
@@ -161,6 +162,18 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     a.P = P;
     a.ms = ms;
     a.Ps = Ps;
+    if (!small) {
+        void* region = static_cast<char*>(ws) + L.large;
+        if (passes & 1) {
+            e = launch_large(a, region, mixed, false, s);
+            if (e != hipSuccess) return hip_fail(e, "filter kernels");
+        }
+        if (passes & 2) {
+            e = launch_large(a, region, mixed, true, s);
+            if (e != hipSuccess) return hip_fail(e, "smoother kernels");
+        }
+        return PKS_OK;
+    }
     if (a.nthr > L.cap_thr || a.nwaves > L.cap_waves || a.nthr1 > L.cap_thr1 || a.nwaves1 > L.cap_waves1)
         return fail(PKS_E_ARG, "tile configuration (ept %d, ept1 %d) does not fit the workspace", cfg.ept, cfg.ept1);
     if (passes & 1) {

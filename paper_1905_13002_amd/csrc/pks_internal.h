@@ -38,11 +38,12 @@ __host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
     L.K1 = o; o += nm;
     L.c1 = o; o += nx;
     L.C1 = o; o += n2;
+    L.G = o; o += nm;        // H F         [ny][nx]  (J = W G: the rank-ny factors of J)
+    L.S = o; o += ny * ny;   // H Q H^T + R [ny][ny]
+    // smoother constants last: a filter-only precompute writes [0, F)
     L.F = o; o += n2;
     L.Q = o; o += n2;
     L.u = o; o += nx;
-    L.G = o; o += nm;    // H F      [ny][nx]  (J = W G: the rank-ny factors of J)
-    L.S = o; o += ny * ny;  // H Q H^T + R [ny][ny]
     L.words = (o + 15) & ~15;
     return L;
 }
@@ -130,5 +131,9 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
 hipError_t launch_small_filter(ScanArgs a, bool mixed, hipStream_t s);
 hipError_t launch_small_smoother(ScanArgs a, bool mixed, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
+
+// large-state path (scan_large.hip), 5 <= nx <= 64
+size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);
+hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
 
 }  // namespace pks

@@ -225,7 +225,7 @@ __device__ __forceinline__ void make_selem(const R* __restrict__ cst, const Cons
 // ---------------------------------------------------------------------------
 template <int N, typename R, bool G>
 __device__ __forceinline__ void wave_inclusive_f(FElem<N, R>& incl, int lane) {
-#pragma unroll
+#pragma unroll 1
     for (int d = 1; d < 64; d <<= 1) {
         FElem<N, R> o = incl;
         shfl_up_words<Words<N>::F>(reinterpret_cast<R*>(&o), d);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void wave_exclusive_from_inclusive_f(const FElem<N, R
 }
 template <int N, typename R, bool G>
 __device__ __forceinline__ void wave_inclusive_suffix_s(SElem<N, R>& incl, int lane) {
-#pragma unroll
+#pragma unroll 1
     for (int d = 1; d < 64; d <<= 1) {
         SElem<N, R> o = incl;
         shfl_down_words<Words<N>::S>(reinterpret_cast<R*>(&o), d);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
     set_identity(acc);
     if (k0 < a.total) {
         Seq s = seq_find<SEG>(a, k0);
-#pragma unroll
+#pragma unroll 1
         for (int e = 0; e < EPT; ++e) {
             const int64_t k = k0 + e;
             if (k < a.total) {
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce_items(ScanArgs a) {
     const int64_t i0 = gt * EPT;
     FElem<N, R> acc;
     set_identity(acc);
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t i = i0 + e;
         if (i < a.nwaves) {
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_items(ScanArgs a) {
     FElem<N, R> pre;
     load_f(a.thr1, a.nthr1, gt, pre);
     fcarry<N, R, G>(X, pre);
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t i = i0 + e;
         if (i < a.nwaves) {
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         fcarry<N, R, SEG>(X, pre);
     }
     Seq s = seq_find<SEG>(a, k0);
-#pragma unroll
+#pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t k = k0 + e;
         if (k < a.total) {
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
     if (k0 < a.total) {
         const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
         Seq s = seq_find<SEG>(a, klast);
-#pragma unroll
+#pragma unroll 1
         for (int e = EPT - 1; e >= 0; --e) {
             const int64_t k = k0 + e;
             if (k < a.total) {
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce_items(ScanArgs a) {
     const int64_t i0 = gt * EPT;
     SElem<N, R> acc;
     set_identity(acc);
-#pragma unroll
+#pragma unroll 1
     for (int e = EPT - 1; e >= 0; --e) {
         const int64_t i = i0 + e;
         if (i < a.nwaves) {
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down_items(ScanArgs a) {
     SElem<N, R> pre;
     load_s(a.thr1, a.nthr1, gt, pre);
     scarry<N, R, G>(pre, Y);
-#pragma unroll
+#pragma unroll 1
     for (int e = EPT - 1; e >= 0; --e) {
         const int64_t i = i0 + e;
         if (i < a.nwaves) {
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
     }
     const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
     Seq s = seq_find<SEG>(a, klast);
-#pragma unroll
+#pragma unroll 1
     for (int e = EPT - 1; e >= 0; --e) {
         const int64_t k = k0 + e;
         if (k < a.total) {

@@ -282,3 +282,52 @@ def test_batched_B4096_sampled(pks):
             s = w.seq(b)
             ref = oracle_run(w.model_of(b), ref_input(w.y[s], precision))
             assert_parity({k: v[s] for k, v in out.items()}, ref, precision, "B4096 seq %d" % b)
+
+
+# ---------------------------------------------------------------------------
+# large state dimensions (workgroup per block element)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,T", [(5, 2, 777), (6, 6, 500), (8, 3, 1025), (8, 9, 300), (16, 8, 2000),
+                                     (12, 12, 257)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_random_models(pks, nx, ny, T, precision):
+    rng = np.random.default_rng(900 + 7 * nx + ny)
+    model = wl.random_stable_model(nx, ny, rng, radius=0.97, with_offsets=True)
+    w = wl.single_sequence(model, T, seed=nx + 100 * ny)
+    check(pks, model, w.y, precision, "large nx=%d ny=%d T=%d" % (nx, ny, T),
+          floor="rms" if precision == "mixed" else "none")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workload3_reduced(pks, precision):
+    w = wl.workload(3, T=4096)
+    check(pks, w.model, w.y, precision, "nx16 T=4096")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workload5_reduced(pks, precision):
+    w = wl.workload(5, B=3, T=200)
+    ref = oracle_run(w.model, ref_input(w.y, precision), w.offsets)
+    out = gpu_run(pks, w.model, w.y, precision, offsets=w.offsets)
+    assert_parity(out, ref, precision, "nx64 B=3 T=200")
+
+
+def test_large_batched_per_sequence(pks):
+    rng = np.random.default_rng(31)
+    models = [wl.random_stable_model(6, 3, np.random.default_rng(40 + b), radius=0.95, with_offsets=True)
+              for b in range(5)]
+    lengths = [1, 37, 0, 120, 64]
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 3)) for mo, L in zip(models, lengths)]
+    y = np.concatenate(ys)
+    stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+    model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), stack("u"), stack("d"))
+    ref = oracle_run(model, y, offsets, per_sequence=True)
+    out = gpu_run(pks, model, y, "fp64", offsets=offsets, per_sequence=True)
+    assert_parity(out, ref, "fp64", "large batched per-sequence")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workload3_full(pks, precision):
+    w = wl.workload(3)
+    check(pks, w.model, w.y, precision, "nx16 T=65536")
