@@ -219,6 +219,109 @@ __device__ __forceinline__ void make_selem(const R* __restrict__ cst, const Cons
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Wave-cooperative moment transfers.  Lane l of a wave handles step
+// kbase + l * stride; a direct per-lane access of its moments would touch a
+// different cache line in every lane of every memory instruction.  Instead the
+// 64 records pass through an LDS slice of the wave and are moved with
+// consecutive lanes on consecutive units of the same record, so a memory
+// instruction covers a few whole records.
+// ---------------------------------------------------------------------------
+template <int Bytes> struct UnitT;
+template <> struct UnitT<16> { using T = uint4; };
+template <> struct UnitT<8> { using T = uint2; };
+template <> struct UnitT<4> { using T = unsigned int; };
+
+template <int N, typename R>
+struct MomStage {
+    static constexpr int WM = N, WP = N * N;                         // words of m and of P
+    static constexpr int UBP = (WP * sizeof(R)) % 16 == 0 ? 16 : ((WP * sizeof(R)) % 8 == 0 ? 8 : 4);
+    static constexpr int UBM = (WM * sizeof(R)) % 16 == 0 ? 16 : ((WM * sizeof(R)) % 8 == 0 ? 8 : 4);
+    static constexpr int UP = WP * (int)sizeof(R) / UBP;               // units per P record
+    static constexpr int UM = WM * (int)sizeof(R) / UBM;               // units per m record
+    static constexpr int ROW = WP + WM + (sizeof(R) == 8 ? 1 : 1);     // padded LDS row (words)
+    static constexpr int WORDS = 64 * ROW;                              // LDS words per wave
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// store x (this lane's moments, step kbase + lane * stride) to m [.][N], P [.][N][N]
+template <int N, typename R>
+__device__ __forceinline__ void wave_store_moments(R* __restrict__ m, R* __restrict__ P, int64_t kbase, int64_t stride,
+                                                   int64_t total, R* st, int lane, const Moments<N, R>& x) {
+    using S = MomStage<N, R>;
+    R* row = st + lane * S::ROW;
+#pragma unroll
+    for (int r = 0; r < N; ++r) row[r] = x.m[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) row[N + r * N + c] = x.P[sidx(r, c)];
+    wave_sync();
+    using UP_T = typename UnitT<S::UBP>::T;
+    using UM_T = typename UnitT<S::UBM>::T;
+#pragma unroll
+    for (int i = 0; i < S::UP; ++i) {
+        const int f = lane + 64 * i, l = f / S::UP, u = f % S::UP;
+        const int64_t k = kbase + (int64_t)l * stride;
+        if (k < total) {
+            UP_T v;
+            __builtin_memcpy(&v, reinterpret_cast<const char*>(st + l * S::ROW + N) + u * S::UBP, S::UBP);
+            reinterpret_cast<UP_T*>(P + k * S::WP)[u] = v;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S::UM; ++i) {
+        const int f = lane + 64 * i, l = f / S::UM, u = f % S::UM;
+        const int64_t k = kbase + (int64_t)l * stride;
+        if (k < total) {
+            UM_T v;
+            __builtin_memcpy(&v, reinterpret_cast<const char*>(st + l * S::ROW) + u * S::UBM, S::UBM);
+            reinterpret_cast<UM_T*>(m + k * S::WM)[u] = v;
+        }
+    }
+    wave_sync();
+}
+
+// load this lane's moments (step kbase + lane * stride; zeros beyond total)
+template <int N, typename R>
+__device__ __forceinline__ void wave_load_moments(const R* __restrict__ m, const R* __restrict__ P, int64_t kbase,
+                                                  int64_t stride, int64_t total, R* st, int lane, Moments<N, R>& x) {
+    using S = MomStage<N, R>;
+    using UP_T = typename UnitT<S::UBP>::T;
+    using UM_T = typename UnitT<S::UBM>::T;
+#pragma unroll
+    for (int i = 0; i < S::UP; ++i) {
+        const int f = lane + 64 * i, l = f / S::UP, u = f % S::UP;
+        const int64_t k = kbase + (int64_t)l * stride;
+        UP_T v{};
+        if (k < total) v = reinterpret_cast<const UP_T*>(P + k * S::WP)[u];
+        __builtin_memcpy(reinterpret_cast<char*>(st + l * S::ROW + N) + u * S::UBP, &v, S::UBP);
+    }
+#pragma unroll
+    for (int i = 0; i < S::UM; ++i) {
+        const int f = lane + 64 * i, l = f / S::UM, u = f % S::UM;
+        const int64_t k = kbase + (int64_t)l * stride;
+        UM_T v{};
+        if (k < total) v = reinterpret_cast<const UM_T*>(m + k * S::WM)[u];
+        __builtin_memcpy(reinterpret_cast<char*>(st + l * S::ROW) + u * S::UBM, &v, S::UBM);
+    }
+    wave_sync();
+    const R* row = st + lane * S::ROW;
+#pragma unroll
+    for (int r = 0; r < N; ++r) x.m[r] = row[r];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) x.P[sidx(r, c)] = row[N + r * N + c];
+    wave_sync();
+}
+
 // ---------------------------------------------------------------------------
 // wave-level scans (Kogge-Stone over shuffles).  Lanes without a partner take
 // the identity as the shuffled operand, so every lane runs the same combine.
@@ -416,9 +519,13 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_items(ScanArgs a) {
 // level-0 down: outputs m_k, P_k
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
+    __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
-    if (k0 >= a.total) return;
+    const int64_t kw = (gt - lane) * EPT;          // first step of the wave
+    if (kw >= a.total) return;                     // whole wave beyond the end
+    R* st = stage[threadIdx.x >> 6];
     const ConstLayout CL = const_layout(N, a.ny);
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
@@ -430,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         load_f(a.thr, a.nthr, gt, pre);
         fcarry<N, R, SEG>(X, pre);
     }
-    Seq s = seq_find<SEG>(a, k0);
+    Seq s = seq_find<SEG>(a, k0 < a.total ? k0 : a.total - 1);
 #pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t k = k0 + e;
@@ -449,8 +556,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
                 load_gz<N, MM, R>(cst, CL, first, Gz);
                 fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
             }
-            store_moments_step(mo, Po, k, X);
         }
+        wave_store_moments<N, R>(mo, Po, kw + e, EPT, a.total, st, lane, X);
     }
 }
 
@@ -470,19 +577,19 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
     if (k0 < a.total) {
         const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
         Seq s = seq_find<SEG>(a, klast);
+        // the loads of the next (earlier) step are issued before this step's work
+        Moments<N, R> xn;
+        load_moments_step(m, P, klast, xn);
 #pragma unroll 1
-        for (int e = EPT - 1; e >= 0; --e) {
-            const int64_t k = k0 + e;
-            if (k < a.total) {
-                seq_backward<SEG>(a, s, k);
-                const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
-                Moments<N, R> x;
-                load_moments_step(m, P, k, x);
-                SElem<N, R> el;
-                make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
-                if (k == klast) acc = el;
-                else scombine<N, R, SEG>(el, acc, acc);
-            }
+        for (int64_t k = klast; k >= k0; --k) {
+            const Moments<N, R> x = xn;
+            if (k > k0) load_moments_step(m, P, k - 1, xn);
+            seq_backward<SEG>(a, s, k);
+            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            SElem<N, R> el;
+            make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
+            if (k == klast) acc = el;
+            else scombine<N, R, SEG>(el, acc, acc);
         }
     }
     wave_inclusive_suffix_s<N, R, SEG>(acc, lane);
@@ -591,9 +698,13 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down_items(ScanArgs a) {
 
 template <int N, typename R, int EPT, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
+    __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
-    if (k0 >= a.total) return;
+    const int64_t kw = (gt - lane) * EPT;
+    if (kw >= a.total) return;
+    R* st = stage[threadIdx.x >> 6];
     const ConstLayout CL = const_layout(N, a.ny);
     const R* m = static_cast<const R*>(a.m);
     const R* P = static_cast<const R*>(a.P);
@@ -608,19 +719,21 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
     }
     const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
     Seq s = seq_find<SEG>(a, klast);
+    Moments<N, R> xn;
+    load_moments_step(m, P, klast, xn);
 #pragma unroll 1
     for (int e = EPT - 1; e >= 0; --e) {
         const int64_t k = k0 + e;
-        if (k < a.total) {
+        const Moments<N, R> x = xn;
+        if (k <= klast && k > k0) load_moments_step(m, P, k - 1, xn);
+        if (k <= klast) {
             seq_backward<SEG>(a, s, k);
             const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
-            Moments<N, R> x;
-            load_moments_step(m, P, k, x);
             SElem<N, R> el;
             make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
             scarry<N, R, SEG>(el, Y);
-            store_moments_step(mso, Pso, k, Y);
         }
+        wave_store_moments<N, R>(mso, Pso, kw + e, EPT, a.total, st, lane, Y);
     }
 }
 
