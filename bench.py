@@ -131,10 +131,11 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB once
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     w = wl.workload(args.workload)
