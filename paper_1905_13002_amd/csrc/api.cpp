@@ -176,14 +176,8 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     }
     if (a.nthr > L.cap_thr || a.nwaves > L.cap_waves || a.nthr1 > L.cap_thr1 || a.nwaves1 > L.cap_waves1)
         return fail(PKS_E_ARG, "tile configuration (ept %d, ept1 %d) does not fit the workspace", cfg.ept, cfg.ept1);
-    if (passes & 1) {
-        e = launch_small_filter(a, mixed, s);
-        if (e != hipSuccess) return hip_fail(e, "filter kernels");
-    }
-    if (passes & 2) {
-        e = launch_small_smoother(a, mixed, s);
-        if (e != hipSuccess) return hip_fail(e, "smoother kernels");
-    }
+    e = launch_small(a, mixed, passes, s);
+    if (e != hipSuccess) return hip_fail(e, "scan kernels");
     return PKS_OK;
 }
 

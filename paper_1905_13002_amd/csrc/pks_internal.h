@@ -128,8 +128,8 @@ bool small_supported(int nx);
 // (cleared when `reset`, or when the workspace was never prepared).
 hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model,
                              void* ws, const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s);
-hipError_t launch_small_filter(ScanArgs a, bool mixed, hipStream_t s);
-hipError_t launch_small_smoother(ScanArgs a, bool mixed, hipStream_t s);
+// passes: 1 = filter, 2 = smoother, 3 = both (fused where possible)
+hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
 
 // large-state path (scan_large.hip), 5 <= nx <= 64

@@ -5,17 +5,17 @@
 namespace pks {
 
 template <int N, typename R>
-hipError_t small_run(ScanArgs a, bool smoother, hipStream_t s);
+hipError_t small_run(ScanArgs a, int passes, hipStream_t s);
 
 namespace {
 
 template <typename R>
-hipError_t dispatch_n(ScanArgs a, bool smoother, hipStream_t s) {
+hipError_t dispatch_n(ScanArgs a, int passes, hipStream_t s) {
     switch (a.nx) {
-        case 1: return small_run<1, R>(a, smoother, s);
-        case 2: return small_run<2, R>(a, smoother, s);
-        case 3: return small_run<3, R>(a, smoother, s);
-        case 4: return small_run<4, R>(a, smoother, s);
+        case 1: return small_run<1, R>(a, passes, s);
+        case 2: return small_run<2, R>(a, passes, s);
+        case 3: return small_run<3, R>(a, passes, s);
+        case 4: return small_run<4, R>(a, passes, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -39,11 +39,8 @@ TileConfig small_default_config(int nx, int64_t total, bool mixed) {
     return c;
 }
 
-hipError_t launch_small_filter(ScanArgs a, bool mixed, hipStream_t s) {
-    return mixed ? dispatch_n<float>(a, false, s) : dispatch_n<double>(a, false, s);
-}
-hipError_t launch_small_smoother(ScanArgs a, bool mixed, hipStream_t s) {
-    return mixed ? dispatch_n<float>(a, true, s) : dispatch_n<double>(a, true, s);
+hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s) {
+    return mixed ? dispatch_n<float>(a, passes, s) : dispatch_n<double>(a, passes, s);
 }
 
 }  // namespace pks

@@ -236,12 +236,24 @@ template <> struct UnitT<4> { using T = unsigned int; };
 template <int N, typename R>
 struct MomStage {
     static constexpr int WM = N, WP = N * N;                         // words of m and of P
+    static constexpr int BM = WM * (int)sizeof(R), BP = WP * (int)sizeof(R);
+    // consecutive steps of one lane buffered before a write, so that a lane's
+    // run of records fills whole 128-byte lines when the record divides 128.
+    // FP64 means are written step by step: on gfx950 the grouped form measured
+    // slower there (the larger stage costs more than the partial lines).
+    static constexpr int GM = (sizeof(R) == 8) ? 1 : ((128 % BM == 0 && BM < 128) ? 128 / BM : 1);
+    static constexpr int GP = (128 % BP == 0 && BP < 128) ? 128 / BP : 1;
     static constexpr int UBP = (WP * sizeof(R)) % 16 == 0 ? 16 : ((WP * sizeof(R)) % 8 == 0 ? 8 : 4);
     static constexpr int UBM = (WM * sizeof(R)) % 16 == 0 ? 16 : ((WM * sizeof(R)) % 8 == 0 ? 8 : 4);
-    static constexpr int UP = WP * (int)sizeof(R) / UBP;               // units per P record
-    static constexpr int UM = WM * (int)sizeof(R) / UBM;               // units per m record
-    static constexpr int ROW = WP + WM + (sizeof(R) == 8 ? 1 : 1);     // padded LDS row (words)
-    static constexpr int WORDS = 64 * ROW;                              // LDS words per wave
+    static constexpr int UP = BP / UBP;                                 // units per P record
+    static constexpr int UM = BM / UBM;                                 // units per m record
+    // words per lane row, padded to an odd count so that lanes writing their
+    // own rows fall into distinct LDS banks
+    static constexpr int ROWM = GM * WM + ((GM * WM) % 2 == 0 ? 1 : 0);
+    static constexpr int ROWP = GP * WP + ((GP * WP) % 2 == 0 ? 1 : 0);
+    static constexpr int ROW = WP + WM + 1;                             // load stage row (padded)
+    static constexpr int WORDS_LOAD = 64 * ROW;
+    static constexpr int WORDS = 64 * (ROWM + ROWP) > WORDS_LOAD ? 64 * (ROWM + ROWP) : WORDS_LOAD;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -250,42 +262,75 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// store x (this lane's moments, step kbase + lane * stride) to m [.][N], P [.][N][N]
-template <int N, typename R>
-__device__ __forceinline__ void wave_store_moments(R* __restrict__ m, R* __restrict__ P, int64_t kbase, int64_t stride,
-                                                   int64_t total, R* st, int lane, const Moments<N, R>& x) {
-    using S = MomStage<N, R>;
-    R* row = st + lane * S::ROW;
+// write the G buffered records of every lane: lane l's records are steps
+// kfirst + l * stride .. + G - 1 (contiguous in memory), `rec_words` R words
+// each, held in the stage at row l (ROW words per row)
+template <int G, int U, int UB, int ROW, typename R>
+__device__ __forceinline__ void wave_flush(R* __restrict__ dst, const R* st, int rec_words, int64_t kfirst,
+                                           int64_t stride, int64_t total, int lane, int filled) {
+    using UT = typename UnitT<UB>::T;
+    constexpr int PER = G * U;                       // units per lane
 #pragma unroll
-    for (int r = 0; r < N; ++r) row[r] = x.m[r];
+    for (int i = 0; i < PER; ++i) {
+        const int f = lane + 64 * i, l = f / PER, v = f % PER, s = v / U;
+        const int64_t k = kfirst + (int64_t)l * stride + s;
+        if (s < filled && k < total) {
+            UT val;
+            __builtin_memcpy(&val, reinterpret_cast<const char*>(st + l * ROW) + v * UB, UB);
+            reinterpret_cast<UT*>(dst + (kfirst + (int64_t)l * stride) * rec_words)[v] = val;
+        }
+    }
+}
+
+// Buffer this lane's moments of iteration e (step kw + lane * stride + e) and
+// write the buffered runs when a run is complete or the loop ends.
+template <int N, typename R>
+__device__ __forceinline__ void wave_store_moments(R* __restrict__ m, R* __restrict__ P, int64_t kw, int e, int last_e,
+                                                   int64_t stride, int64_t total, R* st, int lane,
+                                                   const Moments<N, R>& x) {
+    using S = MomStage<N, R>;
+    R* sm = st;                       // [64][GM][N]
+    R* sp = st + 64 * S::ROWM;        // [64][GP][N*N]
+    R* rm = sm + lane * S::ROWM + (e % S::GM) * N;
+    R* rp = sp + lane * S::ROWP + (e % S::GP) * (N * N);
+#pragma unroll
+    for (int r = 0; r < N; ++r) rm[r] = x.m[r];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
-        for (int c = 0; c < N; ++c) row[N + r * N + c] = x.P[sidx(r, c)];
-    wave_sync();
-    using UP_T = typename UnitT<S::UBP>::T;
-    using UM_T = typename UnitT<S::UBM>::T;
+        for (int c = 0; c < N; ++c) rp[r * N + c] = x.P[sidx(r, c)];
+    const bool fm = (e % S::GM == S::GM - 1) || e == last_e;
+    const bool fp = (e % S::GP == S::GP - 1) || e == last_e;
+    if (fm || fp) wave_sync();
+    if (fm) wave_flush<S::GM, S::UM, S::UBM, S::ROWM, R>(m, sm, N, kw + e - e % S::GM, stride, total, lane, e % S::GM + 1);
+    if (fp) wave_flush<S::GP, S::UP, S::UBP, S::ROWP, R>(P, sp, N * N, kw + e - e % S::GP, stride, total, lane, e % S::GP + 1);
+    if (fm || fp) wave_sync();
+}
+
+// reverse-order variant (the smoother produces steps from the last to the
+// first): iteration e runs EPT-1 .. 0, so a run is complete at e % G == 0
+template <int N, typename R>
+__device__ __forceinline__ void wave_store_moments_rev(R* __restrict__ m, R* __restrict__ P, int64_t kw, int e,
+                                                       int ept, int64_t stride, int64_t total, R* st, int lane,
+                                                       const Moments<N, R>& x) {
+    using S = MomStage<N, R>;
+    R* sm = st;
+    R* sp = st + 64 * S::ROWM;
+    R* rm = sm + lane * S::ROWM + (e % S::GM) * N;
+    R* rp = sp + lane * S::ROWP + (e % S::GP) * (N * N);
 #pragma unroll
-    for (int i = 0; i < S::UP; ++i) {
-        const int f = lane + 64 * i, l = f / S::UP, u = f % S::UP;
-        const int64_t k = kbase + (int64_t)l * stride;
-        if (k < total) {
-            UP_T v;
-            __builtin_memcpy(&v, reinterpret_cast<const char*>(st + l * S::ROW + N) + u * S::UBP, S::UBP);
-            reinterpret_cast<UP_T*>(P + k * S::WP)[u] = v;
-        }
-    }
+    for (int r = 0; r < N; ++r) rm[r] = x.m[r];
 #pragma unroll
-    for (int i = 0; i < S::UM; ++i) {
-        const int f = lane + 64 * i, l = f / S::UM, u = f % S::UM;
-        const int64_t k = kbase + (int64_t)l * stride;
-        if (k < total) {
-            UM_T v;
-            __builtin_memcpy(&v, reinterpret_cast<const char*>(st + l * S::ROW) + u * S::UBM, S::UBM);
-            reinterpret_cast<UM_T*>(m + k * S::WM)[u] = v;
-        }
-    }
-    wave_sync();
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) rp[r * N + c] = x.P[sidx(r, c)];
+    const bool fm = e % S::GM == 0;
+    const bool fp = e % S::GP == 0;
+    if (fm || fp) wave_sync();
+    // the run written here is steps e .. min(e + G, ept) - 1 of every lane
+    if (fm) wave_flush<S::GM, S::UM, S::UBM, S::ROWM, R>(m, sm, N, kw + e, stride, total, lane, min(S::GM, ept - e));
+    if (fp) wave_flush<S::GP, S::UP, S::UBP, S::ROWP, R>(P, sp, N * N, kw + e, stride, total, lane, min(S::GP, ept - e));
+    if (fm || fp) wave_sync();
 }
 
 // load this lane's moments (step kbase + lane * stride; zeros beyond total)
@@ -557,8 +602,70 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
                 fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
             }
         }
-        wave_store_moments<N, R>(mo, Po, kw + e, EPT, a.total, st, lane, X);
+        wave_store_moments<N, R>(mo, Po, kw, e, EPT - 1, EPT, a.total, st, lane, X);
     }
+}
+
+// Filter down-sweep fused with the smoother's reduce: the filtered moments of
+// each step are still in registers, so the smoothing element (Lemma 3) is
+// built and folded right away, and the smoother's per-thread prefixes and wave
+// aggregates are written as by k_smoother_reduce (into the same workspace
+// arrays: each thread reads its filter prefix before writing its smoother one).
+template <int N, typename R, int EPT, bool SEG, int M>
+__global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a) {
+    __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t k0 = gt * EPT;
+    const int64_t kw = (gt - lane) * EPT;
+    if (kw >= a.total) return;
+    R* st = stage[threadIdx.x >> 6];
+    const ConstLayout CL = const_layout(N, a.ny);
+    const R* y = static_cast<const R*>(a.y);
+    R* mo = static_cast<R*>(a.m);
+    R* Po = static_cast<R*>(a.P);
+    Moments<N, R> X;
+    load_m(a.carry, a.nwaves, gt >> 6, X);
+    {
+        FElem<N, R> pre;
+        load_f(a.thr, a.nthr, gt, pre);
+        fcarry<N, R, SEG>(X, pre);
+    }
+    SElem<N, R> sacc;
+    set_identity(sacc);
+    Seq s = seq_find<SEG>(a, k0 < a.total ? k0 : a.total - 1);
+#pragma unroll 1
+    for (int e = 0; e < EPT; ++e) {
+        const int64_t k = k0 + e;
+        if (k < a.total) {
+            seq_forward<SEG>(a, s, k);
+            const int64_t moff = SEG ? s.b * a.model_stride : 0;
+            const R* cst = static_cast<const R*>(a.consts) + moff;
+            const bool first = k == s.start;
+            {
+                FElem<N, R> x;
+                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+                if (M == 0) {
+                    fcarry<N, R, SEG>(X, x);
+                } else {
+                    constexpr int MM = M > 0 ? M : 1;
+                    R Gz[MM * N];
+                    load_gz<N, MM, R>(cst, CL, first, Gz);
+                    fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
+                }
+            }
+            SElem<N, R> el;
+            make_selem<N, R>(cst, CL, X, k == s.end - 1, el, a.status, s.b);
+            if (e == 0) sacc = el;
+            else scombine<N, R, SEG>(sacc, el, sacc);
+        }
+        wave_store_moments<N, R>(mo, Po, kw, e, EPT - 1, EPT, a.total, st, lane, X);
+    }
+    wave_inclusive_suffix_s<N, R, SEG>(sacc, lane);
+    SElem<N, R> ex;
+    wave_exclusive_suffix_s(sacc, ex, lane);
+    store_s(a.thr, a.nthr, gt, ex);
+    if (lane == 0) store_s(a.agg, a.nwaves, gt >> 6, sacc);
 }
 
 // ===========================================================================
@@ -733,7 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
             make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
             scarry<N, R, SEG>(el, Y);
         }
-        wave_store_moments<N, R>(mso, Pso, kw + e, EPT, a.total, st, lane, Y);
+        wave_store_moments_rev<N, R>(mso, Pso, kw, e, EPT, EPT, a.total, st, lane, Y);
     }
 }
 
@@ -820,26 +927,83 @@ hipError_t run_smoother(ScanArgs a, hipStream_t s) {
     prof_end(s);
     return hipGetLastError();
 }
+// Both passes with the filter down-sweep and the smoother reduce fused.
+template <int N, typename R, int EPT, bool SEG, int M>
+hipError_t run_filter_smoother(ScanArgs a, hipStream_t s) {
+    const int64_t nb0 = a.nthr / kBlock;
+    prof_begin("k_filter_reduce", s);
+    hipLaunchKernelGGL((k_filter_reduce<N, R, EPT, SEG, M>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    if (a.nwaves1 == 0) {
+        launch_filter_top<N, R, SEG>(a.agg, a.nwaves, a.carry, a, s);
+    } else {
+        const int64_t nb1 = a.nthr1 / kBlock;
+        prof_begin("k_filter_reduce_items", s);
+        PKS_EPT1_SWITCH(k_filter_reduce_items)
+        prof_end(s);
+        launch_filter_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, a, s);
+        prof_begin("k_filter_down_items", s);
+        PKS_EPT1_SWITCH(k_filter_down_items)
+        prof_end(s);
+    }
+    prof_begin("k_filter_down_smooth_reduce", s);
+    hipLaunchKernelGGL((k_filter_down_smooth_reduce<N, R, EPT, SEG, M>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    if (a.nwaves1 == 0) {
+        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, s);
+    } else {
+        const int64_t nb1 = a.nthr1 / kBlock;
+        prof_begin("k_smoother_reduce_items", s);
+        PKS_EPT1_SWITCH(k_smoother_reduce_items)
+        prof_end(s);
+        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, s);
+        prof_begin("k_smoother_down_items", s);
+        PKS_EPT1_SWITCH(k_smoother_down_items)
+        prof_end(s);
+    }
+    prof_begin("k_smoother_down", s);
+    hipLaunchKernelGGL((k_smoother_down<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
+    prof_end(s);
+    return hipGetLastError();
+}
 #undef PKS_EPT1_SWITCH
+
+// passes: 1 filter, 2 smoother, 3 both.  With FP32 storage both passes use the
+// fused filter down-sweep / smoother reduce; in FP64 the fused kernel needs
+// more registers than one wave per SIMD leaves, and the two separate kernels
+// measured faster, so FP64 runs the passes one after the other.
+template <int N, typename R, int EPT, bool SEG, int M>
+hipError_t run_passes(ScanArgs a, int passes, hipStream_t s) {
+    if (passes == 3) {
+        if constexpr (sizeof(R) == 4) {
+            return run_filter_smoother<N, R, EPT, SEG, M>(a, s);
+        } else {
+            const hipError_t e = run_filter<N, R, EPT, SEG, M>(a, s);
+            return e != hipSuccess ? e : run_smoother<N, R, EPT, SEG>(a, s);
+        }
+    }
+    if (passes == 2) return run_smoother<N, R, EPT, SEG>(a, s);
+    return run_filter<N, R, EPT, SEG, M>(a, s);
+}
 
 // rank-ny single-step combines when ny < nx (M = ny), the general form otherwise
 template <int N, typename R, int EPT, bool SEG>
-hipError_t run_filter_m(ScanArgs a, hipStream_t s) {
-    if (a.ny >= N || EPT < 8) return run_filter<N, R, EPT, SEG, 0>(a, s);
+hipError_t run_m(ScanArgs a, int passes, hipStream_t s) {
+    if (a.ny >= N || EPT < 8) return run_passes<N, R, EPT, SEG, 0>(a, passes, s);
     switch (a.ny) {
-        case 1: return run_filter<N, R, EPT, SEG, 1>(a, s);
-        case 2: return run_filter<N, R, EPT, SEG, (N > 2 ? 2 : 0)>(a, s);
-        case 3: return run_filter<N, R, EPT, SEG, (N > 3 ? 3 : 0)>(a, s);
-        default: return run_filter<N, R, EPT, SEG, 0>(a, s);
+        case 1: return run_passes<N, R, EPT, SEG, 1>(a, passes, s);
+        case 2: return run_passes<N, R, EPT, SEG, (N > 2 ? 2 : 0)>(a, passes, s);
+        case 3: return run_passes<N, R, EPT, SEG, (N > 3 ? 3 : 0)>(a, passes, s);
+        default: return run_passes<N, R, EPT, SEG, 0>(a, passes, s);
     }
 }
 
 template <int N, typename R, bool SEG>
-hipError_t dispatch_ept(ScanArgs a, bool smoother, hipStream_t s) {
+hipError_t dispatch_ept(ScanArgs a, int passes, hipStream_t s) {
     switch (a.ept) {
-        case 4: return smoother ? run_smoother<N, R, 4, SEG>(a, s) : run_filter_m<N, R, 4, SEG>(a, s);
-        case 8: return smoother ? run_smoother<N, R, 8, SEG>(a, s) : run_filter_m<N, R, 8, SEG>(a, s);
-        case 16: return smoother ? run_smoother<N, R, 16, SEG>(a, s) : run_filter_m<N, R, 16, SEG>(a, s);
+        case 4: return run_m<N, R, 4, SEG>(a, passes, s);
+        case 8: return run_m<N, R, 8, SEG>(a, passes, s);
+        case 16: return run_m<N, R, 16, SEG>(a, passes, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -848,8 +1012,8 @@ hipError_t dispatch_ept(ScanArgs a, bool smoother, hipStream_t s) {
 
 // All scan kernels of one state dimension and precision (one translation unit each).
 template <int N, typename R>
-hipError_t small_run(ScanArgs a, bool smoother, hipStream_t s) {
-    return a.offsets != nullptr ? dispatch_ept<N, R, true>(a, smoother, s) : dispatch_ept<N, R, false>(a, smoother, s);
+hipError_t small_run(ScanArgs a, int passes, hipStream_t s) {
+    return a.offsets != nullptr ? dispatch_ept<N, R, true>(a, passes, s) : dispatch_ept<N, R, false>(a, passes, s);
 }
 
 }  // namespace pks

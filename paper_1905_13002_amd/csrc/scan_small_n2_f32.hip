@@ -2,5 +2,5 @@
 #include "scan_small_impl.hpp"
 
 namespace pks {
-template hipError_t small_run<2, float>(ScanArgs, bool, hipStream_t);
+template hipError_t small_run<2, float>(ScanArgs, int, hipStream_t);
 }

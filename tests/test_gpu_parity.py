@@ -148,12 +148,21 @@ def test_static_model_Q0(pks):
     check(pks, model, w.y, "fp64", "static Q=0")
 
 
-def test_separate_calls_match_fused(pks):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separate_calls_match_fused(pks, prec):
+    """pks_filter + pks_smooth vs pks_filter_smooth.  In FP64 the combined call
+    runs the same kernels one after the other: bitwise equal.  With FP32 storage
+    its filter down-sweep also folds the smoothing elements, in another
+    bracketing: filtered outputs bitwise equal, smoothed equal to FP32 rounding."""
     w = wl.workload(1, T=5000)
-    a = gpu_run(pks, w.model, w.y, "fp64")
-    b = gpu_run(pks, w.model, w.y, "fp64", separate=True)
-    for k in a:
-        assert np.array_equal(a[k], b[k])
+    a = gpu_run(pks, w.model, w.y, prec)
+    b = gpu_run(pks, w.model, w.y, prec, separate=True)
+    assert np.array_equal(a["m"], b["m"]) and np.array_equal(a["P"], b["P"])
+    for k in ("ms", "Ps"):
+        if prec == "fp64":
+            assert np.array_equal(a[k], b[k]), k
+        else:
+            assert wl.max_rel_err(a[k], b[k], floor="rms") <= 1e-5, k
 
 
 @pytest.mark.parametrize("ept,ept1", [(4, 0), (8, 0), (16, 0), (4, 1), (8, 2), (16, 1), (4, 4), (8, 8), (16, 4)])
@@ -199,6 +208,10 @@ def test_batched_shared_model(pks):
 # plans, status, propagation
 # ---------------------------------------------------------------------------
 def test_plan_replays_match_eager(pks):
+    """A HIP-graph plan replayed several times, with unrelated eager work and the
+    outputs poisoned between replays: every replay is bitwise identical to the
+    first, and the first matches the eager batched calls to rounding (the plan
+    runs the fused down-sweep, which brackets the smoother block differently)."""
     w = wl.workload(4, B=33, T=2000)
     dm = pks.to_device(w.model, per_sequence=True)
     yd = torch.as_tensor(w.y).cuda()
@@ -207,11 +220,17 @@ def test_plan_replays_match_eager(pks):
     ms, Ps = pks.smooth_batched(dm, od, m, P, "fp64")
     eager = [t.clone() for t in (m, P, ms, Ps)]
     plan = pks.Plan(dm, yd, od, "fp64")
+    first = None
     for rep in range(3):
         outs = plan.launch()
         torch.cuda.synchronize()
-        for a, b in zip(outs, eager):
-            assert torch.equal(a, b), rep
+        if first is None:
+            first = [o.clone() for o in outs]
+            for a, b in zip(first, eager):
+                assert wl.max_rel_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+        else:
+            for a, b in zip(outs, first):
+                assert torch.equal(a, b), rep
         # unrelated eager work between replays
         _ = (torch.randn(1000, device="cuda") * 2).sum().item()
         for o in outs:
