@@ -56,8 +56,12 @@ def kernel_model(nx, ny, rs):
         "down_f": dict(bytes=ny * rs + mom, flops=f["f_carry"] + f["f_elem"]),
         "reduce_s": dict(bytes=mom, flops=f["s_elem"] + f["s_full"]),
         "down_s": dict(bytes=2 * mom, flops=f["s_elem"] + f["s_carry"]),
+        # filter down-sweep fused with the smoother reduce: the filtered moments
+        # are written once and folded into smoothing elements from registers
+        "down_f_reduce_s": dict(bytes=ny * rs + mom, flops=f["f_carry"] + f["f_elem"] + f["s_elem"] + f["s_full"]),
     }
     return {
+        "k_filter_down_smooth_reduce": per_step["down_f_reduce_s"],
         "k_filter_reduce": per_step["reduce_f"], "k_large_filter_reduce": per_step["reduce_f"],
         "k_filter_down": per_step["down_f"], "k_large_filter_down": per_step["down_f"],
         "k_smoother_reduce": per_step["reduce_s"], "k_large_smoother_reduce": per_step["reduce_s"],
@@ -94,6 +98,97 @@ def measured_traffic(workload_name, precision, kernel):
     return ent.get("hbm_bytes_per_launch")
 
 
+# rocprofv3 runs that the committed kernel profile of the default workload
+# comes from (run from the repository root, then summarised with
+# `python bench.py --summarize-profiles gpurun_out`)
+PROFILE_COMMANDS = [
+    "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace -- "
+    "python bench.py --steps 5 --warmup 2 --no-cpu-baseline",
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch -- "
+    "python bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write -- "
+    "python bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration",
+]
+
+
+def summarize_profiles(base, workload_name):
+    """Write profiles/<workload>_kernels.md and profiles/traffic_<workload>.json
+    from the three rocprofv3 databases under `base` (kernel trace statistics,
+    FETCH_SIZE and WRITE_SIZE per dispatch).  The HBM byte counters are scaled
+    by what they read for the calibration kernel of --copy-calibration (an
+    elementwise multiply that reads 1 GiB and writes 1 GiB)."""
+    import collections
+    import re
+    import sqlite3
+
+    def short(n):
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "")
+        m = re.match(r"void (\w+<[^>]*>)", n)
+        return m.group(1) if m else n
+
+    def find_db(d):
+        for f in sorted(os.listdir(d)):
+            if f.endswith("_results.db"):
+                return os.path.join(d, f)
+        raise FileNotFoundError("no *_results.db under %s" % d)
+
+    cur = sqlite3.connect(find_db(os.path.join(base, "prof_trace"))).cursor()
+    # top_kernels: name, total_calls, total_duration, average (microseconds), percentage
+    trace = [(short(r[0]), int(r[1]), float(r[3])) for r in
+             cur.execute("select name, total_calls, total_duration, average from top_kernels")]
+
+    def counters(sub, name):
+        c = sqlite3.connect(find_db(os.path.join(base, sub))).cursor()
+        d = collections.defaultdict(list)
+        for kn, v in c.execute("select kernel_name, value from counters_collection where counter_name=?", (name,)):
+            d[short(kn)].append(float(v))
+        return d
+
+    fetch = counters("prof_fetch", "FETCH_SIZE")
+    write = counters("prof_write", "WRITE_SIZE")
+    calib = [k for k in fetch if "elementwise" in k and "Mul" in k]
+    if not calib:
+        raise RuntimeError("calibration kernel not found: run the counter passes with --copy-calibration")
+    cal_f = statistics.median(fetch[calib[0]])
+    cal_w = statistics.median(write[calib[0]])
+    gib_kib = float(1 << 20)
+    fs, ws_ = gib_kib / cal_f, gib_kib / cal_w
+    med = lambda v: statistics.median(v) if v else float("nan")
+    rows, kernels = [], {}
+    for name, calls, avg in trace:
+        if not name.startswith("k_"):
+            continue
+        f_k, w_k = med(fetch.get(name, [])), med(write.get(name, []))
+        hbm = (f_k * fs + w_k * ws_) * 1024.0
+        rows.append((name, calls, avg, f_k / 1024.0, w_k / 1024.0, hbm / (1 << 20)))
+        prec = "fp64" if "double" in name else "mixed"
+        key = "%s/%s" % (prec, name.split("<")[0])
+        if key not in kernels:
+            kernels[key] = dict(kernel=name, avg_us=round(avg, 3), fetch_kib_raw=f_k, write_kib_raw=w_k,
+                                hbm_bytes_per_launch=int(round(hbm)))
+    rec = dict(workload=workload_name, sources_sha=sources_sha(), fetch_scale=round(fs, 4),
+               write_scale=round(ws_, 4),
+               note="HBM bytes per launch = FETCH_SIZE*fetch_scale + WRITE_SIZE*write_scale (KiB), "
+                    "median over dispatches", kernels=kernels)
+    with open(os.path.join(ROOT, "profiles", "traffic_%s.json" % workload_name), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = ["# Kernel profile: %s, filter + smoother" % workload_name, "",
+             "`rocprofv3` on one MI355X, library built from this tree.  Commands (repository root):", "", "```"]
+    lines += PROFILE_COMMANDS + ["python bench.py --summarize-profiles gpurun_out", "```", "",
+                                 "Each bench run times the FP64 path and then the mixed path; `avg_us` is "
+                                 "rocprofv3's mean kernel duration over all dispatches (warm-up included).", "",
+                                 "Counter calibration (`--copy-calibration`, elementwise multiply of 2^28 float32: "
+                                 "1 GiB read, 1 GiB written): FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB per dispatch, "
+                                 "so HBM bytes = FETCH_SIZE x %.3f + WRITE_SIZE x %.3f." % (cal_f, cal_w, fs, ws_), "",
+                                 "| kernel | calls | avg_us | FETCH_SIZE MiB (raw) | WRITE_SIZE MiB (raw) | "
+                                 "HBM MiB (scaled) |", "|---|---:|---:|---:|---:|---:|"]
+    for name, calls, avg, f_m, w_m, h_m in rows:
+        lines.append("| `%s` | %d | %.1f | %.1f | %.1f | %.1f |" % (name, calls, avg, f_m, w_m, h_m))
+    with open(os.path.join(ROOT, "profiles", "%s_kernels.md" % workload_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote profiles/%s_kernels.md and profiles/traffic_%s.json" % (workload_name, workload_name))
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -115,7 +210,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters under rocprofv3)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="summarise the rocprofv3 databases under DIR into profiles/ and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, "cv_T1048576")
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on exactly one GPU (the scan of one GPU's share); "

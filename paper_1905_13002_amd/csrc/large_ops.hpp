@@ -22,86 +22,44 @@ __device__ __forceinline__ double rcp64l(double x) {
     return fma(r, e, r);
 }
 
-// C[m x n] = alpha * op(A) op(B) (+ D), row-major with leading dimensions.
-// op(A) = A [m x k] or A^T (A stored [k x m]); same for B.  Each thread
-// computes a 4 x 4 block of C.  C may alias D but not A or B.
-template <typename TA, typename TB, typename TC, typename TD>
-__device__ void gemm(TC* C, int ldc, const TA* A, int lda, bool ta, const TB* B, int ldb, bool tb, int m, int n,
-                     int k, double alpha = 1.0, const TD* D = nullptr, int ldd = 0) {
-    const int bm = (m + 3) >> 2, bn = (n + 3) >> 2;
+// C[m x n] = alpha * op(A) op(B) (+ D), row-major with leading dimensions,
+// products and sums in the storage type R (float in the mixed mode).  op(A) =
+// A [m x k] or A^T (A stored [k x m]); same for B.  Each thread computes a
+// BS x BS block of C.  C may alias D but not A or B.
+template <int BS, typename R>
+__device__ __forceinline__ void gemm_blocks(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb,
+                                            int m, int n, int k, R alpha, const R* D, int ldd) {
+    const int bm = (m + BS - 1) / BS, bn = (n + BS - 1) / BS;
     for (int blk = threadIdx.x; blk < bm * bn; blk += blockDim.x) {
-        const int i0 = (blk / bn) << 2, j0 = (blk % bn) << 2;
-        double acc[4][4];
+        const int i0 = (blk / bn) * BS, j0 = (blk % bn) * BS;
+        R acc[BS][BS];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BS; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int b = 0; b < BS; ++b) acc[a][b] = R(0);
+        // unrolled so that the loads of several k steps are in flight together
+#pragma unroll(BS == 4 ? 4 : 8)
         for (int l = 0; l < k; ++l) {
-            double av[4], bv[4];
+            R av[BS], bv[BS];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int i = i0 + a;
-                av[a] = i < m ? double(ta ? A[l * lda + i] : A[i * lda + l]) : 0.0;
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int j = j0 + b;
-                bv[b] = j < n ? double(tb ? B[j * ldb + l] : B[l * ldb + j]) : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = i0 + a, j = j0 + b;
-                if (i < m && j < n) {
-                    double v = alpha * acc[a][b];
-                    if (D) v += double(D[i * ldd + j]);
-                    C[i * ldc + j] = TC(v);
-                }
-            }
-    }
-    __syncthreads();
-}
-
-// Products of the storage type: for R = float the sums run in float (the
-// mixed mode keeps products in FP32), for R = double in double.
-template <typename R>
-__device__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
-                      R alpha = R(1), const R* D = nullptr, int ldd = 0) {
-    const int bm = (m + 3) >> 2, bn = (n + 3) >> 2;
-    for (int blk = threadIdx.x; blk < bm * bn; blk += blockDim.x) {
-        const int i0 = (blk / bn) << 2, j0 = (blk % bn) << 2;
-        R acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = R(0);
-        for (int l = 0; l < k; ++l) {
-            R av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < BS; ++a) {
                 const int i = i0 + a;
                 av[a] = i < m ? (ta ? A[l * lda + i] : A[i * lda + l]) : R(0);
             }
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < BS; ++b) {
                 const int j = j0 + b;
                 bv[b] = j < n ? (tb ? B[j * ldb + l] : B[l * ldb + j]) : R(0);
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < BS; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+                for (int b = 0; b < BS; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BS; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < BS; ++b) {
                 const int i = i0 + a, j = j0 + b;
                 if (i < m && j < n) {
                     R v = alpha * acc[a][b];
@@ -110,6 +68,66 @@ __device__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, i
                 }
             }
     }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 product on the matrix cores: one wave per 16 x 16 tile of C, K in
+// steps of 4 (v_mfma_f32_16x16x4f32).  Lane l supplies A(i0 + l % 16, k + l / 16)
+// and B(k + l / 16, j0 + l % 16) and receives C(i0 + 4 (l / 16) + r, j0 + l % 16)
+// in accumulator register r.  Out-of-range operands are read as zero, so any
+// m, n, k work; every lane of a wave issues every MFMA.
+__device__ __forceinline__ void gemm_mfma_f32(float* C, int ldc, const float* A, int lda, bool ta, const float* B,
+                                              int ldb, bool tb, int m, int n, int k, float alpha, const float* D,
+                                              int ldd) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+    for (int t = wave; t < tm * tn; t += nwaves) {
+        const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+        const int ia = i0 + li, jb = j0 + li;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int l0 = 0; l0 < k; l0 += 4) {
+            const int l = l0 + lk;
+            const float av = (ia < m && l < k) ? (ta ? A[l * lda + ia] : A[ia * lda + l]) : 0.f;
+            const float bv = (jb < n && l < k) ? (tb ? B[jb * ldb + l] : B[l * ldb + jb]) : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+        const int j = j0 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 4 * lk + r;
+            if (i < m && j < n) {
+                float v = alpha * acc[r];
+                if (D) v += D[i * ldd + j];
+                C[i * ldc + j] = v;
+            }
+        }
+    }
+}
+
+// Products of the storage type.  FP32 products with both output dimensions
+// at least 32 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
+// everything else on the vector units, with the largest register block that
+// still gives every thread of the workgroup a block of C.
+template <typename R>
+__device__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
+                      R alpha = R(1), const R* D = nullptr, int ldd = 0) {
+    const int threads = blockDim.x;
+    if constexpr (sizeof(R) == 4) {
+        if (m >= 32 && n >= 32) {
+            gemm_mfma_f32(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
+            __syncthreads();
+            return;
+        }
+    }
+    if (((m + 3) >> 2) * ((n + 3) >> 2) >= threads)
+        gemm_blocks<4, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
+    else if (((m + 1) >> 1) * ((n + 1) >> 1) >= threads)
+        gemm_blocks<2, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
+    else
+        gemm_blocks<1, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
     __syncthreads();
 }
 
@@ -141,6 +159,7 @@ __device__ void gemv(R* y, const R* A, int lda, bool ta, const R* x, int m, int 
                      R alpha = R(1)) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
         R s = R(0);
+#pragma unroll 8
         for (int l = 0; l < k; ++l) s = fma(ta ? A[l * lda + i] : A[i * lda + l], x[l], s);
         y[i] = alpha * s + (d ? d[i] : R(0));
     }
@@ -190,58 +209,84 @@ __device__ void lu_solve(double* a, int lda, int n, int w, int* piv_sh) {
         }
         __syncthreads();
     }
-    // back substitution, one right-hand side column per thread
-    for (int c = n + tid; c < width; c += blockDim.x) {
-        for (int i = n - 1; i >= 0; --i) {
-            double s = a[i * lda + c];
-            for (int l = i + 1; l < n; ++l) s = fma(-a[i * lda + l], a[l * lda + c], s);
-            a[i * lda + c] = s * rcp64l(a[i * lda + i]);
+    // back substitution U x = z, all right-hand sides at once: at step i the
+    // entries of row i are final; rows above it are updated with row i scaled
+    // by 1 / u_ii (scaled copies of the rows are written after the sweep)
+    for (int i = n - 1; i > 0; --i) {
+        const double inv = rcp64l(a[i * lda + i]);
+        for (int idx = tid; idx < i * w; idx += blockDim.x) {
+            const int r = idx / w, c = n + idx % w;
+            a[r * lda + c] = fma(-a[r * lda + i] * inv, a[i * lda + c], a[r * lda + c]);
         }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < n * w; idx += blockDim.x) {
+        const int r = idx / w, c = n + idx % w;
+        a[r * lda + c] *= rcp64l(a[r * lda + r]);
     }
     __syncthreads();
 }
 
 // In-place lower Cholesky factor (double) of the n x n SPD matrix S (stride
-// lds); returns false (workgroup-uniform) if a pivot is not positive.
+// lds); returns false (workgroup-uniform) if a pivot is not positive.  At step
+// j column j is final; the trailing lower triangle is updated with that column
+// scaled by 1 / sqrt(s_jj), and the scaled columns are written after the loop.
 __device__ bool cholesky(double* S, int lds, int n, int* flag_sh) {
     const int tid = threadIdx.x;
-    if (tid == 0) *flag_sh = 0;
-    __syncthreads();
+    bool ok = true;
     for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            const double d = S[j * lds + j];
-            if (!(d > 0.0)) *flag_sh = 1;
-            S[j * lds + j] = sqrt(d);
-        }
-        __syncthreads();
-        const double inv = rcp64l(S[j * lds + j]);
-        for (int i = j + 1 + tid; i < n; i += blockDim.x) S[i * lds + j] *= inv;
-        __syncthreads();
+        const double d = S[j * lds + j];
+        ok = ok && d > 0.0;
+        const double inv = rcp64l(d);               // 1 / s_jj = (1 / sqrt(s_jj))^2
         const int m = n - j - 1;
         for (int idx = tid; idx < m * m; idx += blockDim.x) {
             const int i = j + 1 + idx / m, l = j + 1 + idx % m;
-            if (l <= i) S[i * lds + l] = fma(-S[i * lds + j], S[l * lds + j], S[i * lds + l]);
+            if (l <= i) S[i * lds + l] = fma(-S[i * lds + j] * inv, S[l * lds + j], S[i * lds + l]);
         }
         __syncthreads();
     }
-    const bool ok = *flag_sh == 0;
+    for (int idx = tid; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        if (j < i) S[i * lds + j] *= rcp64l(sqrt(S[j * lds + j]));
+    }
     __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) S[j * lds + j] = sqrt(S[j * lds + j]);
+    __syncthreads();
+    (void)flag_sh;
     return ok;
 }
 
-// X [n x r] (stride ldx) <- (L L^T)^-1 X, one column per thread
+// X [n x r] (stride ldx) <- (L L^T)^-1 X, all columns at once: one barrier per
+// pivot row in each of the two triangular sweeps
 __device__ void chol_solve(const double* L, int ldl, int n, double* X, int ldx, int r) {
-    for (int c = threadIdx.x; c < r; c += blockDim.x) {
-        for (int i = 0; i < n; ++i) {
-            double s = X[i * ldx + c];
-            for (int l = 0; l < i; ++l) s = fma(-L[i * ldl + l], X[l * ldx + c], s);
-            X[i * ldx + c] = s * rcp64l(L[i * ldl + i]);
+    const int tid = threadIdx.x;
+    // L z = x
+    for (int i = 0; i + 1 < n; ++i) {
+        const double inv = rcp64l(L[i * ldl + i]);
+        const int rows = n - i - 1;
+        for (int idx = tid; idx < rows * r; idx += blockDim.x) {
+            const int j = i + 1 + idx / r, c = idx % r;
+            X[j * ldx + c] = fma(-L[j * ldl + i] * inv, X[i * ldx + c], X[j * ldx + c]);
         }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = X[i * ldx + c];
-            for (int l = i + 1; l < n; ++l) s = fma(-L[l * ldl + i], X[l * ldx + c], s);
-            X[i * ldx + c] = s * rcp64l(L[i * ldl + i]);
+        __syncthreads();
+    }
+    for (int idx = tid; idx < n * r; idx += blockDim.x) {
+        const int j = idx / r, c = idx % r;
+        X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
+    }
+    __syncthreads();
+    // L^T x = z
+    for (int i = n - 1; i > 0; --i) {
+        const double inv = rcp64l(L[i * ldl + i]);
+        for (int idx = tid; idx < i * r; idx += blockDim.x) {
+            const int j = idx / r, c = idx % r;
+            X[j * ldx + c] = fma(-L[i * ldl + j] * inv, X[i * ldx + c], X[j * ldx + c]);
         }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < n * r; idx += blockDim.x) {
+        const int j = idx / r, c = idx % r;
+        X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
     }
     __syncthreads();
 }

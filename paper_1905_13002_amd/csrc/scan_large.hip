@@ -52,8 +52,11 @@ __host__ __device__ inline SLay slay(int n) {
 // moments: m at 0, P at n
 
 // ---------------------------------------------------------------------------
-// arena layout (R words unless noted), shared by every large-state kernel
+// arena layouts (R words unless noted).  Each kernel gets only the buffers its
+// operators touch; the offsets of the others stay 0 and are never used by it.
 // ---------------------------------------------------------------------------
+enum ArenaKind : int { kArFRed = 0, kArFKs, kArFDown, kArSRed, kArSKs, kArSDown, kArKinds };
+
 struct Arena {
     // R buffers
     int acc, out, sel, xv, X1, x2, X3, w, JA, Z, T, Y, mom;
@@ -61,27 +64,65 @@ struct Arena {
     int aug, sig;
     int rwords, dwords;
 };
-__host__ __device__ inline Arena arena_layout(int n, int ny) {
-    Arena a;
-    const int n2 = n * n, fw = flay(n).words;
-    int o = 0;
-    a.acc = o; o += fw;
-    a.out = o; o += fw;
-    a.sel = o; o += 2 * n2 + n;      // a second smoothing element
-    a.xv = o; o += 2 * n + ny;      // b_k, eta_k of a single step (+ y)
-    a.X1 = o; o += n2;
-    a.x2 = o; o += n;
-    a.X3 = o; o += n2;
-    a.w = o; o += n;
-    a.JA = o; o += n2;
-    a.Z = o; o += n2;
-    a.T = o; o += n2;
-    a.Y = o; o += n * ny + ny * n + ny;   // Y [n x ny], GA [ny x n], Gv / Gb
-    a.mom = o; o += n + n2;
+__host__ __device__ inline Arena arena_layout(int n, int ny, int kind) {
+    Arena a = {};
+    const int n2 = n * n, fw = flay(n).words, sw = slay(n).words;
+    const bool lowrank = ny < n;
+    int o = 0, d = 0;
+    switch (kind) {
+        case kArFRed:                       // accumulator updated in place
+            a.acc = o; o += fw;
+            a.out = a.acc;
+            a.xv = o; o += 2 * n + ny;      // b_k, eta_k of a single step
+            break;
+        case kArFDown:
+            a.mom = o; o += n + n2;
+            a.xv = o; o += 2 * n + ny;
+            break;
+        case kArSRed:                       // accumulator / result ping-pong
+            a.acc = o; o += sw;
+            a.out = o; o += sw;             // element of step k
+            a.sel = o; o += sw;
+            a.mom = o; o += n + n2;
+            break;
+        case kArSDown:
+            a.acc = o; o += n + n2;         // smoothed moments
+            a.out = o; o += sw;
+            break;
+        default:                            // scans over block elements: operands and result in the workspace
+            break;
+    }
+    if (kind <= kArFDown) {
+        const bool combine = kind != kArFDown;          // two elements (else moments (x) element)
+        const bool full = kind == kArFKs || !lowrank;   // LU of I + C J (else rank-ny form)
+        a.x2 = o; o += n;
+        a.X3 = o; o += n2;
+        a.w = o; o += n;
+        if (full || !combine) {              // the rank-ny combine puts its n x n scratch in Y and sig
+            a.Z = o; o += n2;
+            a.T = o; o += n2;
+        }
+        if (combine) {
+            a.X1 = o; o += n2;
+            a.JA = o; o += n2;
+        }
+        if (full) {
+            a.aug = d; d += n * (combine ? 3 * n + 1 : 2 * n + 1);
+        } else {
+            const int yw = n * ny + ny * n + ny;           // Y [n x ny], GA [ny x n], Gv / Gb
+            const int sw2 = ny * ny + ny * (combine ? 2 * n + 1 : n + 1);
+            a.Y = o; o += combine && yw < n2 ? n2 : yw;
+            a.sig = d; d += combine && sw2 < n2 ? n2 : sw2;
+        }
+    } else {
+        a.T = o; o += n2;
+        a.Z = o; o += n2;
+        if (kind != kArSKs) {
+            a.x2 = o; o += n;
+            a.aug = d; d += 2 * n2;         // F P F^T + Q and E^T
+        }
+    }
     a.rwords = (o + 3) & ~3;
-    int d = 0;
-    a.aug = d; d += n * (3 * n + 1);      // [M | A_i | v | C_i]  or  [Sigma^-1 rhs]
-    a.sig = d; d += ny * ny + ny * (2 * n + 1);
     a.dwords = d;
     return a;
 }
@@ -102,8 +143,8 @@ struct Ctx {
 };
 
 template <typename R>
-__host__ __device__ inline size_t arena_bytes(int n, int ny) {
-    const Arena a = arena_layout(n, ny);
+__host__ __device__ inline size_t arena_bytes(int n, int ny, int kind) {
+    const Arena a = arena_layout(n, ny, kind);
     return (((size_t)a.rwords * sizeof(R) + 15) & ~size_t(15)) + sizeof(double) * a.dwords;
 }
 
@@ -113,12 +154,23 @@ struct LargeArgs {
     int64_t nblocks;
     void* agg[2];        // ping-pong block elements [nblocks][words]
     int final_buf;       // which agg buffer holds the scanned elements
-    char* slots;         // per-block arena slots in the workspace (nullptr: LDS)
+    int slot_mask;       // bit k: kernels of arena kind k use workspace slots, not LDS
+    char* slots;         // per-block arena slots in the workspace
     size_t slot_bytes;
 };
 
-__device__ __forceinline__ char* arena_base(const LargeArgs& a, char* lds) {
-    return a.slots ? a.slots + (size_t)blockIdx.x * a.slot_bytes : lds;
+__device__ __forceinline__ char* arena_base(const LargeArgs& a, char* lds, int kind) {
+    return ((a.slot_mask >> kind) & 1) ? a.slots + (size_t)blockIdx.x * a.slot_bytes : lds;
+}
+
+// context of one kernel: dimensions, record layouts and its arena
+__device__ __forceinline__ void make_ctx(Ctx& c, const LargeArgs& la, char* lds, int kind) {
+    c.n = la.s.nx;
+    c.ny = la.s.ny;
+    c.fl = flay(c.n);
+    c.sl = slay(c.n);
+    c.ar = arena_layout(c.n, c.ny, kind);
+    c.base = arena_base(la, lds, kind);
 }
 
 // sequence lookup (workgroup-uniform)
@@ -160,17 +212,16 @@ __device__ void seq_bwd(const ScanArgs& a, SeqL& s, int64_t k) {
 // Output half of Lemma 2 given X1 = M^-1 A_i, x2 = M^-1 (b_i + C_i eta_j),
 // X3 = M^-1 C_i, w = eta_j - J_j b_i and JA = J_j A_i (all in the arena):
 //   A = A_j X1, b = A_j x2 + b_j, C = sym(A_j X3 A_j^T) + C_j,
-//   eta = X1^T w + eta_i, J = sym(X1^T JA) + J_i.   Result in `out`.
+//   eta = X1^T w + eta_i, J = sym(X1^T JA) + J_i.   Result in `out`, which may
+// be ei itself.  Z and T are n x n scratch.
 template <typename R>
-__device__ void fcombine_tail(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, R* out) {
+__device__ void fcombine_tail(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, R* out, R* Z, R* T) {
     const int n = c.n;
     R* X1 = c.r<R>(c.ar.X1);
     R* x2 = c.r<R>(c.ar.x2);
     R* X3 = c.r<R>(c.ar.X3);
     R* w = c.r<R>(c.ar.w);
     R* JA = c.r<R>(c.ar.JA);
-    R* Z = c.r<R>(c.ar.Z);
-    R* T = c.r<R>(c.ar.T);
     gemv<R>(out + c.fl.eta, X1, n, true, w, n, n, ei + c.fl.eta);
     gemmR<R>(Z, n, X1, n, true, JA, n, false, n, n, n);
     sym_add<R>(out + c.fl.J, Z, ei + c.fl.J, n);
@@ -215,7 +266,7 @@ __device__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj,
     // w = eta_j - J_j b_i ; JA = J_j A_i
     gemv<R>(c.r<R>(c.ar.w), Jj, n, false, ei + c.fl.b, n, n, etaj, R(-1));
     gemmR<R>(c.r<R>(c.ar.JA), n, Jj, n, false, ei + c.fl.A, n, false, n, n, n);
-    fcombine_tail<R>(c, ei, Aj, bj, Cj, out);
+    fcombine_tail<R>(c, ei, Aj, bj, Cj, out, Z, c.r<R>(c.ar.T));
 }
 
 // Lemma 2 with ej a single step k > 1 (J_j = W G, rank ny < nx)
@@ -233,9 +284,10 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     gemv<R>(v, ei + c.fl.C, n, false, etaj, n, n, ei + c.fl.b);             // b_i + C_i eta_j
     gemmR<R>(GA, n, Gm, n, false, ei + c.fl.A, n, false, m, n, n);          // G A_i
     gemv<R>(Gv, Gm, n, false, v, m, n);                                     // G v
-    gemmR<R>(c.r<R>(c.ar.Z), m, Gm, n, false, Y, m, false, m, m, n);        // G C_i G^T
+    // G C_i G^T into the X1 buffer (free until X1 is formed)
+    gemmR<R>(c.r<R>(c.ar.X1), m, Gm, n, false, Y, m, false, m, m, n);
     {
-        const R* GY = c.r<R>(c.ar.Z);
+        const R* GY = c.r<R>(c.ar.X1);
         for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
             const int r = idx / m, q = idx % m;
             sg[idx] = S[idx] + 0.5 * (double(GY[r * m + q]) + double(GY[q * m + r]));
@@ -255,6 +307,7 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int r = idx / n, q = idx % n;
         double a = double(ei[c.fl.A + idx]), p = 0.0, s = 0.0;
+#pragma unroll 8
         for (int l = 0; l < m; ++l) {
             a = fma(-double(Y[r * m + l]), rh[l * rhs + q], a);
             p = fma(double(Y[r * m + l]), rh[l * rhs + n + 1 + q], p);
@@ -266,6 +319,7 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     __syncthreads();
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         double a = double(v[r]);
+#pragma unroll 8
         for (int l = 0; l < m; ++l) a = fma(-double(Y[r * m + l]), rh[l * rhs + n], a);
         x2[r] = R(a);
     }
@@ -274,7 +328,9 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     gemv<R>(Gv, Gm, n, false, ei + c.fl.b, m, n);                           // G b_i (reuses Gv)
     gemv<R>(c.r<R>(c.ar.w), Wm, m, false, Gv, n, m, etaj, R(-1));
     gemmR<R>(c.r<R>(c.ar.JA), n, Wm, m, false, GA, n, false, n, n, m);
-    fcombine_tail<R>(c, ei, Aj, bj, Cj, out);
+    // the tail's scratch reuses the Sigma / right-hand-side region and the
+    // Y | GA | Gv region, both consumed by now
+    fcombine_tail<R>(c, ei, Aj, bj, Cj, out, reinterpret_cast<R*>(sg), Y);
 }
 
 // moments X (prefix with A = 0) <- X (x) a_j
@@ -346,6 +402,7 @@ __device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, co
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
         const int r = idx / n, q = idx % n;
         double p = 0.0, s = 0.0;
+#pragma unroll 8
         for (int l = 0; l < m; ++l) {
             p = fma(double(Y[r * m + l]), rh[l * rhs + 1 + q], p);
             s = fma(double(Y[q * m + l]), rh[l * rhs + 1 + r], s);
@@ -354,6 +411,7 @@ __device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, co
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         double a = double(v[r]);
+#pragma unroll 8
         for (int l = 0; l < m; ++l) a = fma(-double(Y[r * m + l]), rh[l * rhs], a);
         x2[r] = R(a);
     }
@@ -375,6 +433,7 @@ __device__ void build_fvec(const Ctx& c, const R* cst, const ConstLayout& CL, co
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         R sb = first ? cst[CL.c1 + r] : cst[CL.c + r];
         R se = first ? R(0) : cst[CL.w + r];
+#pragma unroll 4
         for (int q = 0; q < ny; ++q) {
             const R yq = yk[q];
             sb = fma(first ? cst[CL.K1 + r * ny + q] : cst[CL.K + r * ny + q], yq, sb);
@@ -395,15 +454,13 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_reduce(LargeArgs la) 
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArFRed);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const bool lowrank = a.ny < a.nx;
     const int64_t k0 = blockIdx.x * la.blen;
     const int64_t k1 = (k0 + la.blen < a.total) ? k0 + la.blen : a.total;
     R* acc = c.r<R>(c.ar.acc);
-    R* out = c.r<R>(c.ar.out);
     const R* bk = c.r<R>(c.ar.xv);
     const R* ek = bk + n;
     const R* y = static_cast<const R*>(a.y);
@@ -433,12 +490,13 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_reduce(LargeArgs la) 
             __syncthreads();
             continue;
         }
+        // the combine updates the accumulator in place (every operand read
+        // from it is consumed before the output block that overwrites it)
         if (lowrank)
             fcombine_fresh_wg<R>(c, acc, cst + CL.A, bk, cst + CL.C, ek, cst + CL.G, cst + CL.W,
-                                 a.consts64 + moff + CL.S, out, ish);
+                                 a.consts64 + moff + CL.S, acc, ish);
         else
-            fcombine_wg<R>(c, acc, cst + CL.A, bk, cst + CL.C, ek, cst + CL.J, out, ish);
-        copy<R, R>(acc, out, c.fl.words);
+            fcombine_wg<R>(c, acc, cst + CL.A, bk, cst + CL.C, ek, cst + CL.J, acc, ish);
     }
     R* dst = static_cast<R*>(la.agg[0]) + (size_t)blockIdx.x * c.fl.words;
     copy<R, R>(dst, acc, c.fl.words);
@@ -451,8 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_ks(LargeArgs la, cons
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArFKs);
     const int64_t i = blockIdx.x;
     const int fw = c.fl.words;
     const R* in = static_cast<const R*>(in_);
@@ -463,19 +520,17 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_ks(LargeArgs la, cons
         return;
     }
     const R* ei = in + (size_t)(i - d) * fw;
-    R* tmp = c.r<R>(c.ar.out);
-    fcombine_wg<R>(c, ei, ej + c.fl.A, ej + c.fl.b, ej + c.fl.C, ej + c.fl.eta, ej + c.fl.J, tmp, ish);
+    fcombine_wg<R>(c, ei, ej + c.fl.A, ej + c.fl.b, ej + c.fl.C, ej + c.fl.eta, ej + c.fl.J, out, ish);
     if (SEG && all_zero<R>(ej + c.fl.A, c.n * c.n, ish)) {
         // the right operand starts a sequence: its f-part passes through
         // untouched (exactly what A_j = 0 gives, without 0 * NaN from the left)
         for (int idx = threadIdx.x; idx < c.n * c.n; idx += blockDim.x) {
-            tmp[c.fl.A + idx] = R(0);
-            tmp[c.fl.C + idx] = ej[c.fl.C + idx];
+            out[c.fl.A + idx] = R(0);
+            out[c.fl.C + idx] = ej[c.fl.C + idx];
         }
-        for (int r = threadIdx.x; r < c.n; r += blockDim.x) tmp[c.fl.b + r] = ej[c.fl.b + r];
+        for (int r = threadIdx.x; r < c.n; r += blockDim.x) out[c.fl.b + r] = ej[c.fl.b + r];
         __syncthreads();
     }
-    copy<R, R>(out, tmp, fw);
 }
 
 template <typename R, bool SEG>
@@ -484,8 +539,7 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_down(LargeArgs la) {
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArFDown);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const bool lowrank = a.ny < a.nx;
@@ -532,11 +586,9 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_down(LargeArgs la) {
 // Lemma 3 element of step k (not last) from moments (m, P) at `mom`, into e:
 // E = P F^T (F P F^T + Q)^-1, g = m - E (F m + u), L = sym(P - E F P)
 template <typename R>
-__device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL, const R* mom, R* e, int* status,
-                               int b, int* ish) {
+__device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL, const R* m, const R* P, R* e,
+                               int* status, int b, int* ish) {
     const int n = c.n;
-    const R* m = mom;
-    const R* P = mom + n;
     const R* F = cst + CL.F;
     R* V = c.r<R>(c.ar.T);
     R* Z = c.r<R>(c.ar.Z);
@@ -612,8 +664,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_reduce(LargeArgs la
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArSRed);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const int64_t k0 = blockIdx.x * la.blen;
@@ -632,17 +683,18 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_reduce(LargeArgs la
             fill<R>(e + c.sl.E, R(0), n2);
             copy<R, R>(e + c.sl.g, mom, n + n2);    // g = m, L = P (contiguous)
         } else {
-            build_selem_wg<R>(c, cst, CL, mom, e, a.status, s.b, ish);
+            build_selem_wg<R>(c, cst, CL, mom, mom + n, e, a.status, s.b, ish);
         }
         if (k == k0) {
             copy<R, R>(acc, e, c.sl.words);
         } else {
             scombine_wg<R>(c, acc, e, tmp);
-            // an accumulator ending a sequence (E = 0) passes through
-            if (SEG && all_zero<R>(acc + c.sl.E, n2, ish)) {
-                __syncthreads();
-            } else {
-                copy<R, R>(acc, tmp, c.sl.words);
+            // an accumulator ending a sequence (E = 0) passes through; else
+            // the result becomes the accumulator
+            if (!(SEG && all_zero<R>(acc + c.sl.E, n2, ish))) {
+                R* t = acc;
+                acc = tmp;
+                tmp = t;
             }
         }
     }
@@ -658,8 +710,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_ks(LargeArgs la, co
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArSKs);
     const int64_t i = blockIdx.x;
     const int sw = c.sl.words;
     const R* in = static_cast<const R*>(in_);
@@ -669,9 +720,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_ks(LargeArgs la, co
         copy<R, R>(out, ei, sw);
         return;
     }
-    R* tmp = c.r<R>(c.ar.out);
-    scombine_wg<R>(c, ei, in + (size_t)(i + d) * sw, tmp);
-    copy<R, R>(out, tmp, sw);
+    scombine_wg<R>(c, ei, in + (size_t)(i + d) * sw, out);
 }
 
 template <typename R, bool SEG>
@@ -680,8 +729,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
     __shared__ int ish[4];
     const ScanArgs& a = la.s;
     Ctx c;
-    c.n = a.nx; c.ny = a.ny; c.fl = flay(a.nx); c.sl = slay(a.nx); c.ar = arena_layout(a.nx, a.ny);
-    c.base = arena_base(la, lds);
+    make_ctx(c, la, lds, kArSDown);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const int64_t blk = blockIdx.x;
@@ -690,7 +738,6 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
     if (k0 >= k1) return;
     R* Y = c.r<R>(c.ar.acc);
     R* e = c.r<R>(c.ar.out);
-    R* mom = c.r<R>(c.ar.mom);
     R* mso = static_cast<R*>(a.ms);
     R* Pso = static_cast<R*>(a.Ps);
     if (blk + 1 < la.nblocks) {
@@ -703,11 +750,14 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
     for (int64_t k = k1 - 1; k >= k0; --k) {
         seq_bwd<SEG>(a, s, k);
         const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
-        load_moments<R>(c, a, k, mom);
+        // the filtered moments of step k are read where the filter wrote them
+        const R* mk = static_cast<const R*>(a.m) + k * n;
+        const R* Pk = static_cast<const R*>(a.P) + k * n2;
         if (k == s.end - 1) {
-            copy<R, R>(Y, mom, n + n2);
+            copy<R, R>(Y, mk, n);
+            copy<R, R>(Y + n, Pk, n2);
         } else {
-            build_selem_wg<R>(c, cst, CL, mom, e, a.status, s.b, ish);
+            build_selem_wg<R>(c, cst, CL, mk, Pk, e, a.status, s.b, ish);
             scarry_wg<R>(c, e, Y);
         }
         for (int r = threadIdx.x; r < n; r += blockDim.x) mso[k * n + r] = Y[r];
@@ -719,86 +769,135 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// workgroup size: one wave for nx <= 16 (barriers are then nearly free and
+// the products still give every lane work), two for nx <= 32, four above
+__host__ __device__ inline int large_threads(int nx) { return nx <= 16 ? 64 : (nx <= 32 ? 128 : 256); }
+
+// arenas up to this size live in LDS (gfx950 addresses 160 KB of LDS per
+// workgroup; the kernels' static scratch is a few bytes)
+constexpr size_t kMaxLdsArena = 160 * 1024 - 256;
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <typename R>
+size_t kind_lds(const LargeArgs& la, int kind) {
+    return ((la.slot_mask >> kind) & 1) ? 0 : arena_bytes<R>(la.s.nx, la.s.ny, kind);
+}
+
 template <typename R, bool SEG>
 hipError_t run_large(LargeArgs la, bool smoother, hipStream_t s) {
-    const size_t lds = la.slots ? 0 : arena_bytes<R>(la.s.nx, la.s.ny);
-    const dim3 grid((unsigned)la.nblocks), block(kThreads);
+    const dim3 grid((unsigned)la.nblocks), block(large_threads(la.s.nx));
+    hipError_t e;
     if (!smoother) {
+        const size_t l_red = kind_lds<R>(la, kArFRed), l_ks = kind_lds<R>(la, kArFKs),
+                     l_down = kind_lds<R>(la, kArFDown);
+        if ((e = allow_lds(k_large_filter_reduce<R, SEG>, l_red)) != hipSuccess) return e;
+        if ((e = allow_lds(k_large_filter_ks<R, SEG>, l_ks)) != hipSuccess) return e;
+        if ((e = allow_lds(k_large_filter_down<R, SEG>, l_down)) != hipSuccess) return e;
         prof_begin("k_large_filter_reduce", s);
-        hipLaunchKernelGGL((k_large_filter_reduce<R, SEG>), grid, block, lds, s, la);
+        hipLaunchKernelGGL((k_large_filter_reduce<R, SEG>), grid, block, l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_filter_ks", s);
-            hipLaunchKernelGGL((k_large_filter_ks<R, SEG>), grid, block, lds, s, la, la.agg[cur], la.agg[cur ^ 1], d);
+            hipLaunchKernelGGL((k_large_filter_ks<R, SEG>), grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1],
+                               d);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_filter_down", s);
-        hipLaunchKernelGGL((k_large_filter_down<R, SEG>), grid, block, lds, s, la);
+        hipLaunchKernelGGL((k_large_filter_down<R, SEG>), grid, block, l_down, s, la);
         prof_end(s);
     } else {
+        const size_t l_red = kind_lds<R>(la, kArSRed), l_ks = kind_lds<R>(la, kArSKs),
+                     l_down = kind_lds<R>(la, kArSDown);
+        if ((e = allow_lds(k_large_smoother_reduce<R, SEG>, l_red)) != hipSuccess) return e;
+        if ((e = allow_lds(k_large_smoother_ks<R, SEG>, l_ks)) != hipSuccess) return e;
+        if ((e = allow_lds(k_large_smoother_down<R, SEG>, l_down)) != hipSuccess) return e;
         prof_begin("k_large_smoother_reduce", s);
-        hipLaunchKernelGGL((k_large_smoother_reduce<R, SEG>), grid, block, lds, s, la);
+        hipLaunchKernelGGL((k_large_smoother_reduce<R, SEG>), grid, block, l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_smoother_ks", s);
-            hipLaunchKernelGGL((k_large_smoother_ks<R, SEG>), grid, block, lds, s, la, la.agg[cur], la.agg[cur ^ 1], d,
-                               la.nblocks);
+            hipLaunchKernelGGL((k_large_smoother_ks<R, SEG>), grid, block, l_ks, s, la, la.agg[cur],
+                               la.agg[cur ^ 1], d, la.nblocks);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_smoother_down", s);
-        hipLaunchKernelGGL((k_large_smoother_down<R, SEG>), grid, block, lds, s, la);
+        hipLaunchKernelGGL((k_large_smoother_down<R, SEG>), grid, block, l_down, s, la);
         prof_end(s);
     }
     return hipGetLastError();
 }
 
-constexpr size_t kMaxLdsArena = 60 * 1024;
+size_t arena_bytes_prec(int nx, int ny, bool mixed, int kind) {
+    return mixed ? arena_bytes<float>(nx, ny, kind) : arena_bytes<double>(nx, ny, kind);
+}
 
-}  // namespace
+// arena kinds too large for LDS, and the largest of them (the workspace slot)
+int slot_mask_of(int nx, int ny, bool mixed, size_t* slot_bytes) {
+    int mask = 0;
+    size_t big = 0;
+    for (int k = 0; k < kArKinds; ++k) {
+        const size_t b = arena_bytes_prec(nx, ny, mixed, k);
+        if (b > kMaxLdsArena) {
+            mask |= 1 << k;
+            if (b > big) big = b;
+        }
+    }
+    if (slot_bytes) *slot_bytes = (big + 255) & ~size_t(255);
+    return mask;
+}
 
-int64_t large_blocks(int64_t total) {
-    // about 1024 blocks (four rounds of 256 workgroups), at least 4 steps each
+// Blocks of the time axis: about 2048 one-wave workgroups for nx <= 16 and
+// 1024 otherwise when every per-step kernel keeps its arena in LDS; 2048 when
+// some arena lives in the workspace (more workgroups in flight hide its
+// latency).  At least 4 steps per block.
+int64_t large_blocks(int64_t total, int nx, int ny, bool mixed) {
+    const bool in_lds = slot_mask_of(nx, ny, mixed, nullptr) == 0;
+    const int64_t cap = (in_lds && nx > 16) ? 1024 : 2048;
     int64_t nb = (total + 3) / 4;
-    if (nb > 1024) nb = 1024;
+    if (nb > cap) nb = cap;
     return nb < 1 ? 1 : nb;
 }
 
+}  // namespace
+
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec) {
-    const size_t rs = prec == PKS_FP64 ? 8 : 4;
-    const int64_t nb = large_blocks(total);
+    const bool mixed = prec != PKS_FP64;
+    const size_t rs = mixed ? 4 : 8;
+    const int64_t nb = large_blocks(total, nx, ny, mixed);
     const size_t fw = (size_t)flay(nx).words;
-    const size_t ab = prec == PKS_FP64 ? arena_bytes<double>(nx, ny) : arena_bytes<float>(nx, ny);
-    const size_t slots = ab > kMaxLdsArena ? ab * nb : 0;
-    return 2 * ((rs * fw * nb + 255) & ~size_t(255)) + ((slots + 255) & ~size_t(255));
+    size_t slot = 0;
+    slot_mask_of(nx, ny, mixed, &slot);
+    return 2 * ((rs * fw * nb + 255) & ~size_t(255)) + slot * nb;
 }
 
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
     LargeArgs la;
     la.s = a;
-    la.nblocks = large_blocks(a.total);
+    const int64_t nb_max = large_blocks(a.total, a.nx, a.ny, mixed);
+    la.nblocks = nb_max;
     la.blen = (a.total + la.nblocks - 1) / la.nblocks;
     la.nblocks = (a.total + la.blen - 1) / la.blen;
     const size_t rs = mixed ? 4 : 8;
     const size_t fw = (size_t)flay(a.nx).words;
-    const size_t one = (rs * fw * large_blocks(a.total) + 255) & ~size_t(255);
+    const size_t one = (rs * fw * nb_max + 255) & ~size_t(255);
     char* base = static_cast<char*>(region);
     la.agg[0] = base;
     la.agg[1] = base + one;
     la.final_buf = 0;
-    const size_t ab = mixed ? arena_bytes<float>(a.nx, a.ny) : arena_bytes<double>(a.nx, a.ny);
-    if (ab > kMaxLdsArena) {
-        la.slots = base + 2 * one;
-        la.slot_bytes = ab;
-    } else {
-        la.slots = nullptr;
-        la.slot_bytes = 0;
-    }
+    la.slot_mask = slot_mask_of(a.nx, a.ny, mixed, &la.slot_bytes);
+    la.slots = la.slot_mask ? base + 2 * one : nullptr;
     const bool seg = a.offsets != nullptr;
     if (mixed) return seg ? run_large<float, true>(la, smoother, s) : run_large<float, false>(la, smoother, s);
     return seg ? run_large<double, true>(la, smoother, s) : run_large<double, false>(la, smoother, s);

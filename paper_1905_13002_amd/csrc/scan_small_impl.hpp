@@ -511,25 +511,35 @@ __global__ __launch_bounds__(NT) void k_filter_top(const void* items, int64_t n,
         for (int k = 0; k < Words<N>::F; ++k) sh[wave][k] = w[k];
     }
     __syncthreads();
+    // incoming moments of this thread's first item.  Every prefix that starts
+    // at the first item has A = 0 (it contains step 1), so the waves before
+    // this one and the in-wave prefix are applied in moments form.
+    Moments<N, R> X;
     if (wave > 0) {
-        FElem<N, R> wp;
-        R* wpw = reinterpret_cast<R*>(&wp);
+        {
+            FElem<N, R> x0;
+            R* xw = reinterpret_cast<R*>(&x0);
 #pragma unroll
-        for (int k = 0; k < Words<N>::F; ++k) wpw[k] = sh[0][k];
+            for (int k = 0; k < Words<N>::F; ++k) xw[k] = sh[0][k];
+#pragma unroll
+            for (int r = 0; r < N; ++r) X.m[r] = x0.b[r];
+#pragma unroll
+            for (int r = 0; r < tri(N); ++r) X.P[r] = x0.C[r];
+        }
         for (int w = 1; w < wave; ++w) {
             FElem<N, R> x;
             R* xw = reinterpret_cast<R*>(&x);
 #pragma unroll
             for (int k = 0; k < Words<N>::F; ++k) xw[k] = sh[w][k];
-            fcombine<N, R, G>(wp, x, wp);
+            fcarry<N, R, G>(X, x);
         }
-        fcombine<N, R, G>(wp, ex, ex);
+        fcarry<N, R, G>(X, ex);
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) X.m[r] = ex.b[r];
+#pragma unroll
+        for (int r = 0; r < tri(N); ++r) X.P[r] = ex.C[r];
     }
-    Moments<N, R> X;
-#pragma unroll
-    for (int r = 0; r < N; ++r) X.m[r] = ex.b[r];
-#pragma unroll
-    for (int r = 0; r < tri(N); ++r) X.P[r] = ex.C[r];
     for (int64_t i = i0; i < i1; ++i) {
         store_m(carry, n, i, X);
         FElem<N, R> x;
@@ -753,26 +763,36 @@ __global__ __launch_bounds__(NT) void k_smoother_top(const void* items, int64_t 
         for (int k = 0; k < Words<N>::S; ++k) sh[wave][k] = w[k];
     }
     __syncthreads();
+    // incoming moments of this thread's last item.  Every suffix that ends at
+    // the last item has E = 0 (it contains step T), so the waves after this
+    // one and the in-wave suffix are applied in moments form.
     constexpr int NW = NT / 64;
+    Moments<N, R> Y;
     if (wave < NW - 1) {
-        SElem<N, R> ws;   // product of waves wave+1 .. NW-1
-        R* wsw = reinterpret_cast<R*>(&ws);
+        {
+            SElem<N, R> xl;
+            R* xw = reinterpret_cast<R*>(&xl);
 #pragma unroll
-        for (int k = 0; k < Words<N>::S; ++k) wsw[k] = sh[NW - 1][k];
+            for (int k = 0; k < Words<N>::S; ++k) xw[k] = sh[NW - 1][k];
+#pragma unroll
+            for (int r = 0; r < N; ++r) Y.m[r] = xl.g[r];
+#pragma unroll
+            for (int r = 0; r < tri(N); ++r) Y.P[r] = xl.L[r];
+        }
         for (int w = NW - 2; w > wave; --w) {
             SElem<N, R> x;
             R* xw = reinterpret_cast<R*>(&x);
 #pragma unroll
             for (int k = 0; k < Words<N>::S; ++k) xw[k] = sh[w][k];
-            scombine<N, R, G>(x, ws, ws);
+            scarry<N, R, G>(x, Y);
         }
-        scombine<N, R, G>(ex, ws, ex);
+        scarry<N, R, G>(ex, Y);
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) Y.m[r] = ex.g[r];
+#pragma unroll
+        for (int r = 0; r < tri(N); ++r) Y.P[r] = ex.L[r];
     }
-    Moments<N, R> Y;
-#pragma unroll
-    for (int r = 0; r < N; ++r) Y.m[r] = ex.g[r];
-#pragma unroll
-    for (int r = 0; r < tri(N); ++r) Y.P[r] = ex.L[r];
     for (int64_t i = i1 - 1; i >= i0; --i) {
         store_m(carry, n, i, Y);
         SElem<N, R> x;

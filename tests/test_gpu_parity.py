@@ -307,7 +307,7 @@ def test_batched_B4096_sampled(pks):
 # large state dimensions (workgroup per block element)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx,ny,T", [(5, 2, 777), (6, 6, 500), (8, 3, 1025), (8, 9, 300), (16, 8, 2000),
-                                     (12, 12, 257)])
+                                     (12, 12, 257), (37, 33, 300), (40, 40, 150)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_large_random_models(pks, nx, ny, T, precision):
     rng = np.random.default_rng(900 + 7 * nx + ny)
@@ -344,6 +344,42 @@ def test_large_batched_per_sequence(pks):
     ref = oracle_run(model, y, offsets, per_sequence=True)
     out = gpu_run(pks, model, y, "fp64", offsets=offsets, per_sequence=True)
     assert_parity(out, ref, "fp64", "large batched per-sequence")
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 7])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_tiny_T(pks, T, precision):
+    """Large-state path with fewer steps than the smallest block count
+    (single-step blocks, T = 1: smoothed = filtered)."""
+    rng = np.random.default_rng(77 + T)
+    model = wl.random_stable_model(6, 2, rng, radius=0.9, with_offsets=True)
+    w = wl.single_sequence(model, T, seed=T)
+    check(pks, model, w.y, precision, "large tiny T=%d" % T, floor="rms" if precision == "mixed" else "none")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workload5_full_sampled(pks, precision):
+    """The full large-state batch (64 sequences of T = 8192, nx = 64, ny = 32,
+    one shared model) through a plan, the launch the benchmark times; the first
+    and the last sequence, whole, against the oracle."""
+    w = wl.workload(5)
+    dm = pks.to_device(w.model, per_sequence=w.per_sequence)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    yd = torch.as_tensor(w.y).to("cuda", dt)
+    od = torch.as_tensor(w.offsets).cuda()
+    plan = pks.Plan(dm, yd, od, precision)
+    plan.launch()
+    torch.cuda.synchronize()
+    out = {k: getattr(plan, k).double().cpu().numpy() for k in ("m", "P", "ms", "Ps")}
+    plan.close()
+    picks = [0, w.B - 1]
+    ys = [ref_input(w.y[w.seq(b)], precision) for b in picks]
+    offs = np.concatenate([[0], np.cumsum([len(v) for v in ys])]).astype(np.int64)
+    mo = w.model
+    ref = oracle.kf_rts_batched(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, np.concatenate(ys), offs,
+                                u=mo.u, d=mo.d, per_sequence=False, threads=2)
+    got = {k: np.concatenate([out[k][w.seq(b)] for b in picks]) for k in out}
+    assert_parity(got, ref, precision, "workload 5 full, sequences %s" % picks)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
