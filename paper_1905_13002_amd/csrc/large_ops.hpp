@@ -112,7 +112,7 @@ __device__ __forceinline__ void gemm_mfma_f32(float* C, int ldc, const float* A,
 // everything else on the vector units, with the largest register block that
 // still gives every thread of the workgroup a block of C.
 template <typename R>
-__device__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
+__device__ __forceinline__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
                       R alpha = R(1), const R* D = nullptr, int ldd = 0) {
     const int threads = blockDim.x;
     if constexpr (sizeof(R) == 4) {
@@ -131,31 +131,147 @@ __device__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, i
     __syncthreads();
 }
 
+// Walks the row-major (row, col) pairs of a range with `cols` columns that
+// thread t of a group of g threads owns (elements t, t + g, t + 2g, ...): one
+// division up front, then additions only (the GPU has no integer divide, and
+// a division per element costs more than the arithmetic it indexes).
+struct Walk2 {
+    int r, c, dr, dc, cols;
+    __device__ __forceinline__ Walk2(int t, int g, int cols_) : cols(cols_) {
+        if (cols_ <= 0) {
+            r = 0x7fffffff;
+            c = dr = dc = 0;
+            return;
+        }
+        r = t / cols_;
+        c = t - r * cols_;
+        dr = g / cols_;
+        dc = g - dr * cols_;
+    }
+    __device__ __forceinline__ void next() {
+        r += dr;
+        c += dc;
+        if (c >= cols) {
+            c -= cols;
+            ++r;
+        }
+    }
+};
+
+// C[m x n] = TC(alpha * A B + D), A [m x k] (TA) and B [k x n] (TB), both
+// row-major and untransposed, sums in double: products of storage values with
+// FP64 solution blocks.  C may alias D but not A or B.
+template <int BS, typename TA, typename TB, typename TC>
+__device__ __forceinline__ void gemm_blocks_acc64(TC* C, int ldc, const TA* A, int lda, const TB* B, int ldb, int m,
+                                                  int n, int k, double alpha, const TC* D, int ldd) {
+    const int bm = (m + BS - 1) / BS, bn = (n + BS - 1) / BS;
+    for (int blk = threadIdx.x; blk < bm * bn; blk += blockDim.x) {
+        const int i0 = (blk / bn) * BS, j0 = (blk % bn) * BS;
+        double acc[BS][BS];
+#pragma unroll
+        for (int a = 0; a < BS; ++a)
+#pragma unroll
+            for (int b = 0; b < BS; ++b) acc[a][b] = 0.0;
+#pragma unroll(BS == 4 ? 4 : 8)
+        for (int l = 0; l < k; ++l) {
+            double av[BS], bv[BS];
+#pragma unroll
+            for (int a = 0; a < BS; ++a) av[a] = i0 + a < m ? double(A[(i0 + a) * lda + l]) : 0.0;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) bv[b] = j0 + b < n ? double(B[l * ldb + j0 + b]) : 0.0;
+#pragma unroll
+            for (int a = 0; a < BS; ++a)
+#pragma unroll
+                for (int b = 0; b < BS; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < BS; ++a)
+#pragma unroll
+            for (int b = 0; b < BS; ++b) {
+                const int i = i0 + a, j = j0 + b;
+                if (i < m && j < n) C[i * ldc + j] = TC(alpha * acc[a][b] + (D ? double(D[i * ldd + j]) : 0.0));
+            }
+    }
+}
+
+template <typename TA, typename TB, typename TC>
+__device__ __forceinline__ void gemm_acc64(TC* C, int ldc, const TA* A, int lda, const TB* B, int ldb, int m, int n, int k,
+                           double alpha, const TC* D = nullptr, int ldd = 0) {
+    const int threads = blockDim.x;
+    if (((m + 3) >> 2) * ((n + 3) >> 2) >= threads)
+        gemm_blocks_acc64<4>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
+    else if (((m + 1) >> 1) * ((n + 1) >> 1) >= threads)
+        gemm_blocks_acc64<2>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
+    else
+        gemm_blocks_acc64<1>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
+    __syncthreads();
+}
+
+// The next (up to) four pairs of a walk over `rows` rows; returns how many.
+// Sweeps load the operands of all four before storing any result, so the four
+// independent updates overlap their memory latency.
+__device__ __forceinline__ int take4(Walk2& it, int rows, int (&r)[4], int (&c)[4]) {
+    int k = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        r[u] = it.r < rows ? it.r : 0;
+        c[u] = it.c;
+        if (it.r < rows) {
+            ++k;
+            it.next();
+        }
+    }
+    return k;
+}
+
+// x[j][c] -= (lv(j) / piv) * x[i][c] for the pairs (j = j0 + row, c = c0 + col)
+// of a rows x w walk by one wave (lv(j) = L[j * sl + i * sc] : stride form)
+__device__ __forceinline__ void wave_axpy_rows(const double* Lc, int sl, double inv, const double* xi, double* X, int ldx,
+                                               int j0, int rows, int c0, int w) {
+    const int lane = threadIdx.x & 63;
+    for (Walk2 it(lane, 64, w); it.r < rows;) {
+        int rr[4], cc[4];
+        const int k = take4(it, rows, rr, cc);
+        double lj[4], xp[4], xc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < k) {
+                lj[u] = Lc[(j0 + rr[u]) * sl];
+                xp[u] = xi[c0 + cc[u]];
+                xc[u] = X[(j0 + rr[u]) * ldx + c0 + cc[u]];
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (u < k) X[(j0 + rr[u]) * ldx + c0 + cc[u]] = fma(-lj[u] * inv, xp[u], xc[u]);
+    }
+}
+
 // out = (X + X^T)/2 + D (symmetrisation in double); out may alias D, not X
 template <typename R>
-__device__ void sym_add(R* out, const R* X, const R* D, int n) {
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
+__device__ __forceinline__ void sym_add(R* out, const R* X, const R* D, int n) {
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int i = it.r, j = it.c;
+        const int idx = it.r * it.cols + it.c;
         out[idx] = R(0.5 * (double(X[i * n + j]) + double(X[j * n + i])) + (D ? double(D[idx]) : 0.0));
     }
     __syncthreads();
 }
 
 template <typename T, typename U>
-__device__ void copy(T* dst, const U* src, int count) {
+__device__ __forceinline__ void copy(T* dst, const U* src, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = T(src[i]);
     __syncthreads();
 }
 
 template <typename T>
-__device__ void fill(T* dst, T v, int count) {
+__device__ __forceinline__ void fill(T* dst, T v, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = v;
     __syncthreads();
 }
 
 // y[m] = op(A) x (+ d), A [m x k] (or [k x m] if ta)
 template <typename R>
-__device__ void gemv(R* y, const R* A, int lda, bool ta, const R* x, int m, int k, const R* d = nullptr,
+__device__ __forceinline__ void gemv(R* y, const R* A, int lda, bool ta, const R* x, int m, int k, const R* d = nullptr,
                      R alpha = R(1)) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
         R s = R(0);
@@ -166,18 +282,54 @@ __device__ void gemv(R* y, const R* A, int lda, bool ta, const R* x, int m, int 
     __syncthreads();
 }
 
-// In-place LU solve with partial pivoting (double): a is [n x (n + w)],
-// row stride lda; on return columns n .. n+w-1 hold M^-1 times the right-hand
-// sides.  `red` is a small double scratch (>= 2 * 64 entries).
-__device__ void lu_solve(double* a, int lda, int n, int w, int* piv_sh) {
-    const int tid = threadIdx.x;
-    const int width = n + w;
-    for (int k = 0; k < n; ++k) {
-        // pivot: argmax |a[r][k]|, r >= k, by wave 0 (n <= 64)
-        if (tid < 64) {
-            const int r = k + tid;
-            double v = r < n ? fabs(a[r * lda + k]) : -1.0;
-            int idx = r;
+// Makes the LDS and global writes of one wave visible to its other lanes (a
+// barrier for the lanes of one wave only; the other waves are not involved).
+__device__ __forceinline__ void wave_sync_mem() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The right-hand-side columns [c0, c1) that wave `wave` of `nw` owns.
+__device__ __forceinline__ void wave_columns(int r, int& c0, int& c1) {
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6;
+    const int per = (r + nw - 1) / nw;
+    c0 = wave * per;
+    c1 = c0 + per < r ? c0 + per : r;
+}
+
+// Upper-triangular back substitution U x = z on columns [c0, c1) of X by one
+// wave: at step i row i is final; the rows above are updated with it scaled by
+// 1 / u_ii on the fly, and the scaled rows are written after the sweep.
+__device__ __forceinline__ void wave_upper_solve(const double* U, int ldu, int n, double* X, int ldx, int c0, int c1) {
+    const int lane = threadIdx.x & 63, w = c1 - c0;
+    for (int i = n - 1; i > 0; --i) {
+        const double inv = rcp64l(U[i * ldu + i]);
+        // rows 0 .. i-1: X[r][c] -= U[r][i] / u_ii * X[i][c]
+        wave_axpy_rows(U + i, ldu, inv, X + i * ldx, X, ldx, 0, i, c0, w);
+        wave_sync_mem();
+    }
+    for (Walk2 it(lane, 64, w); it.r < n; it.next()) {
+        const int r = it.r, c = c0 + it.c;
+        X[r * ldx + c] *= rcp64l(U[r * ldu + r]);
+    }
+    wave_sync_mem();
+}
+
+// In-place LU solve with partial pivoting (double): a is [n x (n + w)], row
+// stride lda, n <= 64; on return columns n .. n+w-1 hold M^-1 times the
+// right-hand sides.  Wave 0 factors M (pivot rows exchanged across M's
+// columns, multipliers kept unscaled below the diagonal); then every wave
+// applies the exchanges and both triangular sweeps to its own right-hand-side
+// columns, synchronising only its own lanes.  piv_sh holds >= n + 1 ints.
+__device__ __forceinline__ void lu_solve(double* a, int lda, int n, int w, int* piv_sh) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < 64) {
+        for (int k = 0; k < n; ++k) {
+            // pivot: argmax |a[r][k]|, r >= k (one row per lane)
+            const int r0 = k + lane;
+            double v = r0 < n ? fabs(a[r0 * lda + k]) : -1.0;
+            int idx = r0;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 const double ov = __shfl_xor(v, off, 64);
@@ -187,113 +339,153 @@ __device__ void lu_solve(double* a, int lda, int n, int w, int* piv_sh) {
                     idx = oi;
                 }
             }
-            if (tid == 0) *piv_sh = idx;
+            const int p = idx;
+            if (lane == 0) piv_sh[k] = p;
+            if (p != k) {
+                for (int c = lane; c < n; c += 64) {
+                    const double t = a[k * lda + c];
+                    a[k * lda + c] = a[p * lda + c];
+                    a[p * lda + c] = t;
+                }
+                wave_sync_mem();
+            }
+            // trailing update of M with the unscaled multipliers a[r][k] / a[k][k]
+            const double inv = rcp64l(a[k * lda + k]);
+            const int rows = n - k - 1;
+            // rows k+1 .. n-1 of columns k+1 .. n-1 (column offset k+1)
+            wave_axpy_rows(a + k, lda, inv, a + k * lda + k + 1, a + k + 1, lda, k + 1, rows, 0, rows);
+            wave_sync_mem();
         }
-        __syncthreads();
-        const int p = *piv_sh;
-        if (p != k) {
-            for (int c = tid; c < width; c += blockDim.x) {
-                const double t = a[k * lda + c];
-                a[k * lda + c] = a[p * lda + c];
-                a[p * lda + c] = t;
+    }
+    __syncthreads();
+    int c0, c1;
+    wave_columns(w, c0, c1);
+    c0 += n;
+    c1 += n;
+    const int wc = c1 - c0;
+    if (wc > 0) {
+        // row exchanges, in order
+        for (int k = 0; k < n; ++k) {
+            const int p = piv_sh[k];
+            if (p != k) {
+                for (int c = c0 + lane; c < c1; c += 64) {
+                    const double t = a[k * lda + c];
+                    a[k * lda + c] = a[p * lda + c];
+                    a[p * lda + c] = t;
+                }
+                wave_sync_mem();
             }
         }
-        __syncthreads();
-        const double inv = rcp64l(a[k * lda + k]);
-        // multipliers then trailing update (rows k+1.., columns k+1..)
-        const int rows = n - k - 1, cols = width - k - 1;
-        for (int idx = tid; idx < rows * cols; idx += blockDim.x) {
-            const int r = k + 1 + idx / cols, c = k + 1 + idx % cols;
-            const double f = a[r * lda + k] * inv;
-            a[r * lda + c] = fma(-f, a[k * lda + c], a[r * lda + c]);
+        // unit lower-triangular forward sweep
+        for (int k = 0; k + 1 < n; ++k) {
+            const double inv = rcp64l(a[k * lda + k]);
+            // rows k+1 .. n-1: a[r][c] -= a[r][k] / a_kk * a[k][c]
+            wave_axpy_rows(a + k, lda, inv, a + k * lda, a, lda, k + 1, n - k - 1, c0, wc);
+            wave_sync_mem();
         }
-        __syncthreads();
-    }
-    // back substitution U x = z, all right-hand sides at once: at step i the
-    // entries of row i are final; rows above it are updated with row i scaled
-    // by 1 / u_ii (scaled copies of the rows are written after the sweep)
-    for (int i = n - 1; i > 0; --i) {
-        const double inv = rcp64l(a[i * lda + i]);
-        for (int idx = tid; idx < i * w; idx += blockDim.x) {
-            const int r = idx / w, c = n + idx % w;
-            a[r * lda + c] = fma(-a[r * lda + i] * inv, a[i * lda + c], a[r * lda + c]);
-        }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < n * w; idx += blockDim.x) {
-        const int r = idx / w, c = n + idx % w;
-        a[r * lda + c] *= rcp64l(a[r * lda + r]);
+        wave_upper_solve(a, lda, n, a, lda, c0, c1);
     }
     __syncthreads();
 }
 
-// In-place lower Cholesky factor (double) of the n x n SPD matrix S (stride
-// lds); returns false (workgroup-uniform) if a pivot is not positive.  At step
-// j column j is final; the trailing lower triangle is updated with that column
-// scaled by 1 / sqrt(s_jj), and the scaled columns are written after the loop.
-__device__ bool cholesky(double* S, int lds, int n, int* flag_sh) {
+// In-place Cholesky factor (double) of the n x n SPD matrix S (stride lds):
+// on return the lower triangle holds L and the upper triangle L^T (so both
+// triangular sweeps read rows).  Returns false (workgroup-uniform) if a pivot
+// is not positive.  At step j row and column j are final; the whole trailing
+// square is updated with l_i l_l, where l = s_.j / sqrt(s_jj) is formed on
+// the fly from the column (for l_i) and the row (for l_l): every access runs
+// along a row, and the square stays bitwise symmetric (l_i l_l = l_l l_i).
+// Up to n = 32 (or in a one-wave workgroup) wave 0 alone factors,
+// synchronising its own lanes; larger matrices use every wave with a barrier
+// per column.  flag_sh holds one int.
+__device__ __forceinline__ bool cholesky(double* S, int lds, int n, int* flag_sh) {
     const int tid = threadIdx.x;
-    bool ok = true;
-    for (int j = 0; j < n; ++j) {
-        const double d = S[j * lds + j];
-        ok = ok && d > 0.0;
-        const double inv = rcp64l(d);               // 1 / s_jj = (1 / sqrt(s_jj))^2
-        const int m = n - j - 1;
-        for (int idx = tid; idx < m * m; idx += blockDim.x) {
-            const int i = j + 1 + idx / m, l = j + 1 + idx % m;
-            if (l <= i) S[i * lds + l] = fma(-S[i * lds + j] * inv, S[l * lds + j], S[i * lds + l]);
+    const bool one_wave = n <= 32 || blockDim.x == 64;
+    const int g = one_wave ? 64 : (int)blockDim.x;
+    if (!one_wave || tid < 64) {
+        bool ok = true;
+        for (int j = 0; j < n; ++j) {
+            const double d = S[j * lds + j];
+            ok = ok && d > 0.0;
+            const double isq = rcp64l(sqrt(d));
+            const int m = n - j - 1;
+            const double* col_row = S + j * lds + j + 1;      // row j right of the diagonal = column j below it
+            for (Walk2 it(tid, g, m); it.r < m;) {
+                int rr[4], cc[4];
+                const int k = take4(it, m, rr, cc);
+                double li[4], ll[4], x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < k) {
+                        li[u] = S[(j + 1 + rr[u]) * lds + j] * isq;
+                        ll[u] = col_row[cc[u]] * isq;
+                        x[u] = S[(j + 1 + rr[u]) * lds + j + 1 + cc[u]];
+                    }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < k) S[(j + 1 + rr[u]) * lds + j + 1 + cc[u]] = fma(-li[u], ll[u], x[u]);
+            }
+            if (one_wave) wave_sync_mem();
+            else __syncthreads();
         }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < n * n; idx += blockDim.x) {
-        const int i = idx / n, j = idx % n;
-        if (j < i) S[i * lds + j] *= rcp64l(sqrt(S[j * lds + j]));
+        for (Walk2 it(tid, g, n); it.r < n; it.next()) {
+            const int i = it.r, j = it.c;
+            if (j < i) {
+                const double v = S[i * lds + j] * rcp64l(sqrt(S[j * lds + j]));
+                S[i * lds + j] = v;
+                S[j * lds + i] = v;
+            }
+        }
+        if (one_wave) wave_sync_mem();
+        else __syncthreads();
+        for (int j = tid; j < n; j += g) S[j * lds + j] = sqrt(S[j * lds + j]);
+        if (tid == 0) *flag_sh = ok ? 0 : 1;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += blockDim.x) S[j * lds + j] = sqrt(S[j * lds + j]);
+    const bool ok = *flag_sh == 0;
     __syncthreads();
-    (void)flag_sh;
     return ok;
 }
 
-// X [n x r] (stride ldx) <- (L L^T)^-1 X, all columns at once: one barrier per
-// pivot row in each of the two triangular sweeps
-__device__ void chol_solve(const double* L, int ldl, int n, double* X, int ldx, int r) {
-    const int tid = threadIdx.x;
-    // L z = x
-    for (int i = 0; i + 1 < n; ++i) {
-        const double inv = rcp64l(L[i * ldl + i]);
-        const int rows = n - i - 1;
-        for (int idx = tid; idx < rows * r; idx += blockDim.x) {
-            const int j = i + 1 + idx / r, c = idx % r;
-            X[j * ldx + c] = fma(-L[j * ldl + i] * inv, X[i * ldx + c], X[j * ldx + c]);
+// X [n x r] (stride ldx) <- (L L^T)^-1 X for a factor from cholesky() (L in
+// the lower triangle, L^T in the upper): the columns are split over the
+// waves, each wave runs both triangular sweeps on its own columns
+__device__ __forceinline__ void chol_solve(const double* L, int ldl, int n, double* X, int ldx, int r) {
+    const int lane = threadIdx.x & 63;
+    int c0, c1;
+    wave_columns(r, c0, c1);
+    const int w = c1 - c0;
+    if (w > 0) {
+        // L z = x
+        for (int i = 0; i + 1 < n; ++i) {
+            const double inv = rcp64l(L[i * ldl + i]);
+            // rows i+1 .. n-1: X[j][c] -= L[j][i] / l_ii * X[i][c]  (L[j][i] = upper row i)
+            wave_axpy_rows(L + i * ldl, 1, inv, X + i * ldx, X, ldx, i + 1, n - i - 1, c0, w);
+            wave_sync_mem();
         }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < n * r; idx += blockDim.x) {
-        const int j = idx / r, c = idx % r;
-        X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
-    }
-    __syncthreads();
-    // L^T x = z
-    for (int i = n - 1; i > 0; --i) {
-        const double inv = rcp64l(L[i * ldl + i]);
-        for (int idx = tid; idx < i * r; idx += blockDim.x) {
-            const int j = idx / r, c = idx % r;
-            X[j * ldx + c] = fma(-L[i * ldl + j] * inv, X[i * ldx + c], X[j * ldx + c]);
+        for (Walk2 it(lane, 64, w); it.r < n; it.next()) {
+            const int j = it.r, c = c0 + it.c;
+            X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
         }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < n * r; idx += blockDim.x) {
-        const int j = idx / r, c = idx % r;
-        X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
+        wave_sync_mem();
+        // L^T x = z
+        for (int i = n - 1; i > 0; --i) {
+            const double inv = rcp64l(L[i * ldl + i]);
+            // rows 0 .. i-1: X[j][c] -= L[i][j] / l_ii * X[i][c]  (L^T: stride 1 along j)
+            wave_axpy_rows(L + i * ldl, 1, inv, X + i * ldx, X, ldx, 0, i, c0, w);
+            wave_sync_mem();
+        }
+        for (Walk2 it(lane, 64, w); it.r < n; it.next()) {
+            const int j = it.r, c = c0 + it.c;
+            X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
+        }
     }
     __syncthreads();
 }
 
 // workgroup-uniform test: every entry of X is zero
 template <typename R>
-__device__ bool all_zero(const R* X, int count, int* flag_sh) {
+__device__ __forceinline__ bool all_zero(const R* X, int count, int* flag_sh) {
     if (threadIdx.x == 0) *flag_sh = 1;
     __syncthreads();
     for (int i = threadIdx.x; i < count; i += blockDim.x)

@@ -159,18 +159,19 @@ struct LargeArgs {
     size_t slot_bytes;
 };
 
-__device__ __forceinline__ char* arena_base(const LargeArgs& a, char* lds, int kind) {
-    return ((a.slot_mask >> kind) & 1) ? a.slots + (size_t)blockIdx.x * a.slot_bytes : lds;
-}
-
-// context of one kernel: dimensions, record layouts and its arena
+// context of one kernel: dimensions, record layouts and its arena.  LDSA:
+// the arena is the kernel's LDS (the base then comes straight from the shared
+// array, so the operators, all inlined, address it with LDS instructions);
+// else the block's workspace slot.
+template <bool LDSA>
 __device__ __forceinline__ void make_ctx(Ctx& c, const LargeArgs& la, char* lds, int kind) {
     c.n = la.s.nx;
     c.ny = la.s.ny;
     c.fl = flay(c.n);
     c.sl = slay(c.n);
     c.ar = arena_layout(c.n, c.ny, kind);
-    c.base = arena_base(la, lds, kind);
+    if constexpr (LDSA) c.base = lds;
+    else c.base = la.slots + (size_t)blockIdx.x * la.slot_bytes;
 }
 
 // sequence lookup (workgroup-uniform)
@@ -196,12 +197,12 @@ __device__ SeqL seq_at(const ScanArgs& a, int64_t k) {
     return s;
 }
 template <bool SEG>
-__device__ void seq_fwd(const ScanArgs& a, SeqL& s, int64_t k) {
+__device__ __forceinline__ void seq_fwd(const ScanArgs& a, SeqL& s, int64_t k) {
     if (!SEG) return;
     while (k >= s.end && s.b < a.B - 1) { ++s.b; s.start = s.end; s.end = a.offsets[s.b + 1]; }
 }
 template <bool SEG>
-__device__ void seq_bwd(const ScanArgs& a, SeqL& s, int64_t k) {
+__device__ __forceinline__ void seq_bwd(const ScanArgs& a, SeqL& s, int64_t k) {
     if (!SEG) return;
     while (k < s.start && s.b > 0) { --s.b; s.end = s.start; s.start = a.offsets[s.b]; }
 }
@@ -215,7 +216,7 @@ __device__ void seq_bwd(const ScanArgs& a, SeqL& s, int64_t k) {
 //   eta = X1^T w + eta_i, J = sym(X1^T JA) + J_i.   Result in `out`, which may
 // be ei itself.  Z and T are n x n scratch.
 template <typename R>
-__device__ void fcombine_tail(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, R* out, R* Z, R* T) {
+__device__ __forceinline__ void fcombine_tail(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, R* out, R* Z, R* T) {
     const int n = c.n;
     R* X1 = c.r<R>(c.ar.X1);
     R* x2 = c.r<R>(c.ar.x2);
@@ -235,7 +236,7 @@ __device__ void fcombine_tail(const Ctx& c, const R* ei, const R* Aj, const R* b
 // full Lemma 2: out = ei (x) ej; ej given by its parts (matrices may live in
 // the model constants)
 template <typename R>
-__device__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, const R* etaj,
+__device__ __forceinline__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, const R* etaj,
                             const R* Jj, R* out, int* ish) {
     const int n = c.n, lda = 3 * n + 1;
     double* aug = c.d<R>(c.ar.aug);
@@ -244,8 +245,9 @@ __device__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj,
     // M = I + C_i J_j (products in R)
     gemmR<R>(Z, n, ei + c.fl.C, n, false, Jj, n, false, n, n, n);
     gemv<R>(v, ei + c.fl.C, n, false, etaj, n, n, ei + c.fl.b);          // b_i + C_i eta_j
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         aug[r * lda + q] = double(Z[idx]) + (r == q ? 1.0 : 0.0);
         aug[r * lda + n + q] = double(ei[c.fl.A + idx]);
         aug[r * lda + 2 * n + 1 + q] = double(ei[c.fl.C + idx]);
@@ -256,8 +258,9 @@ __device__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj,
     R* X1 = c.r<R>(c.ar.X1);
     R* x2 = c.r<R>(c.ar.x2);
     R* X3 = c.r<R>(c.ar.X3);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         X1[idx] = R(aug[r * lda + n + q]);
         X3[idx] = R(aug[r * lda + 2 * n + 1 + q]);
     }
@@ -271,7 +274,7 @@ __device__ void fcombine_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj,
 
 // Lemma 2 with ej a single step k > 1 (J_j = W G, rank ny < nx)
 template <typename R>
-__device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, const R* etaj,
+__device__ __forceinline__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const R* bj, const R* Cj, const R* etaj,
                                   const R* Gm, const R* Wm, const double* S, R* out, int* ish) {
     const int n = c.n, m = c.ny, rhs = 2 * n + 1;
     R* Y = c.r<R>(c.ar.Y);              // [n x m]
@@ -288,12 +291,14 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     gemmR<R>(c.r<R>(c.ar.X1), m, Gm, n, false, Y, m, false, m, m, n);
     {
         const R* GY = c.r<R>(c.ar.X1);
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int r = idx / m, q = idx % m;
+        for (Walk2 it(threadIdx.x, blockDim.x, m); it.r < m; it.next()) {
+            const int r = it.r, q = it.c;
+            const int idx = it.r * it.cols + it.c;
             sg[idx] = S[idx] + 0.5 * (double(GY[r * m + q]) + double(GY[q * m + r]));
         }
-        for (int idx = threadIdx.x; idx < m * rhs; idx += blockDim.x) {
-            const int r = idx / rhs, q = idx % rhs;
+        for (Walk2 it(threadIdx.x, blockDim.x, rhs); it.r < m; it.next()) {
+            const int r = it.r, q = it.c;
+            const int idx = it.r * it.cols + it.c;
             rh[idx] = q < n ? double(GA[r * n + q]) : (q == n ? double(Gv[r]) : double(Y[(q - n - 1) * m + r]));
         }
         __syncthreads();
@@ -303,27 +308,14 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
     R* X1 = c.r<R>(c.ar.X1);
     R* x2 = c.r<R>(c.ar.x2);
     R* X3 = c.r<R>(c.ar.X3);
-    // X1 = A_i - Y T1 ; x2 = v - Y t2 ; X3 = sym(C_i - Y Zt)   (T1, t2, Zt in rh)
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
-        double a = double(ei[c.fl.A + idx]), p = 0.0, s = 0.0;
-#pragma unroll 8
-        for (int l = 0; l < m; ++l) {
-            a = fma(-double(Y[r * m + l]), rh[l * rhs + q], a);
-            p = fma(double(Y[r * m + l]), rh[l * rhs + n + 1 + q], p);
-            s = fma(double(Y[q * m + l]), rh[l * rhs + n + 1 + r], s);
-        }
-        X1[idx] = R(a);
-        X3[idx] = R(double(ei[c.fl.C + idx]) - 0.5 * (p + s));
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        double a = double(v[r]);
-#pragma unroll 8
-        for (int l = 0; l < m; ++l) a = fma(-double(Y[r * m + l]), rh[l * rhs + n], a);
-        x2[r] = R(a);
-    }
-    __syncthreads();
+    // X1 = A_i - Y T1 ; x2 = v - Y t2 ; X3 = C_i - sym(Y Zt)   (T1, t2, Zt in rh),
+    // products of Y with the FP64 solution summed in double.  Y Zt goes to the
+    // JA buffer, free until JA is formed.
+    gemm_acc64<R, double, R>(X1, n, Y, m, rh, rhs, n, n, m, -1.0, ei + c.fl.A, n);
+    gemm_acc64<R, double, R>(x2, 1, Y, m, rh + n, rhs, n, 1, m, -1.0, v, 1);
+    R* YZ = c.r<R>(c.ar.JA);
+    gemm_acc64<R, double, R>(YZ, n, Y, m, rh + n + 1, rhs, n, n, m, -1.0);
+    sym_add<R>(X3, YZ, ei + c.fl.C, n);
     // w = eta_j - W (G b_i) ; JA = W (G A_i)
     gemv<R>(Gv, Gm, n, false, ei + c.fl.b, m, n);                           // G b_i (reuses Gv)
     gemv<R>(c.r<R>(c.ar.w), Wm, m, false, Gv, n, m, etaj, R(-1));
@@ -335,7 +327,7 @@ __device__ void fcombine_fresh_wg(const Ctx& c, const R* ei, const R* Aj, const 
 
 // moments X (prefix with A = 0) <- X (x) a_j
 template <typename R>
-__device__ void fcarry_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R* Cj, const R* etaj, const R* Jj,
+__device__ __forceinline__ void fcarry_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R* Cj, const R* etaj, const R* Jj,
                           int* ish) {
     const int n = c.n, lda = 2 * n + 1;
     R* m = X;
@@ -345,8 +337,9 @@ __device__ void fcarry_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R*
     R* v = c.r<R>(c.ar.w);
     gemmR<R>(Z, n, P, n, false, Jj, n, false, n, n, n);
     gemv<R>(v, P, n, false, etaj, n, n, m);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         aug[r * lda + q] = double(Z[idx]) + (r == q ? 1.0 : 0.0);
         aug[r * lda + n + 1 + q] = double(P[idx]);
     }
@@ -355,8 +348,9 @@ __device__ void fcarry_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R*
     lu_solve(aug, lda, n, n + 1, ish);
     R* x2 = c.r<R>(c.ar.x2);
     R* X3 = c.r<R>(c.ar.X3);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         X3[idx] = R(aug[r * lda + n + 1 + q]);
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x) x2[r] = R(aug[r * lda + n]);
@@ -369,7 +363,7 @@ __device__ void fcarry_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R*
 }
 
 template <typename R>
-__device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R* Cj, const R* etaj,
+__device__ __forceinline__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, const R* Cj, const R* etaj,
                                 const R* Gm, const double* S, int* ish) {
     const int n = c.n, m = c.ny, rhs = n + 1;
     R* mm = X;
@@ -385,12 +379,14 @@ __device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, co
     gemmR<R>(c.r<R>(c.ar.Z), m, Gm, n, false, Y, m, false, m, m, n);        // G P G^T
     {
         const R* GY = c.r<R>(c.ar.Z);
-        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-            const int r = idx / m, q = idx % m;
+        for (Walk2 it(threadIdx.x, blockDim.x, m); it.r < m; it.next()) {
+            const int r = it.r, q = it.c;
+            const int idx = it.r * it.cols + it.c;
             sg[idx] = S[idx] + 0.5 * (double(GY[r * m + q]) + double(GY[q * m + r]));
         }
-        for (int idx = threadIdx.x; idx < m * rhs; idx += blockDim.x) {
-            const int r = idx / rhs, q = idx % rhs;
+        for (Walk2 it(threadIdx.x, blockDim.x, rhs); it.r < m; it.next()) {
+            const int r = it.r, q = it.c;
+            const int idx = it.r * it.cols + it.c;
             rh[idx] = q == 0 ? double(Gv[r]) : double(Y[(q - 1) * m + r]);
         }
         __syncthreads();
@@ -399,26 +395,14 @@ __device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, co
     chol_solve(sg, m, m, rh, rhs, rhs);
     R* x2 = c.r<R>(c.ar.x2);
     R* X3 = c.r<R>(c.ar.X3);
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
-        double p = 0.0, s = 0.0;
-#pragma unroll 8
-        for (int l = 0; l < m; ++l) {
-            p = fma(double(Y[r * m + l]), rh[l * rhs + 1 + q], p);
-            s = fma(double(Y[q * m + l]), rh[l * rhs + 1 + r], s);
-        }
-        X3[idx] = R(double(P[idx]) - 0.5 * (p + s));
-    }
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        double a = double(v[r]);
-#pragma unroll 8
-        for (int l = 0; l < m; ++l) a = fma(-double(Y[r * m + l]), rh[l * rhs], a);
-        x2[r] = R(a);
-    }
-    __syncthreads();
-    gemv<R>(mm, Aj, n, false, x2, n, n, bj);
     R* T = c.r<R>(c.ar.T);
     R* Z = c.r<R>(c.ar.Z);
+    // X3 = P - sym(Y Zt), x2 = v - Y t (Zt, t in rh; sums in double); Y Zt
+    // goes to T, free until the output products
+    gemm_acc64<R, double, R>(T, n, Y, m, rh + 1, rhs, n, n, m, -1.0);
+    gemm_acc64<R, double, R>(x2, 1, Y, m, rh, rhs, n, 1, m, -1.0, v, 1);
+    sym_add<R>(X3, T, P, n);
+    gemv<R>(mm, Aj, n, false, x2, n, n, bj);
     gemmR<R>(T, n, Aj, n, false, X3, n, false, n, n, n);
     gemmR<R>(Z, n, T, n, false, Aj, n, true, n, n, n);
     sym_add<R>(P, Z, Cj, n);
@@ -426,7 +410,7 @@ __device__ void fcarry_fresh_wg(const Ctx& c, R* X, const R* Aj, const R* bj, co
 
 // b_k = c + K y_k, eta_k = w + W y_k (or b_1 = c1 + K1 y_1, eta_1 = 0) into xv
 template <typename R>
-__device__ void build_fvec(const Ctx& c, const R* cst, const ConstLayout& CL, const R* yk, bool first) {
+__device__ __forceinline__ void build_fvec(const Ctx& c, const R* cst, const ConstLayout& CL, const R* yk, bool first) {
     const int n = c.n, ny = c.ny;
     R* bk = c.r<R>(c.ar.xv);
     R* ek = bk + n;
@@ -448,13 +432,13 @@ __device__ void build_fvec(const Ctx& c, const R* cst, const ConstLayout& CL, co
 // ---------------------------------------------------------------------------
 // filter kernels
 // ---------------------------------------------------------------------------
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_filter_reduce(LargeArgs la) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArFRed);
+    make_ctx<LDSA>(c, la, lds, kArFRed);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const bool lowrank = a.ny < a.nx;
@@ -503,13 +487,13 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_reduce(LargeArgs la) 
 }
 
 // out[i] = in[i - d] (x) in[i] (i >= d), else in[i]
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_filter_ks(LargeArgs la, const void* in_, void* out_, int64_t d) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArFKs);
+    make_ctx<LDSA>(c, la, lds, kArFKs);
     const int64_t i = blockIdx.x;
     const int fw = c.fl.words;
     const R* in = static_cast<const R*>(in_);
@@ -533,13 +517,13 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_ks(LargeArgs la, cons
     }
 }
 
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_filter_down(LargeArgs la) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArFDown);
+    make_ctx<LDSA>(c, la, lds, kArFDown);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const bool lowrank = a.ny < a.nx;
@@ -586,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_down(LargeArgs la) {
 // Lemma 3 element of step k (not last) from moments (m, P) at `mom`, into e:
 // E = P F^T (F P F^T + Q)^-1, g = m - E (F m + u), L = sym(P - E F P)
 template <typename R>
-__device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL, const R* m, const R* P, R* e,
+__device__ __forceinline__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL, const R* m, const R* P, R* e,
                                int* status, int b, int* ish) {
     const int n = c.n;
     const R* F = cst + CL.F;
@@ -596,8 +580,9 @@ __device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL
     double* Et = S + n * n;
     gemmR<R>(V, n, F, n, false, P, n, false, n, n, n);                 // F P
     gemmR<R>(Z, n, V, n, false, F, n, true, n, n, n);                  // F P F^T
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         S[idx] = 0.5 * (double(Z[r * n + q]) + double(Z[q * n + r])) + double(cst[CL.Q + idx]);
         Et[idx] = double(V[idx]);
     }
@@ -605,8 +590,9 @@ __device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL
     const bool ok = cholesky(S, n, n, ish);
     if (!ok && threadIdx.x == 0) atomicMin(status, b);
     chol_solve(S, n, n, Et, n, n);                                        // (F P F^T + Q)^-1 F P = E^T
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         e[c.sl.E + idx] = R(Et[q * n + r]);
     }
     __syncthreads();
@@ -614,8 +600,9 @@ __device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL
     gemv<R>(p, F, n, false, m, n, n, cst + CL.u);                        // F m + u
     gemv<R>(e + c.sl.g, e + c.sl.E, n, false, p, n, n, m, R(-1));        // m - E p
     gemmR<R>(Z, n, e + c.sl.E, n, false, V, n, false, n, n, n);         // E F P
-    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-        const int r = idx / n, q = idx % n;
+    for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
+        const int r = it.r, q = it.c;
+        const int idx = it.r * it.cols + it.c;
         e[c.sl.L + idx] = R(double(P[idx]) - 0.5 * (double(Z[r * n + q]) + double(Z[q * n + r])));
     }
     __syncthreads();
@@ -623,7 +610,7 @@ __device__ void build_selem_wg(const Ctx& c, const R* cst, const ConstLayout& CL
 
 // out = ei (x) ej (Lemma 4)
 template <typename R>
-__device__ void scombine_wg(const Ctx& c, const R* ei, const R* ej, R* out) {
+__device__ __forceinline__ void scombine_wg(const Ctx& c, const R* ei, const R* ej, R* out) {
     const int n = c.n;
     R* T = c.r<R>(c.ar.T);
     R* Z = c.r<R>(c.ar.Z);
@@ -636,7 +623,7 @@ __device__ void scombine_wg(const Ctx& c, const R* ei, const R* ej, R* out) {
 
 // moments Y (suffix with E = 0) <- ei (x) Y
 template <typename R>
-__device__ void scarry_wg(const Ctx& c, const R* ei, R* Y) {
+__device__ __forceinline__ void scarry_wg(const Ctx& c, const R* ei, R* Y) {
     const int n = c.n;
     R* T = c.r<R>(c.ar.T);
     R* Z = c.r<R>(c.ar.Z);
@@ -649,7 +636,7 @@ __device__ void scarry_wg(const Ctx& c, const R* ei, R* Y) {
 }
 
 template <typename R>
-__device__ void load_moments(const Ctx& c, const ScanArgs& a, int64_t k, R* mom) {
+__device__ __forceinline__ void load_moments(const Ctx& c, const ScanArgs& a, int64_t k, R* mom) {
     const int n = c.n;
     const R* m = static_cast<const R*>(a.m);
     const R* P = static_cast<const R*>(a.P);
@@ -658,13 +645,13 @@ __device__ void load_moments(const Ctx& c, const ScanArgs& a, int64_t k, R* mom)
     __syncthreads();
 }
 
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_smoother_reduce(LargeArgs la) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArSRed);
+    make_ctx<LDSA>(c, la, lds, kArSRed);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const int64_t k0 = blockIdx.x * la.blen;
@@ -703,14 +690,14 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_reduce(LargeArgs la
 }
 
 // out[i] = in[i] (x) in[i + d] (i + d < n), else in[i]
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_smoother_ks(LargeArgs la, const void* in_, void* out_, int64_t d,
                                                                int64_t nb) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArSKs);
+    make_ctx<LDSA>(c, la, lds, kArSKs);
     const int64_t i = blockIdx.x;
     const int sw = c.sl.words;
     const R* in = static_cast<const R*>(in_);
@@ -723,13 +710,13 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_ks(LargeArgs la, co
     scombine_wg<R>(c, ei, in + (size_t)(i + d) * sw, out);
 }
 
-template <typename R, bool SEG>
+template <typename R, bool SEG, bool LDSA>
 __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ int ish[4];
+    __shared__ int ish[72];   // flags; LU pivot rows
     const ScanArgs& a = la.s;
     Ctx c;
-    make_ctx(c, la, lds, kArSDown);
+    make_ctx<LDSA>(c, la, lds, kArSDown);
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = c.n, n2 = n * n;
     const int64_t blk = blockIdx.x;
@@ -775,7 +762,7 @@ __host__ __device__ inline int large_threads(int nx) { return nx <= 16 ? 64 : (n
 
 // arenas up to this size live in LDS (gfx950 addresses 160 KB of LDS per
 // workgroup; the kernels' static scratch is a few bytes)
-constexpr size_t kMaxLdsArena = 160 * 1024 - 256;
+constexpr size_t kMaxLdsArena = 160 * 1024 - 512;
 
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds) {
@@ -792,48 +779,53 @@ size_t kind_lds(const LargeArgs& la, int kind) {
 template <typename R, bool SEG>
 hipError_t run_large(LargeArgs la, bool smoother, hipStream_t s) {
     const dim3 grid((unsigned)la.nblocks), block(large_threads(la.s.nx));
+    const auto in_lds = [&](int kind) { return ((la.slot_mask >> kind) & 1) == 0; };
     hipError_t e;
     if (!smoother) {
         const size_t l_red = kind_lds<R>(la, kArFRed), l_ks = kind_lds<R>(la, kArFKs),
                      l_down = kind_lds<R>(la, kArFDown);
-        if ((e = allow_lds(k_large_filter_reduce<R, SEG>, l_red)) != hipSuccess) return e;
-        if ((e = allow_lds(k_large_filter_ks<R, SEG>, l_ks)) != hipSuccess) return e;
-        if ((e = allow_lds(k_large_filter_down<R, SEG>, l_down)) != hipSuccess) return e;
+        auto kred = in_lds(kArFRed) ? k_large_filter_reduce<R, SEG, true> : k_large_filter_reduce<R, SEG, false>;
+        auto kks = in_lds(kArFKs) ? k_large_filter_ks<R, SEG, true> : k_large_filter_ks<R, SEG, false>;
+        auto kdown = in_lds(kArFDown) ? k_large_filter_down<R, SEG, true> : k_large_filter_down<R, SEG, false>;
+        if ((e = allow_lds(kred, l_red)) != hipSuccess) return e;
+        if ((e = allow_lds(kks, l_ks)) != hipSuccess) return e;
+        if ((e = allow_lds(kdown, l_down)) != hipSuccess) return e;
         prof_begin("k_large_filter_reduce", s);
-        hipLaunchKernelGGL((k_large_filter_reduce<R, SEG>), grid, block, l_red, s, la);
+        hipLaunchKernelGGL(kred, grid, block, l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_filter_ks", s);
-            hipLaunchKernelGGL((k_large_filter_ks<R, SEG>), grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1],
-                               d);
+            hipLaunchKernelGGL(kks, grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_filter_down", s);
-        hipLaunchKernelGGL((k_large_filter_down<R, SEG>), grid, block, l_down, s, la);
+        hipLaunchKernelGGL(kdown, grid, block, l_down, s, la);
         prof_end(s);
     } else {
         const size_t l_red = kind_lds<R>(la, kArSRed), l_ks = kind_lds<R>(la, kArSKs),
                      l_down = kind_lds<R>(la, kArSDown);
-        if ((e = allow_lds(k_large_smoother_reduce<R, SEG>, l_red)) != hipSuccess) return e;
-        if ((e = allow_lds(k_large_smoother_ks<R, SEG>, l_ks)) != hipSuccess) return e;
-        if ((e = allow_lds(k_large_smoother_down<R, SEG>, l_down)) != hipSuccess) return e;
+        auto kred = in_lds(kArSRed) ? k_large_smoother_reduce<R, SEG, true> : k_large_smoother_reduce<R, SEG, false>;
+        auto kks = in_lds(kArSKs) ? k_large_smoother_ks<R, SEG, true> : k_large_smoother_ks<R, SEG, false>;
+        auto kdown = in_lds(kArSDown) ? k_large_smoother_down<R, SEG, true> : k_large_smoother_down<R, SEG, false>;
+        if ((e = allow_lds(kred, l_red)) != hipSuccess) return e;
+        if ((e = allow_lds(kks, l_ks)) != hipSuccess) return e;
+        if ((e = allow_lds(kdown, l_down)) != hipSuccess) return e;
         prof_begin("k_large_smoother_reduce", s);
-        hipLaunchKernelGGL((k_large_smoother_reduce<R, SEG>), grid, block, l_red, s, la);
+        hipLaunchKernelGGL(kred, grid, block, l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_smoother_ks", s);
-            hipLaunchKernelGGL((k_large_smoother_ks<R, SEG>), grid, block, l_ks, s, la, la.agg[cur],
-                               la.agg[cur ^ 1], d, la.nblocks);
+            hipLaunchKernelGGL(kks, grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d, la.nblocks);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_smoother_down", s);
-        hipLaunchKernelGGL((k_large_smoother_down<R, SEG>), grid, block, l_down, s, la);
+        hipLaunchKernelGGL(kdown, grid, block, l_down, s, la);
         prof_end(s);
     }
     return hipGetLastError();
