@@ -238,10 +238,8 @@ struct MomStage {
     static constexpr int WM = N, WP = N * N;                         // words of m and of P
     static constexpr int BM = WM * (int)sizeof(R), BP = WP * (int)sizeof(R);
     // consecutive steps of one lane buffered before a write, so that a lane's
-    // run of records fills whole 128-byte lines when the record divides 128.
-    // FP64 means are written step by step: on gfx950 the grouped form measured
-    // slower there (the larger stage costs more than the partial lines).
-    static constexpr int GM = (sizeof(R) == 8) ? 1 : ((128 % BM == 0 && BM < 128) ? 128 / BM : 1);
+    // run of records fills whole 128-byte lines when the record divides 128
+    static constexpr int GM = (128 % BM == 0 && BM < 128) ? 128 / BM : 1;
     static constexpr int GP = (128 % BP == 0 && BP < 128) ? 128 / BP : 1;
     static constexpr int UBP = (WP * sizeof(R)) % 16 == 0 ? 16 : ((WP * sizeof(R)) % 8 == 0 ? 8 : 4);
     static constexpr int UBM = (WM * sizeof(R)) % 16 == 0 ? 16 : ((WM * sizeof(R)) % 8 == 0 ? 8 : 4);

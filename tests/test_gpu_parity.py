@@ -207,6 +207,26 @@ def test_batched_shared_model(pks):
 # ---------------------------------------------------------------------------
 # plans, status, propagation
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotune_writes_cache_and_is_used(pks, tmp_path, monkeypatch, precision):
+    """pks_autotune times the tile configurations on a synthetic problem of the
+    same shape, records the fastest in the JSON cache, and the scan then runs
+    with it (checked against the oracle).  The large-state path is not tuned."""
+    T = 1 << 17
+    cache = tmp_path / "tune.json"
+    pks.autotune(4, 2, 1, T, precision, str(cache))
+    entries = json.loads(cache.read_text())
+    key = "nx4_ny2_%s_T17_B0" % precision
+    assert key in entries, entries
+    ept, ept1 = entries[key]
+    assert ept in (4, 8, 16) and ept1 in (0, 1, 2, 4, 8)
+    monkeypatch.setenv("PKS_TUNE_CACHE", str(cache))
+    w = wl.workload(1, T=T)
+    check(pks, w.model, w.y, precision, "autotuned ept=%d ept1=%d" % (ept, ept1))
+    with pytest.raises(pks.PksError):
+        pks.autotune(16, 8, 1, 4096, precision, str(cache))
+
+
 def test_plan_replays_match_eager(pks):
     """A HIP-graph plan replayed several times, with unrelated eager work and the
     outputs poisoned between replays: every replay is bitwise identical to the
