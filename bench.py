@@ -189,6 +189,11 @@ def summarize_profiles(base, workload_name):
     print("wrote profiles/%s_kernels.md and profiles/traffic_%s.json" % (workload_name, workload_name))
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -239,6 +244,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = wl.workload(args.workload)
+    progress("workload %s generated (%d steps, %d sequences)" % (w.name, w.total, w.B))
     T = w.total
     nx, ny = w.model.nx, w.model.ny
     batched = w.B > 1
@@ -277,6 +283,7 @@ def main():
             torch.cuda.synchronize()
         out = {k: v.double().cpu().numpy() for k, v in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps))}
         results[prec] = dict(sec=sec, prof=prof, out=out)
+        progress("%s timed: %.4f ms per pass" % (prec, sec * 1e3))
 
     # accuracy against the oracle (FP64; the mixed reference uses the float32-rounded y).
     # Batched workloads: a sample of sequences (first, last and evenly spaced).
@@ -300,13 +307,17 @@ def main():
         if not batched:
             ref = ref_for(prec)
             errs[prec] = {k: wl.max_rel_err(out[k], ref[k]) for k in ("m", "P", "ms", "Ps")}
+            progress("%s checked against the oracle" % prec)
         else:
             e = {k: 0.0 for k in ("m", "P", "ms", "Ps")}
-            for b in sample:
+            for i, b in enumerate(sample):
                 ref = ref_for(prec, b)
                 for key in e:
                     e[key] = max(e[key], wl.max_rel_err(out[key][w.seq(b)], ref[key]))
+                if (i + 1) % 512 == 0:
+                    progress("%s: %d of %d sampled sequences checked" % (prec, i + 1, len(sample)))
             errs[prec] = e
+            progress("%s checked against the oracle on %d sequences" % (prec, len(sample)))
 
     # roofline of the dominant kernel (FP64 headline)
     def roofline(prec):
@@ -372,6 +383,8 @@ def main():
                        sample="full workload (T=%d), %d runs, median; sequential C FP64 KF+RTS, 1 thread"
                        % (T, len(times)))
 
+    if cpu is not None:
+        progress("oracle baseline on the host: %.3e steps/s" % cpu["value"])
     sec64 = results["fp64"]["sec"]
     secm = results["mixed"]["sec"]
     line = {

@@ -311,6 +311,24 @@ def test_cv_T2pow20(pks, precision):
     check(pks, w.model, w.y, precision, "cv T=2^20")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cv_T2pow23(pks, precision):
+    """A sequence eight times the benchmark length (T = 2^23, the top-level scan
+    then has 8192 FP64 wave aggregates), every step against the oracle."""
+    w = wl.workload(2, T=1 << 23)
+    check(pks, w.model, w.y, precision, "cv T=2^23")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_largest_dimensions(pks, precision):
+    """nx = ny = 64, the largest supported state and measurement dimensions
+    (full LU form of Lemma 2, workspace arenas), a few blocks of steps."""
+    rng = np.random.default_rng(6464)
+    model = wl.random_stable_model(64, 64, rng, radius=0.95, with_offsets=True)
+    w = wl.single_sequence(model, 96, seed=64)
+    check(pks, model, w.y, precision, "nx=ny=64", floor="rms" if precision == "mixed" else "none")
+
+
 def test_batched_B4096_sampled(pks):
     """The full batched workload (4096 uneven sequences); the oracle checks a sample of sequences."""
     w = wl.workload(4)
