@@ -1,7 +1,9 @@
 // large_ops.hpp -- workgroup-cooperative matrix operations for the scan of
-// large state dimensions (5 <= nx <= 64): one workgroup (256 threads) owns
-// one scan element at a time; matrices live in an arena that is LDS when it
-// fits and a per-workgroup workspace slot otherwise (generic addressing).
+// large state dimensions (5 <= nx <= 64): one workgroup (one, two or four
+// waves, by nx) owns one scan element at a time; matrices live in an arena
+// that is LDS when it fits and a per-workgroup workspace slot otherwise (the
+// kernels are instantiated for each placement, so LDS arenas are addressed
+// with LDS instructions).
 //
 // Precision policy (as for small states): R is the storage/product type; the
 // LU factorisation with partial pivoting of I + C_i J_j and its solves, the
@@ -12,7 +14,7 @@
 namespace pks {
 namespace large {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;           // largest workgroup (launch bound)
 
 __device__ __forceinline__ double rcp64l(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -224,8 +226,9 @@ __device__ __forceinline__ int take4(Walk2& it, int rows, int (&r)[4], int (&c)[
     return k;
 }
 
-// x[j][c] -= (lv(j) / piv) * x[i][c] for the pairs (j = j0 + row, c = c0 + col)
-// of a rows x w walk by one wave (lv(j) = L[j * sl + i * sc] : stride form)
+// X[j][c] -= Lc[j * sl] * inv * xi[c] for j = j0 .. j0 + rows - 1 and
+// c = c0 .. c0 + w - 1, by one wave (Lc: the coefficient column or row, stride
+// sl; xi: the pivot row, already final)
 __device__ __forceinline__ void wave_axpy_rows(const double* Lc, int sl, double inv, const double* xi, double* X, int ldx,
                                                int j0, int rows, int c0, int w) {
     const int lane = threadIdx.x & 63;
