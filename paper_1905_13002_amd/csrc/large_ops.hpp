@@ -391,6 +391,64 @@ __device__ __forceinline__ void lu_solve(double* a, int lda, int n, int w, int* 
     __syncthreads();
 }
 
+__device__ __forceinline__ double pick4(const double (&v)[4], int t) {
+    return t == 0 ? v[0] : (t == 1 ? v[1] : (t == 2 ? v[2] : v[3]));
+}
+
+// Cholesky factor of an n x n SPD matrix, n <= 16, by wave 0 in registers:
+// lane 4 i + q holds row i, columns 4 q .. 4 q + 3 (zero outside n).  Each
+// column step takes the pivot, the lane's entry of column j and its four
+// entries of row j by lane permutes, then updates the trailing square with
+// l_i l_c (bitwise symmetric).  On return S holds L below the diagonal and
+// L^T above it, as cholesky() leaves it.
+__device__ __forceinline__ bool cholesky_reg16(double* S, int lds, int n, int* flag_sh) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int i = tid >> 2, q = tid & 3, c0 = 4 * q;
+        double s[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) s[t] = (i < n && c0 + t < n) ? S[i * lds + c0 + t] : 0.0;
+        bool ok = true;
+        for (int j = 0; j < n; ++j) {
+            const int jq = j >> 2, jt = j & 3;
+            const double mine = pick4(s, jt);                   // this lane's entry in column j (if its quad holds j)
+            const double d = __shfl(mine, 4 * j + jq, 64);        // s_jj
+            const double colv = __shfl(mine, 4 * i + jq, 64);     // s_ij
+            double rowv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) rowv[t] = __shfl(s[t], 4 * j + q, 64);   // s_j,c0+t
+            ok = ok && d > 0.0;
+            const double isq = rcp64l(sqrt(d));
+            const double li = colv * isq;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (i > j && c0 + t > j) s[t] = fma(-li, rowv[t] * isq, s[t]);
+        }
+        // the pivots: s_cc of this lane's columns sits in lane 4 c + q, entry t
+        double dg[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) dg[t] = __shfl(s[t], 4 * (c0 + t) + q, 64);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = c0 + t;
+            if (i < n && c < n) {
+                if (c < i) {
+                    const double v = s[t] * rcp64l(sqrt(dg[t]));
+                    S[i * lds + c] = v;
+                    S[c * lds + i] = v;
+                } else if (c == i) {
+                    S[i * lds + i] = sqrt(s[t]);
+                }
+            }
+        }
+        if (tid == 0) *flag_sh = ok ? 0 : 1;
+    }
+    __syncthreads();
+    const bool ok = *flag_sh == 0;
+    __syncthreads();
+    return ok;
+}
+
 // In-place Cholesky factor (double) of the n x n SPD matrix S (stride lds):
 // on return the lower triangle holds L and the upper triangle L^T (so both
 // triangular sweeps read rows).  Returns false (workgroup-uniform) if a pivot
@@ -402,6 +460,7 @@ __device__ __forceinline__ void lu_solve(double* a, int lda, int n, int w, int* 
 // synchronising its own lanes; larger matrices use every wave with a barrier
 // per column.  flag_sh holds one int.
 __device__ __forceinline__ bool cholesky(double* S, int lds, int n, int* flag_sh) {
+    if (n <= 16) return cholesky_reg16(S, lds, n, flag_sh);
     const int tid = threadIdx.x;
     const bool one_wave = n <= 32 || blockDim.x == 64;
     const int g = one_wave ? 64 : (int)blockDim.x;
@@ -450,10 +509,78 @@ __device__ __forceinline__ bool cholesky(double* S, int lds, int n, int* flag_sh
     return ok;
 }
 
+// X [n x r] <- (L L^T)^-1 X for n <= 16 by wave 0 in registers, 16 columns
+// per pass: lane 4 i + q holds X[i][4 q .. 4 q + 3] of the pass and caches row
+// i of the stored factor, which is L[i][j] for j < i and L[j][i] for j > i
+// (cholesky() keeps L^T above the diagonal).  Each step finishes one row and
+// sends it to the others by lane permutes; both sweeps are fully unrolled.
+__device__ __forceinline__ void chol_solve_reg16(const double* L, int ldl, int n, double* X, int ldx, int r) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int i = tid >> 2, q = tid & 3, c0 = 4 * q;
+        double rw[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) rw[j] = (i < n && j < n) ? L[i * ldl + j] : 0.0;
+        const double dinv = i < n ? rcp64l(L[i * ldl + i]) : 0.0;
+        for (int cb = 0; cb < r; cb += 16) {
+            double x[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = cb + c0 + t;
+                x[t] = (i < n && c < r) ? X[i * ldx + c] : 0.0;
+            }
+            // L z = x: row j is final once scaled by 1 / l_jj
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j < n) {
+                    if (i == j) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) x[t] *= dinv;
+                    }
+                    double zj[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) zj[t] = __shfl(x[t], 4 * j + q, 64);
+                    if (i > j) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], zj[t], x[t]);
+                    }
+                }
+            }
+            // L^T x = z, from the last row up
+#pragma unroll
+            for (int j = 15; j >= 0; --j) {
+                if (j < n) {
+                    if (i == j) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) x[t] *= dinv;
+                    }
+                    double xj[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) xj[t] = __shfl(x[t], 4 * j + q, 64);
+                    if (i < j) {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], xj[t], x[t]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = cb + c0 + t;
+                if (i < n && c < r) X[i * ldx + c] = x[t];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // X [n x r] (stride ldx) <- (L L^T)^-1 X for a factor from cholesky() (L in
 // the lower triangle, L^T in the upper): the columns are split over the
 // waves, each wave runs both triangular sweeps on its own columns
 __device__ __forceinline__ void chol_solve(const double* L, int ldl, int n, double* X, int ldx, int r) {
+    if (n <= 16) {
+        chol_solve_reg16(L, ldl, n, X, ldx, r);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     int c0, c1;
     wave_columns(r, c0, c1);
