@@ -395,171 +395,184 @@ __device__ __forceinline__ double pick4(const double (&v)[4], int t) {
     return t == 0 ? v[0] : (t == 1 ? v[1] : (t == 2 ? v[2] : v[3]));
 }
 
-// Cholesky factor of an n x n SPD matrix, n <= 16, by wave 0 in registers:
-// lane 4 i + q holds row i, columns 4 q .. 4 q + 3 (zero outside n).  Each
-// column step takes the pivot, the lane's entry of column j and its four
-// entries of row j by lane permutes, then updates the trailing square with
-// l_i l_c (bitwise symmetric).  On return S holds L below the diagonal and
-// L^T above it, as cholesky() leaves it.
-__device__ __forceinline__ bool cholesky_reg16(double* S, int lds, int n, int* flag_sh) {
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int i = tid >> 2, q = tid & 3, c0 = 4 * q;
-        double s[4];
+// Cholesky factor of an n x n SPD matrix, n <= 16, by one wave in registers
+// (no workgroup barrier): lane 4 i + q holds row i, columns 4 q .. 4 q + 3
+// (zero outside n).  Each column step takes the pivot, the lane's entry of
+// column j and its four entries of row j by lane permutes, then updates the
+// trailing square with l_i l_c (bitwise symmetric).  On return S holds L
+// below the diagonal and L^T above it.  Returns false if a pivot is not
+// positive (the same on every lane).
+__device__ __forceinline__ bool cholesky_reg16_wave(double* S, int lds, int n) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane >> 2, q = lane & 3, c0 = 4 * q;
+    double s[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) s[t] = (i < n && c0 + t < n) ? S[i * lds + c0 + t] : 0.0;
-        bool ok = true;
-        for (int j = 0; j < n; ++j) {
-            const int jq = j >> 2, jt = j & 3;
-            const double mine = pick4(s, jt);                   // this lane's entry in column j (if its quad holds j)
-            const double d = __shfl(mine, 4 * j + jq, 64);        // s_jj
-            const double colv = __shfl(mine, 4 * i + jq, 64);     // s_ij
-            double rowv[4];
+    for (int t = 0; t < 4; ++t) s[t] = (i < n && c0 + t < n) ? S[i * lds + c0 + t] : 0.0;
+    bool ok = true;
+    for (int j = 0; j < n; ++j) {
+        const int jq = j >> 2, jt = j & 3;
+        const double mine = pick4(s, jt);                   // this lane's entry in column j (if its quad holds j)
+        const double d = __shfl(mine, 4 * j + jq, 64);        // s_jj
+        const double colv = __shfl(mine, 4 * i + jq, 64);     // s_ij
+        double rowv[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) rowv[t] = __shfl(s[t], 4 * j + q, 64);   // s_j,c0+t
-            ok = ok && d > 0.0;
-            const double isq = rcp64l(sqrt(d));
-            const double li = colv * isq;
+        for (int t = 0; t < 4; ++t) rowv[t] = __shfl(s[t], 4 * j + q, 64);   // s_j,c0+t
+        ok = ok && d > 0.0;
+        const double isq = rcp64l(sqrt(d));
+        const double li = colv * isq;
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (i > j && c0 + t > j) s[t] = fma(-li, rowv[t] * isq, s[t]);
+        for (int t = 0; t < 4; ++t)
+            if (i > j && c0 + t > j) s[t] = fma(-li, rowv[t] * isq, s[t]);
+    }
+    // the pivots: s_cc of this lane's columns sits in lane 4 c + q, entry t
+    double dg[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dg[t] = __shfl(s[t], 4 * (c0 + t) + q, 64);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = c0 + t;
+        if (i < n && c < n) {
+            if (c < i) {
+                const double v = s[t] * rcp64l(sqrt(dg[t]));
+                S[i * lds + c] = v;
+                S[c * lds + i] = v;
+            } else if (c == i) {
+                S[i * lds + i] = sqrt(s[t]);
+            }
         }
-        // the pivots: s_cc of this lane's columns sits in lane 4 c + q, entry t
-        double dg[4];
+    }
+    return ok;
+}
+
+// n <= 16: wave 0 factors, the workgroup waits
+__device__ __forceinline__ bool cholesky_reg16(double* S, int lds, int n, int* flag_sh) {
+    if (threadIdx.x < 64) {
+        const bool ok = cholesky_reg16_wave(S, lds, n);
+        if (threadIdx.x == 0) *flag_sh = ok ? 0 : 1;
+    }
+    __syncthreads();
+    const bool ok = *flag_sh == 0;
+    __syncthreads();
+    return ok;
+}
+
+// Blocked Cholesky factor for 16 < n <= 64 (same storage: L below, L^T above
+// the diagonal).  For each block column of 16: wave 0 factors the diagonal
+// block in registers; one thread per row below solves that row of the panel
+// (x L_JJ^T = s) and writes it to both triangles; the trailing square is
+// updated with the panel product (FP64, register-blocked, bitwise symmetric).
+__device__ __forceinline__ bool cholesky_blocked(double* S, int lds, int n, int* flag_sh) {
+    const int tid = threadIdx.x;
+    bool ok = true;
+    for (int j0 = 0; j0 < n; j0 += 16) {
+        const int bj = n - j0 < 16 ? n - j0 : 16;
+        double* D = S + j0 * lds + j0;
+        if (tid < 64) ok = cholesky_reg16_wave(D, lds, bj) && ok;
+        __syncthreads();
+        const int i0 = j0 + bj, rows = n - i0;
+        for (int rr = tid; rr < rows; rr += blockDim.x) {
+            const int i = i0 + rr;
+            double x[16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) dg[t] = __shfl(s[t], 4 * (c0 + t) + q, 64);
+            for (int c = 0; c < 16; ++c) x[c] = c < bj ? S[i * lds + j0 + c] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int c = c0 + t;
-            if (i < n && c < n) {
-                if (c < i) {
-                    const double v = s[t] * rcp64l(sqrt(dg[t]));
-                    S[i * lds + c] = v;
-                    S[c * lds + i] = v;
-                } else if (c == i) {
-                    S[i * lds + i] = sqrt(s[t]);
+            for (int c = 0; c < 16; ++c) {
+                if (c < bj) {
+                    double v = x[c];
+#pragma unroll
+                    for (int k = 0; k < c; ++k) v = fma(-x[k], D[c * lds + k], v);
+                    x[c] = v * rcp64l(D[c * lds + c]);
                 }
             }
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < bj) {
+                    S[i * lds + j0 + c] = x[c];
+                    S[(j0 + c) * lds + i] = x[c];
+                }
         }
-        if (tid == 0) *flag_sh = ok ? 0 : 1;
+        __syncthreads();
+        if (rows > 0) {
+            double* P = S + i0 * lds + j0;            // the panel, rows i0 .. n-1
+            double* T = S + i0 * lds + i0;            // the trailing square
+            gemmR<double>(T, lds, P, lds, false, P, lds, true, rows, rows, bj, -1.0, T, lds);
+        }
     }
+    if (tid == 0) *flag_sh = ok ? 0 : 1;
     __syncthreads();
-    const bool ok = *flag_sh == 0;
+    const bool res = *flag_sh == 0;
     __syncthreads();
-    return ok;
+    return res;
 }
 
-// In-place Cholesky factor (double) of the n x n SPD matrix S (stride lds):
-// on return the lower triangle holds L and the upper triangle L^T (so both
-// triangular sweeps read rows).  Returns false (workgroup-uniform) if a pivot
-// is not positive.  At step j row and column j are final; the whole trailing
-// square is updated with l_i l_l, where l = s_.j / sqrt(s_jj) is formed on
-// the fly from the column (for l_i) and the row (for l_l): every access runs
-// along a row, and the square stays bitwise symmetric (l_i l_l = l_l l_i).
-// Up to n = 32 (or in a one-wave workgroup) wave 0 alone factors,
-// synchronising its own lanes; larger matrices use every wave with a barrier
-// per column.  flag_sh holds one int.
+// In-place Cholesky factor (double) of the n x n SPD matrix S (stride lds),
+// n <= 64: on return the lower triangle holds L and the upper triangle L^T (so
+// every triangular sweep reads rows).  Returns false (workgroup-uniform) if a
+// pivot is not positive.  n <= 16: one wave in registers; larger: blocked by
+// 16.  flag_sh holds one int.
 __device__ __forceinline__ bool cholesky(double* S, int lds, int n, int* flag_sh) {
     if (n <= 16) return cholesky_reg16(S, lds, n, flag_sh);
-    const int tid = threadIdx.x;
-    const bool one_wave = n <= 32 || blockDim.x == 64;
-    const int g = one_wave ? 64 : (int)blockDim.x;
-    if (!one_wave || tid < 64) {
-        bool ok = true;
-        for (int j = 0; j < n; ++j) {
-            const double d = S[j * lds + j];
-            ok = ok && d > 0.0;
-            const double isq = rcp64l(sqrt(d));
-            const int m = n - j - 1;
-            const double* col_row = S + j * lds + j + 1;      // row j right of the diagonal = column j below it
-            for (Walk2 it(tid, g, m); it.r < m;) {
-                int rr[4], cc[4];
-                const int k = take4(it, m, rr, cc);
-                double li[4], ll[4], x[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u < k) {
-                        li[u] = S[(j + 1 + rr[u]) * lds + j] * isq;
-                        ll[u] = col_row[cc[u]] * isq;
-                        x[u] = S[(j + 1 + rr[u]) * lds + j + 1 + cc[u]];
-                    }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u < k) S[(j + 1 + rr[u]) * lds + j + 1 + cc[u]] = fma(-li[u], ll[u], x[u]);
-            }
-            if (one_wave) wave_sync_mem();
-            else __syncthreads();
-        }
-        for (Walk2 it(tid, g, n); it.r < n; it.next()) {
-            const int i = it.r, j = it.c;
-            if (j < i) {
-                const double v = S[i * lds + j] * rcp64l(sqrt(S[j * lds + j]));
-                S[i * lds + j] = v;
-                S[j * lds + i] = v;
-            }
-        }
-        if (one_wave) wave_sync_mem();
-        else __syncthreads();
-        for (int j = tid; j < n; j += g) S[j * lds + j] = sqrt(S[j * lds + j]);
-        if (tid == 0) *flag_sh = ok ? 0 : 1;
-    }
-    __syncthreads();
-    const bool ok = *flag_sh == 0;
-    __syncthreads();
-    return ok;
+    return cholesky_blocked(S, lds, n, flag_sh);
 }
 
-// X [n x r] <- (L L^T)^-1 X for n <= 16 by wave 0 in registers, 16 columns
-// per pass: lane 4 i + q holds X[i][4 q .. 4 q + 3] of the pass and caches row
-// i of the stored factor, which is L[i][j] for j < i and L[j][i] for j > i
-// (cholesky() keeps L^T above the diagonal).  Each step finishes one row and
-// sends it to the others by lane permutes; both sweeps are fully unrolled.
-__device__ __forceinline__ void chol_solve_reg16(const double* L, int ldl, int n, double* X, int ldx, int r) {
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int i = tid >> 2, q = tid & 3, c0 = 4 * q;
+// Triangular sweeps with a factor block from cholesky() (n <= 16; L below,
+// L^T above the diagonal): X [n x r] <- L^-1 X (fwd) and/or L^-T X (bwd).  The
+// columns go in passes of 16, one pass per wave at a time: lane 4 i + q holds
+// X[i][4 q .. 4 q + 3] of the pass and caches row i of the stored factor
+// (L[i][j] for j < i, L[j][i] for j > i); each step finishes one row and sends
+// it to the others by lane permutes (sweeps fully unrolled).  Ends with a
+// workgroup barrier.
+__device__ __forceinline__ void trsm_reg16(const double* L, int ldl, int n, double* X, int ldx, int r, bool fwd,
+                                           bool bwd) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int i = lane >> 2, q = lane & 3, c0 = 4 * q;
+    if (16 * wave < r) {
         double rw[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) rw[j] = (i < n && j < n) ? L[i * ldl + j] : 0.0;
         const double dinv = i < n ? rcp64l(L[i * ldl + i]) : 0.0;
-        for (int cb = 0; cb < r; cb += 16) {
+        for (int cb = 16 * wave; cb < r; cb += 16 * nw) {
             double x[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int c = cb + c0 + t;
                 x[t] = (i < n && c < r) ? X[i * ldx + c] : 0.0;
             }
-            // L z = x: row j is final once scaled by 1 / l_jj
+            if (fwd) {
+                // L z = x: row j is final once scaled by 1 / l_jj
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (j < n) {
-                    if (i == j) {
+                for (int j = 0; j < 16; ++j) {
+                    if (j < n) {
+                        if (i == j) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) x[t] *= dinv;
-                    }
-                    double zj[4];
+                            for (int t = 0; t < 4; ++t) x[t] *= dinv;
+                        }
+                        double zj[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) zj[t] = __shfl(x[t], 4 * j + q, 64);
-                    if (i > j) {
+                        for (int t = 0; t < 4; ++t) zj[t] = __shfl(x[t], 4 * j + q, 64);
+                        if (i > j) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], zj[t], x[t]);
+                            for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], zj[t], x[t]);
+                        }
                     }
                 }
             }
-            // L^T x = z, from the last row up
+            if (bwd) {
+                // L^T x = z, from the last row up
 #pragma unroll
-            for (int j = 15; j >= 0; --j) {
-                if (j < n) {
-                    if (i == j) {
+                for (int j = 15; j >= 0; --j) {
+                    if (j < n) {
+                        if (i == j) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) x[t] *= dinv;
-                    }
-                    double xj[4];
+                            for (int t = 0; t < 4; ++t) x[t] *= dinv;
+                        }
+                        double xj[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) xj[t] = __shfl(x[t], 4 * j + q, 64);
-                    if (i < j) {
+                        for (int t = 0; t < 4; ++t) xj[t] = __shfl(x[t], 4 * j + q, 64);
+                        if (i < j) {
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], xj[t], x[t]);
+                            for (int t = 0; t < 4; ++t) x[t] = fma(-rw[j], xj[t], x[t]);
+                        }
                     }
                 }
             }
@@ -573,44 +586,29 @@ __device__ __forceinline__ void chol_solve_reg16(const double* L, int ldl, int n
     __syncthreads();
 }
 
-// X [n x r] (stride ldx) <- (L L^T)^-1 X for a factor from cholesky() (L in
-// the lower triangle, L^T in the upper): the columns are split over the
-// waves, each wave runs both triangular sweeps on its own columns
+// X [n x r] <- (L L^T)^-1 X for 16 < n <= 64: blocked sweeps, the diagonal
+// blocks with trsm_reg16, the rest as FP64 products
+__device__ __forceinline__ void chol_solve_blocked(const double* L, int ldl, int n, double* X, int ldx, int r) {
+    for (int j0 = 0; j0 < n; j0 += 16) {
+        const int bj = n - j0 < 16 ? n - j0 : 16, i0 = j0 + bj;
+        trsm_reg16(L + j0 * ldl + j0, ldl, bj, X + j0 * ldx, ldx, r, true, false);
+        if (i0 < n)
+            gemmR<double>(X + i0 * ldx, ldx, L + i0 * ldl + j0, ldl, false, X + j0 * ldx, ldx, false, n - i0, r, bj,
+                          -1.0, X + i0 * ldx, ldx);
+    }
+    const int last = ((n - 1) / 16) * 16;
+    for (int j0 = last; j0 >= 0; j0 -= 16) {
+        const int bj = n - j0 < 16 ? n - j0 : 16;
+        trsm_reg16(L + j0 * ldl + j0, ldl, bj, X + j0 * ldx, ldx, r, false, true);
+        if (j0 > 0)   // rows above: X[0 .. j0) -= (L^T)[0 .. j0, j0 .. j0+bj) X_J, L^T stored above the diagonal
+            gemmR<double>(X, ldx, L + j0, ldl, false, X + j0 * ldx, ldx, false, j0, r, bj, -1.0, X, ldx);
+    }
+}
+
+// X [n x r] (stride ldx) <- (L L^T)^-1 X for a factor from cholesky(), n <= 64
 __device__ __forceinline__ void chol_solve(const double* L, int ldl, int n, double* X, int ldx, int r) {
-    if (n <= 16) {
-        chol_solve_reg16(L, ldl, n, X, ldx, r);
-        return;
-    }
-    const int lane = threadIdx.x & 63;
-    int c0, c1;
-    wave_columns(r, c0, c1);
-    const int w = c1 - c0;
-    if (w > 0) {
-        // L z = x
-        for (int i = 0; i + 1 < n; ++i) {
-            const double inv = rcp64l(L[i * ldl + i]);
-            // rows i+1 .. n-1: X[j][c] -= L[j][i] / l_ii * X[i][c]  (L[j][i] = upper row i)
-            wave_axpy_rows(L + i * ldl, 1, inv, X + i * ldx, X, ldx, i + 1, n - i - 1, c0, w);
-            wave_sync_mem();
-        }
-        for (Walk2 it(lane, 64, w); it.r < n; it.next()) {
-            const int j = it.r, c = c0 + it.c;
-            X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
-        }
-        wave_sync_mem();
-        // L^T x = z
-        for (int i = n - 1; i > 0; --i) {
-            const double inv = rcp64l(L[i * ldl + i]);
-            // rows 0 .. i-1: X[j][c] -= L[i][j] / l_ii * X[i][c]  (L^T: stride 1 along j)
-            wave_axpy_rows(L + i * ldl, 1, inv, X + i * ldx, X, ldx, 0, i, c0, w);
-            wave_sync_mem();
-        }
-        for (Walk2 it(lane, 64, w); it.r < n; it.next()) {
-            const int j = it.r, c = c0 + it.c;
-            X[j * ldx + c] *= rcp64l(L[j * ldl + j]);
-        }
-    }
-    __syncthreads();
+    if (n <= 16) trsm_reg16(L, ldl, n, X, ldx, r, true, true);
+    else chol_solve_blocked(L, ldl, n, X, ldx, r);
 }
 
 // workgroup-uniform test: every entry of X is zero
