@@ -32,6 +32,7 @@ template <int BS, typename R>
 __device__ __forceinline__ void gemm_blocks(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb,
                                             int m, int n, int k, R alpha, const R* D, int ldd) {
     const int bm = (m + BS - 1) / BS, bn = (n + BS - 1) / BS;
+    constexpr int kUnrollK = BS == 4 ? 4 : 8;      // k steps whose loads are in flight together
     for (int blk = threadIdx.x; blk < bm * bn; blk += blockDim.x) {
         const int i0 = (blk / bn) * BS, j0 = (blk % bn) * BS;
         R acc[BS][BS];
@@ -40,7 +41,7 @@ __device__ __forceinline__ void gemm_blocks(R* C, int ldc, const R* A, int lda, 
 #pragma unroll
             for (int b = 0; b < BS; ++b) acc[a][b] = R(0);
         // unrolled so that the loads of several k steps are in flight together
-#pragma unroll(BS == 4 ? 4 : 8)
+#pragma unroll kUnrollK
         for (int l = 0; l < k; ++l) {
             R av[BS], bv[BS];
 #pragma unroll
@@ -89,7 +90,6 @@ __device__ __forceinline__ void gemm_mfma_f32(float* C, int ldc, const float* A,
         const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
         const int ia = i0 + li, jb = j0 + li;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
         for (int l0 = 0; l0 < k; l0 += 4) {
             const int l = l0 + lk;
             const float av = (ia < m && l < k) ? (ta ? A[l * lda + ia] : A[ia * lda + l]) : 0.f;
@@ -167,6 +167,7 @@ template <int BS, typename TA, typename TB, typename TC>
 __device__ __forceinline__ void gemm_blocks_acc64(TC* C, int ldc, const TA* A, int lda, const TB* B, int ldb, int m,
                                                   int n, int k, double alpha, const TC* D, int ldd) {
     const int bm = (m + BS - 1) / BS, bn = (n + BS - 1) / BS;
+    constexpr int kUnrollK = BS == 4 ? 4 : 8;      // k steps whose loads are in flight together
     for (int blk = threadIdx.x; blk < bm * bn; blk += blockDim.x) {
         const int i0 = (blk / bn) * BS, j0 = (blk % bn) * BS;
         double acc[BS][BS];
@@ -174,7 +175,7 @@ __device__ __forceinline__ void gemm_blocks_acc64(TC* C, int ldc, const TA* A, i
         for (int a = 0; a < BS; ++a)
 #pragma unroll
             for (int b = 0; b < BS; ++b) acc[a][b] = 0.0;
-#pragma unroll(BS == 4 ? 4 : 8)
+#pragma unroll kUnrollK
         for (int l = 0; l < k; ++l) {
             double av[BS], bv[BS];
 #pragma unroll
