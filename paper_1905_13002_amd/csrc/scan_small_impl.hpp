@@ -229,8 +229,8 @@ __device__ __forceinline__ void make_selem(const R* __restrict__ cst, const Cons
 // instruction covers a few whole records.
 // ---------------------------------------------------------------------------
 template <int Bytes> struct UnitT;
-template <> struct UnitT<16> { using T = uint4; };
-template <> struct UnitT<8> { using T = uint2; };
+template <> struct UnitT<16> { using T = unsigned int __attribute__((ext_vector_type(4))); };
+template <> struct UnitT<8> { using T = unsigned int __attribute__((ext_vector_type(2))); };
 template <> struct UnitT<4> { using T = unsigned int; };
 
 template <int N, typename R>
@@ -275,7 +275,9 @@ __device__ __forceinline__ void wave_flush(R* __restrict__ dst, const R* st, int
         if (s < filled && k < total) {
             UT val;
             __builtin_memcpy(&val, reinterpret_cast<const char*>(st + l * ROW) + v * UB, UB);
-            reinterpret_cast<UT*>(dst + (kfirst + (int64_t)l * stride) * rec_words)[v] = val;
+            // streaming store: the outputs are not read again by this kernel,
+            // so they should not push out the input lines that still are
+            __builtin_nontemporal_store(val, reinterpret_cast<UT*>(dst + (kfirst + (int64_t)l * stride) * rec_words) + v);
         }
     }
 }
