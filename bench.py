@@ -194,6 +194,39 @@ def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def summarize_trace(base, wid):
+    """Write profiles/<workload>_kernels.md from a rocprofv3 kernel trace of
+    `bench.py --workload wid` under `base` (calls and mean duration per kernel)."""
+    import sqlite3
+    import re
+    from paper_1905_13002_amd import workloads as wl
+    name = wl.WORKLOAD_NAMES[wid]
+    db = [f for f in sorted(os.listdir(base)) if f.endswith("_results.db")]
+    if not db:
+        raise FileNotFoundError("no *_results.db under %s" % base)
+    cur = sqlite3.connect(os.path.join(base, db[0])).cursor()
+    rows = []
+    for n, calls, tot, avg in cur.execute("select name, total_calls, total_duration, average from top_kernels"):
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::lg::", "").replace("pks::", "")
+        m = re.match(r"void (\w+<[^>]*>)", n)
+        n = m.group(1) if m else n
+        if n.startswith("k_"):
+            rows.append((n, int(calls), float(avg), float(tot)))
+    cmd = ("rocprofv3 --kernel-trace --stats -d %s -o trace -- python bench.py --workload %d --steps 2 --warmup 1 "
+           "--no-cpu-baseline" % (base.rstrip("/"), wid))
+    lines = ["# Kernel profile: %s, filter + smoother" % name, "",
+             "`rocprofv3` kernel trace on one MI355X, library built from this tree.  Commands (repository root):", "",
+             "```", cmd, "python bench.py --summarize-trace %s --workload %d" % (base.rstrip("/"), wid), "```", "",
+             "The bench runs the FP64 path and then the mixed path (warm-up, timed passes and one pass with HIP "
+             "events each); `avg_us` is the mean kernel duration over all dispatches, `total_ms` the sum.", "",
+             "| kernel | calls | avg_us | total_ms |", "|---|---:|---:|---:|"]
+    for n, calls, avg, tot in rows:
+        lines.append("| `%s` | %d | %.1f | %.2f |" % (n, calls, avg, tot / 1e3))
+    with open(os.path.join(ROOT, "profiles", "%s_kernels.md" % name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote profiles/%s_kernels.md" % name)
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -217,9 +250,14 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters under rocprofv3)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise the rocprofv3 databases under DIR into profiles/ and exit")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="summarise a rocprofv3 kernel trace of --workload under DIR into profiles/ and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, "cv_T1048576")
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
