@@ -285,6 +285,36 @@ def test_numeric_flag_single_and_batched(pks):
     assert not torch.isnan(m[w.seq(2)]).any()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_numeric_flag_large_state(pks, precision):
+    """Large-state path (nx = 6): a model whose S = H Q H^T + R is not positive
+    definite raises the numeric flag with its sequence index and yields NaN
+    outputs for that sequence only, the others unaffected."""
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rng = np.random.default_rng(606)
+    models = [wl.random_stable_model(6, 2, np.random.default_rng(610 + b), radius=0.9) for b in range(4)]
+    models[2] = wl.Model(models[2].F, models[2].Q, models[2].H, -10.0 * np.eye(2), models[2].m0, models[2].P0)
+    lengths = [50, 70, 40, 60]
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    y = rng.standard_normal((int(offsets[-1]), 2))
+    stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+    model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"))
+    dm = pks.to_device(model, per_sequence=True)
+    od = torch.as_tensor(offsets).cuda()
+    yd = torch.as_tensor(y).to("cuda", dt)
+    ws = pks.workspace(6, 2, int(offsets[-1]), 4, precision)
+    m, P = pks.filter_batched(dm, od, yd, precision, ws=ws)
+    ok, first = pks.read_numeric_status(ws)
+    assert not ok and first == 2
+    assert torch.isnan(m[offsets[2]:offsets[3]]).all()
+    assert not torch.isnan(m[offsets[1]:offsets[2]]).any() and not torch.isnan(m[offsets[3]:]).any()
+    single = pks.to_device(models[2])
+    ws1 = pks.workspace(6, 2, 40, 1, precision)
+    pks.filter(single, yd[:40].contiguous(), precision, ws=ws1)
+    ok, first = pks.read_numeric_status(ws1)
+    assert not ok and first == 0
+
+
 def test_nan_in_y_propagates(pks):
     w = wl.workload(1, T=3000)
     y = w.y.copy()
