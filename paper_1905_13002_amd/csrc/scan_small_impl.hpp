@@ -191,6 +191,15 @@ __device__ __forceinline__ void load_moments_step(const R* __restrict__ m, const
         for (int c = 0; c <= r; ++c) x.P[sidx(r, c)] = P[k * N * N + r * N + c];
 }
 
+// the filtered covariance of step k (lower triangle)
+template <int N, typename R>
+__device__ __forceinline__ void load_cov_step(const R* __restrict__ P, int64_t k, Moments<N, R>& x) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) x.P[sidx(r, c)] = P[k * N * N + r * N + c];
+}
+
 template <int N, typename R>
 __device__ __forceinline__ void store_moments_step(R* __restrict__ m, R* __restrict__ P, int64_t k,
                                                    const Moments<N, R>& x) {
@@ -305,6 +314,24 @@ __device__ __forceinline__ void wave_store_moments(R* __restrict__ m, R* __restr
     if (fm) wave_flush<S::GM, S::UM, S::UBM, S::ROWM, R>(m, sm, N, kw + e - e % S::GM, stride, total, lane, e % S::GM + 1);
     if (fp) wave_flush<S::GP, S::UP, S::UBP, S::ROWP, R>(P, sp, N * N, kw + e - e % S::GP, stride, total, lane, e % S::GP + 1);
     if (fm || fp) wave_sync();
+}
+
+// the inverse of wave_flush: read the G records of every lane (steps
+// kfirst + l * stride .. + G - 1, contiguous) into its stage row, whole lines
+// per instruction; records at or beyond total read as zero
+template <int G, int U, int UB, int ROW, typename R>
+__device__ __forceinline__ void wave_fill(const R* __restrict__ src, R* st, int rec_words, int64_t kfirst,
+                                          int64_t stride, int64_t total, int lane) {
+    using UT = typename UnitT<UB>::T;
+    constexpr int PER = G * U;                       // units per lane
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int f = lane + 64 * i, l = f / PER, v = f % PER, s = v / U;
+        const int64_t k = kfirst + (int64_t)l * stride + s;
+        UT val{};
+        if (k < total) val = reinterpret_cast<const UT*>(src + (kfirst + (int64_t)l * stride) * rec_words)[v];
+        __builtin_memcpy(reinterpret_cast<char*>(st + l * ROW) + v * UB, &val, UB);
+    }
 }
 
 // reverse-order variant (the smoother produces steps from the last to the
@@ -846,13 +873,33 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
     }
     const int64_t klast = (k0 + EPT - 1 < a.total) ? k0 + EPT - 1 : a.total - 1;
     Seq s = seq_find<SEG>(a, klast);
+    // When a lane's run of means is exactly one store group (FP32 means, 8 per
+    // line), the filtered means of the whole run are read into the stage first,
+    // whole lines per instruction, and each step replaces its own slot with the
+    // smoothed mean: a line is never fetched twice.  Covariances are read
+    // directly, one step ahead.
+    using MS = MomStage<N, R>;
+    constexpr bool kRunM = sizeof(R) == 4 && MS::GM == EPT;
+    if constexpr (kRunM) {
+        wave_fill<MS::GM, MS::UM, MS::UBM, MS::ROWM, R>(m, st, N, kw, EPT, a.total, lane);
+        wave_sync();
+    }
     Moments<N, R> xn;
-    load_moments_step(m, P, klast, xn);
+    if constexpr (kRunM) load_cov_step(P, klast, xn);
+    else load_moments_step(m, P, klast, xn);
 #pragma unroll 1
     for (int e = EPT - 1; e >= 0; --e) {
         const int64_t k = k0 + e;
-        const Moments<N, R> x = xn;
-        if (k <= klast && k > k0) load_moments_step(m, P, k - 1, xn);
+        Moments<N, R> x = xn;
+        if (k <= klast && k > k0) {
+            if constexpr (kRunM) load_cov_step(P, k - 1, xn);
+            else load_moments_step(m, P, k - 1, xn);
+        }
+        if constexpr (kRunM) {
+            const R* rm = st + lane * MS::ROWM + (e % MS::GM) * N;
+#pragma unroll
+            for (int r = 0; r < N; ++r) x.m[r] = rm[r];
+        }
         if (k <= klast) {
             seq_backward<SEG>(a, s, k);
             const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
