@@ -334,8 +334,13 @@ struct DualOut {
 template <int NX, int NY>
 __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int nmodels) {
     using SP = SmallPre<NX, NY>;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0) {
+    // Two independent chains per model, in different waves so that they run
+    // concurrently: even blocks derive the shared constants of the steps k > 1,
+    // odd blocks the first-step element (and copy F, Q, u).  The odd half also
+    // factors S = H Q H^T + R, so it alone decides whether the model failed.
+    const int part = blockIdx.x & 1;
+    const int b = (blockIdx.x >> 1) * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (a.reset || a.status[1] != kStatusMagic) {
             a.status[0] = kStatusOk;
             a.status[1] = kStatusMagic;
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     const ConstLayout CL = const_layout(NX, NY);
     DualOut out{a.consts64 + (size_t)b * a.cw, a.mixed ? a.consts32 + (size_t)b * a.cw : nullptr};
     bool ok = true;
-    if (a.what & 1) {
+    if ((a.what & 1) && part == 0) {
         double T1[nm], S[m2], Lc[m2], Kt[nm], G[nm], Z[nm], X[n2], e[NY], v[NX];
         SP::template mm<NY, NX, NX, false, false>(T1, H, Q);          // H Q
         SP::template mm<NY, NX, NY, false, true>(S, T1, H);           // H Q H^T
@@ -415,8 +420,10 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         SP::template mm<NX, NY, 1, true, false>(v, Z, e);
 #pragma unroll
         for (int i = 0; i < NX; ++i) out.put(CL.w + i, -v[i]);
-        // k = 1
-        double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm];
+    }
+    if ((a.what & 1) && part == 1) {
+        // k = 1: one prediction from the prior and one update
+        double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm], X[n2], v[NX];
         SP::template mm<NX, NX, 1, false, false>(m1, F, m0);
 #pragma unroll
         for (int i = 0; i < NX; ++i) m1[i] += u[i];
@@ -430,6 +437,15 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
 #pragma unroll
         for (int i = 0; i < m2; ++i) S1[i] += R[i];
         SP::template sym<NY>(S1);
+        {
+            double T1[nm], S[m2], Lc[m2];
+            SP::template mm<NY, NX, NX, false, false>(T1, H, Q);
+            SP::template mm<NY, NX, NY, false, true>(S, T1, H);
+#pragma unroll
+            for (int i = 0; i < m2; ++i) S[i] += R[i];
+            SP::template sym<NY>(S);
+            ok = SP::template chol<NY>(S, Lc);
+        }
         ok = SP::template chol<NY>(S1, L1) && ok;
 #pragma unroll
         for (int i = 0; i < nm; ++i) K1t[i] = T2[i];
@@ -451,9 +467,9 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         SP::template sym<NX>(X);
 #pragma unroll
         for (int i = 0; i < n2; ++i) out.put(CL.C1 + i, X[i]);
-        a.model_fail[b] = ok ? 0 : 1;
     }
-    if (a.what & 2) {
+    if ((a.what & 1) && part == 1) a.model_fail[b] = ok ? 0 : 1;
+    if ((a.what & 2) && part == 1) {
 #pragma unroll
         for (int i = 0; i < n2; ++i) {
             out.put(CL.F + i, F[i]);
@@ -463,15 +479,19 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         for (int i = 0; i < NX; ++i) out.put(CL.u + i, u[i]);
     }
     if (!ok) {
-        const int lo = (a.what & 1) ? 0 : CL.F;
-        const int hi = (a.what & 2) ? CL.words : CL.F;
+        // NaN in the fields this half owns (constants A .. w and G, S; or the
+        // first-step K1, c1, C1).  Every filtered prefix holds the first-step
+        // element, so all of a failing sequence's outputs come out NaN.
+        const int lo = part == 0 ? CL.A : CL.K1, hi = part == 0 ? CL.K1 : CL.G;
         for (int i = lo; i < hi; ++i) out.put(i, __builtin_nan(""));
+        if (part == 0)
+            for (int i = CL.G; i < CL.F; ++i) out.put(i, __builtin_nan(""));
     }
 }
 
 template <int NX>
 bool launch_small_pre_ny(int ny, PrecomputeArgs a, int nmodels, hipStream_t s) {
-    const dim3 grid((nmodels + 63) / 64), block(64);
+    const dim3 grid(2 * ((nmodels + 63) / 64)), block(64);    // even / odd blocks: the two halves
     switch (ny) {
         case 1: hipLaunchKernelGGL((k_precompute_small<NX, 1>), grid, block, 0, s, a, nmodels); return true;
         case 2: hipLaunchKernelGGL((k_precompute_small<NX, 2>), grid, block, 0, s, a, nmodels); return true;
