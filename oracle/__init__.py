@@ -7,6 +7,9 @@ with the HIP library (``paper_1905_13002_amd``) and imports nothing from it.
 * :func:`kf_rts` / :func:`kf_rts_batched` wrap ``kfrts.c`` (plain C, FP64,
   built with ``gcc -O3 -ffp-contract=off``): the textbook recursions that the
   paper's parallel method reproduces exactly (Theorems 1 and 2).
+* ``loglik=True`` adds the per-step factors log p(y_k | y_1:k-1) of the
+  marginal likelihood (Section III-C); :func:`loglik_prefix` turns them into
+  log p(y_1:k) and the per-sequence totals log p(y_1:n).
 * :mod:`oracle.elements` restates the paper's linear/Gaussian elements and
   associative operators (Lemmas 1-4) in numpy FP64, for operator-level checks.
 """
@@ -44,11 +47,11 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_kf_rts.restype = ctypes.c_int
-        lib.oracle_kf_rts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long] + [dp] * 15
+        lib.oracle_kf_rts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long] + [dp] * 16
         lib.oracle_kf_rts_batched.restype = ctypes.c_int
         lib.oracle_kf_rts_batched.argtypes = (
             [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long), ctypes.c_int]
-            + [dp] * 13 + [ctypes.c_int])
+            + [dp] * 14 + [ctypes.c_int])
         _lib = lib
     return _lib
 
@@ -67,12 +70,13 @@ class OracleError(RuntimeError):
     pass
 
 
-def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False):
+def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False, loglik=False):
     """Run the sequential Kalman filter and (optionally) the RTS smoother.
 
     ``y`` is ``[T, ny]``; returns a dict with ``m [T,nx]``, ``P [T,nx,nx]`` and,
     when ``smooth``, ``ms``, ``Ps``; with ``predicted`` also ``mp``, ``Pp``
-    (the one-step predictions m^-_k, P^-_k).
+    (the one-step predictions m^-_k, P^-_k); with ``loglik`` also ``ll [T]``,
+    the log predictive density log p(y_k | y_1:k-1) of every step.
     """
     lib = _load()
     F, Q, H, R, m0, P0, y = map(_f64, (F, Q, H, R, m0, P0, y))
@@ -86,8 +90,9 @@ def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False):
     Ps = np.empty((T, nx, nx)) if smooth else None
     mp = np.empty((T, nx)) if predicted else None
     Pp = np.empty((T, nx, nx)) if predicted else None
+    ll = np.empty(T) if loglik else None
     st = lib.oracle_kf_rts(nx, ny, T, _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0),
-                           _p(y), _p(m), _p(P), _p(ms), _p(Ps), _p(mp), _p(Pp))
+                           _p(y), _p(m), _p(P), _p(ms), _p(Ps), _p(mp), _p(Pp), _p(ll))
     if st:
         raise OracleError("oracle: Cholesky failed (code %d)" % st)
     out = {"m": m, "P": P}
@@ -95,11 +100,13 @@ def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False):
         out.update(ms=ms, Ps=Ps)
     if predicted:
         out.update(mp=mp, Pp=Pp)
+    if loglik:
+        out["ll"] = ll
     return out
 
 
 def kf_rts_batched(F, Q, H, R, m0, P0, y, offsets, u=None, d=None, per_sequence=False,
-                   threads=None, smooth=True):
+                   threads=None, smooth=True, loglik=False):
     """Independent sequences packed back to back; see ``oracle_kf_rts_batched``."""
     lib = _load()
     F, Q, H, R, m0, P0, y = map(_f64, (F, Q, H, R, m0, P0, y))
@@ -114,18 +121,42 @@ def kf_rts_batched(F, Q, H, R, m0, P0, y, offsets, u=None, d=None, per_sequence=
     P = np.empty((total, nx, nx))
     ms = np.empty((total, nx)) if smooth else None
     Ps = np.empty((total, nx, nx)) if smooth else None
+    ll = np.empty(total) if loglik else None
     if threads is None:
         threads = os.cpu_count() or 1
     st = lib.oracle_kf_rts_batched(
         nx, ny, B, offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), 1 if per_sequence else 0,
         _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0), _p(y), _p(m), _p(P),
-        _p(ms), _p(Ps), int(threads))
+        _p(ms), _p(Ps), _p(ll), int(threads))
     if st:
         raise OracleError("oracle: Cholesky failed in sequence %d" % (st - 1))
     out = {"m": m, "P": P}
     if smooth:
         out.update(ms=ms, Ps=Ps)
+    if loglik:
+        out["ll"] = ll
     return out
+
+
+def loglik_prefix(ll, offsets=None):
+    """From per-step factors log p(y_k | y_1:k-1) to the prefixes log p(y_1:k)
+    of every sequence (a running sum that restarts at each sequence start, in
+    step order) and the per-sequence totals log p(y_1:n) (0 for an empty
+    sequence).  Section III-C: the marginal likelihood is the product of the
+    factors, so its logarithm is their sum."""
+    ll = np.asarray(ll, dtype=np.float64)
+    if offsets is None:
+        offsets = np.array([0, ll.shape[0]], dtype=np.int64)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    cum = np.empty_like(ll)
+    tot = np.zeros(offsets.shape[0] - 1)
+    for b in range(offsets.shape[0] - 1):
+        acc = 0.0
+        for k in range(int(offsets[b]), int(offsets[b + 1])):
+            acc += ll[k]
+            cum[k] = acc
+        tot[b] = acc
+    return cum, tot
 
 
 if __name__ == "__main__":  # pragma: no cover

@@ -18,6 +18,13 @@
  *           equation, in its Gaussian form) with gain G_k = P_k F^T (P^-_{k+1})^{-1}
  *           (the same gain as E_k in Lemma 3) and the last smoothed moment equal
  *           to the last filtered one (Lemma 3, k = n).
+ *   loglik  the factors of the marginal likelihood, p(y_1:n) = prod_k
+ *           p(y_k | y_1:k-1) (Section III-C), each the Gaussian density of y_k
+ *           under the filter's one-step prediction: N(y_k; H m^-_k + d, S_k)
+ *           with the innovation covariance S_k = H P^-_k H^T + R, evaluated
+ *           as -(ny log(2 pi) + log det S_k + e_k^T S_k^{-1} e_k) / 2 from the
+ *           Cholesky factor of S_k (log det = 2 sum log L_ii, and the
+ *           quadratic form is |L^{-1} e_k|^2).
  *
  * The parallel method reaches this result exactly in exact arithmetic
  * (Theorems 1 and 2; Section V says the parallel and sequential solutions
@@ -81,6 +88,20 @@ static int cholesky(int n, double *S)
     return 0;
 }
 
+/* log N(e; 0, L L^T) for a lower Cholesky factor L [n x n] and a residual e [n]. */
+static double gauss_logpdf(int n, const double *L, const double *e, double *z)
+{
+    double logdet = 0.0, quad = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double v = e[i];
+        for (int l = 0; l < i; ++l) v -= L[i * n + l] * z[l];
+        z[i] = v / L[i * n + i];
+        quad += z[i] * z[i];
+        logdet += 2.0 * log(L[i * n + i]);
+    }
+    return -0.5 * ((double)n * log(2.0 * acos(-1.0)) + logdet + quad);
+}
+
 /* Solve (L L^T) X = B in place, L lower [n x n], B [n x r]. */
 static void chol_solve(int n, int r, const double *L, double *B)
 {
@@ -103,7 +124,8 @@ static void chol_solve(int n, int r, const double *L, double *B)
 /*
  * One sequence.  u, d may be NULL (zero).  mp/Pp (predicted moments) may be
  * NULL, in which case an internal buffer is used.  ms/Ps may be NULL to run
- * the filter only.  Returns 0, or k (1-based step) whose Cholesky failed
+ * the filter only.  ll (may be NULL) receives log p(y_k | y_1:k-1) per step.
+ * Returns 0, or k (1-based step) whose Cholesky failed
  * (innovation covariance S_k in the filter, P^-_{k+1} in the smoother, the
  * latter reported as T + k).
  */
@@ -113,7 +135,7 @@ int oracle_kf_rts(int nx, int ny, long T,
                   const double *m0, const double *P0,
                   const double *y,
                   double *m, double *P, double *ms, double *Ps,
-                  double *mp_out, double *Pp_out)
+                  double *mp_out, double *Pp_out, double *ll)
 {
     if (T <= 0) return 0;
     const int n2 = nx * nx;
@@ -125,7 +147,7 @@ int oracle_kf_rts(int nx, int ny, long T,
         mp = own;
         Pp = own + (size_t)T * nx;
     }
-    double *work = (double *)malloc(sizeof(double) * (size_t)(6 * n2 + 6 * nx * ny + 4 * ny * ny + 4 * nx + 4 * ny + 16));
+    double *work = (double *)malloc(sizeof(double) * (size_t)(6 * n2 + 6 * nx * ny + 4 * ny * ny + 4 * nx + 5 * ny + 16));
     if (!work) { free(own); return -1; }
     double *FP = work;              /* nx*nx */
     double *HP = FP + n2;           /* ny*nx */
@@ -139,6 +161,7 @@ int oracle_kf_rts(int nx, int ny, long T,
     double *D = G + n2;             /* nx*nx */
     double *GD = D + n2;            /* nx*nx */
     double *dm = GD + n2;           /* nx */
+    double *z = dm + nx;            /* ny */
     int status = 0;
 
     const double *mprev = m0, *Pprev = P0;
@@ -169,6 +192,7 @@ int oracle_kf_rts(int nx, int ny, long T,
             for (int l = 0; l < nx; ++l) s -= H[i * nx + l] * mpk[l];
             e[i] = s;
         }
+        if (ll) ll[k] = gauss_logpdf(ny, Lc, e, z);
         for (int i = 0; i < nx; ++i) {
             double s = mpk[i];
             for (int l = 0; l < ny; ++l) s += Kt[l * nx + i] * e[l];
@@ -226,7 +250,7 @@ typedef struct {
     const double *F, *u, *Q, *H, *d, *R, *m0, *P0;
     long sF, su, sQ, sH, sd, sR, sm0, sP0; /* per-sequence model strides (0 = shared) */
     const double *y;
-    double *m, *P, *ms, *Ps;
+    double *m, *P, *ms, *Ps, *ll;
     int next;
     pthread_mutex_t lock;
     int status;
@@ -248,7 +272,7 @@ static void *batch_worker(void *arg)
                                J->m0 + b * J->sm0, J->P0 + b * J->sP0,
                                J->y + s * ny, J->m + s * nx, J->P + s * nx * nx,
                                J->ms ? J->ms + s * nx : NULL, J->Ps ? J->Ps + s * nx * nx : NULL,
-                               NULL, NULL);
+                               NULL, NULL, J->ll ? J->ll + s : NULL);
         if (st) {
             pthread_mutex_lock(&J->lock);
             if (!J->status) J->status = b + 1;
@@ -260,7 +284,7 @@ static void *batch_worker(void *arg)
 
 /*
  * B sequences packed back to back (sequence b occupies steps offsets[b] ..
- * offsets[b+1]-1 of y/m/P/ms/Ps).  per_sequence != 0 means model arrays hold
+ * offsets[b+1]-1 of y/m/P/ms/Ps/ll).  per_sequence != 0 means model arrays hold
  * B stacked models; otherwise one model is shared.  Runs on `threads` host
  * threads (sequences are independent).  Returns 0 or 1 + first failing b.
  */
@@ -269,7 +293,7 @@ int oracle_kf_rts_batched(int nx, int ny, int B, const long *offsets, int per_se
                           const double *H, const double *d, const double *R,
                           const double *m0, const double *P0,
                           const double *y, double *m, double *P, double *ms, double *Ps,
-                          int threads)
+                          double *ll, int threads)
 {
     batch_job J;
     J.nx = nx; J.ny = ny; J.B = B; J.offsets = offsets;
@@ -277,7 +301,7 @@ int oracle_kf_rts_batched(int nx, int ny, int B, const long *offsets, int per_se
     long ps = per_sequence ? 1 : 0;
     J.sF = ps * nx * nx; J.su = ps * nx; J.sQ = ps * nx * nx; J.sH = ps * ny * nx;
     J.sd = ps * ny; J.sR = ps * ny * ny; J.sm0 = ps * nx; J.sP0 = ps * nx * nx;
-    J.y = y; J.m = m; J.P = P; J.ms = ms; J.Ps = Ps;
+    J.y = y; J.m = m; J.P = P; J.ms = ms; J.Ps = Ps; J.ll = ll;
     J.next = 0; J.status = 0;
     pthread_mutex_init(&J.lock, NULL);
     if (threads < 1) threads = 1;

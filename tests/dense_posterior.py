@@ -6,6 +6,8 @@ Gaussian and the smoothed moments are the conditional moments E[X | Y],
 Cov[X | Y] computed with one dense solve.  The filtered moment at step k is
 the same computation restricted to y_1..y_k, read at its last block.
 Works with singular Q.  No recursion, no Kalman gain, no element or operator.
+The same joint moments give the marginal likelihood: y_1..y_k are jointly
+Gaussian, so log p(y_1:k) is one dense Gaussian log-density.
 """
 from __future__ import annotations
 
@@ -63,3 +65,21 @@ def posterior(F, Q, H, R, m0, P0, y, u=None, d=None):
         m[k] = muX[sl] + SXY @ np.linalg.solve(SY, Yv[:n] - muY[:n])
         P[k] = SigX[sl, sl] - SXY @ np.linalg.solve(SY, SXY.T)
     return m, P, ms, Ps
+
+
+def joint_loglik(F, Q, H, R, m0, P0, y, u=None, d=None):
+    """log p(y_1:k) for k = 1..T, each the dense Gaussian log-density of the
+    stacked measurements y_1..y_k (slogdet and one solve of its covariance)."""
+    y = np.asarray(y, float)
+    ny = H.shape[0]
+    T = y.shape[0]
+    _, _, muY, SigY, _ = joint_moments(F, Q, H, R, m0, P0, T, u, d)
+    Yv = y.reshape(-1)
+    out = np.empty(T)
+    for k in range(T):
+        n = (k + 1) * ny
+        r = Yv[:n] - muY[:n]
+        sign, logdet = np.linalg.slogdet(SigY[:n, :n])
+        assert sign > 0
+        out[k] = -0.5 * (n * np.log(2.0 * np.pi) + logdet + r @ np.linalg.solve(SigY[:n, :n], r))
+    return out

@@ -16,7 +16,7 @@ import scipy.linalg
 import oracle
 from oracle import elements as el
 from paper_1905_13002_amd import workloads as wl
-from tests.dense_posterior import posterior
+from tests.dense_posterior import joint_loglik, posterior
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -406,3 +406,92 @@ def test_prefix_sum_worked_example():
     x = [x[i] + b[i] for i in range(n)]
     assert x == g["prefix_sums"]
     assert list(np.cumsum(a)) == g["prefix_sums"]
+
+
+# ---------------------------------------------------------------------------
+# marginal likelihood (Section III-C): the per-step factors p(y_k | y_1:k-1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,T,singQ", DENSE_CASES)
+def test_oracle_loglik_matches_dense_joint_density(nx, ny, T, singQ):
+    """The running sum of the oracle's log factors equals the dense Gaussian
+    log-density of y_1..y_k for every k (chain rule of the joint density)."""
+    rng = np.random.default_rng(2000 + 17 * nx + 3 * ny + T)
+    model = wl.random_small_model(nx, ny, rng, singular_Q=singQ)
+    y, _ = wl.simulate(model, T, rng)
+    out = run(model, y, loglik=True)
+    cum, tot = oracle.loglik_prefix(out["ll"])
+    ref = joint_loglik(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, model.u, model.d)
+    assert np.max(np.abs(cum - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
+    assert tot[0] == cum[-1]
+
+
+def test_oracle_loglik_cv_model_matches_dense_joint_density():
+    w = wl.workload(1, T=30)
+    out = run(w.model, w.y, loglik=True)
+    cum, _ = oracle.loglik_prefix(out["ll"])
+    ref = joint_loglik(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, w.y)
+    assert np.max(np.abs(cum - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
+
+
+def test_oracle_loglik_scalar_first_step_closed_form():
+    """T = 1, nx = ny = 1: y_1 ~ N(h (f m0 + u) + d, h^2 (f^2 p0 + q) + r)."""
+    f, q, h, r, m0, p0, u, d, y1 = 0.9, 0.3, 1.7, 0.2, 0.4, 2.0, 0.25, -0.1, 1.3
+    one = lambda v: np.array([[v]])
+    out = oracle.kf_rts(one(f), one(q), one(h), one(r), np.array([m0]), one(p0), np.array([[y1]]),
+                        u=np.array([u]), d=np.array([d]), loglik=True)
+    mu = h * (f * m0 + u) + d
+    var = h * h * (f * f * p0 + q) + r
+    ref = -0.5 * (np.log(2 * np.pi * var) + (y1 - mu) ** 2 / var)
+    assert abs(out["ll"][0] - ref) < 1e-14 * abs(ref)
+
+
+def test_oracle_loglik_static_model_closed_form():
+    """F = I, Q = 0, u = 0: y_k = H x + d + r_k with one x ~ N(m0, P0), so
+    y_1..y_k ~ N(1 (x) (H m0 + d), (1 1^T) (x) (H P0 H^T) + I (x) R); the
+    density of that block matrix is evaluated by the matrix determinant lemma
+    and the Woodbury identity, without forming it."""
+    rng = np.random.default_rng(7)
+    nx, ny, T = 3, 2, 9
+    model = wl.random_small_model(nx, ny, rng)
+    F, Q = np.eye(nx), np.zeros((nx, nx))
+    H, R, m0, P0 = model.H, model.R, model.m0, model.P0
+    y = rng.standard_normal((T, ny))
+    out = oracle.kf_rts(F, Q, H, R, m0, P0, y, loglik=True)
+    cum, _ = oracle.loglik_prefix(out["ll"])
+    Ri = np.linalg.inv(R)
+    for k in range(1, T + 1):
+        r = y[:k] - (H @ m0)                      # k x ny residuals
+        # Sigma = I_k (x) R + U U^T with U = 1_k (x) (H L0), P0 = L0 L0^T
+        L0 = np.linalg.cholesky(P0)
+        HL = H @ L0
+        M = np.eye(nx) + k * HL.T @ Ri @ HL       # I + U^T (I (x) R^-1) U
+        logdet = k * np.linalg.slogdet(R)[1] + np.linalg.slogdet(M)[1]
+        Rr = r @ Ri                               # rows (R^-1 r_i)^T
+        v = HL.T @ Rr.sum(axis=0)                 # U^T (I (x) R^-1) r
+        quad = np.sum(Rr * r) - v @ np.linalg.solve(M, v)
+        ref = -0.5 * (k * ny * np.log(2 * np.pi) + logdet + quad)
+        assert abs(cum[k - 1] - ref) < 1e-12 * max(1.0, abs(ref))
+
+
+def test_oracle_loglik_batched_restarts_per_sequence():
+    rng = np.random.default_rng(11)
+    nx, ny, B = 3, 2, 5
+    lens = [7, 0, 1, 12, 4]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    models = [wl.random_small_model(nx, ny, rng) for _ in range(B)]
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, ny)) for mo, L in zip(models, lens)]
+    stack = lambda a: np.stack([getattr(mo, a) for mo in models])
+    out = oracle.kf_rts_batched(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"),
+                                stack("P0"), np.concatenate(ys), offsets, per_sequence=True,
+                                smooth=False, loglik=True, threads=2)
+    cum, tot = oracle.loglik_prefix(out["ll"], offsets)
+    for b in range(B):
+        if lens[b] == 0:
+            assert tot[b] == 0.0
+            continue
+        mo = models[b]
+        ref = joint_loglik(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, ys[b])
+        sl = slice(offsets[b], offsets[b + 1])
+        assert np.max(np.abs(cum[sl] - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
+        assert tot[b] == cum[offsets[b + 1] - 1]
