@@ -139,6 +139,36 @@ pks_status pks_smooth_batched(const pks_model *model, int32_t B, const int64_t *
                               pks_precision prec, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Marginal likelihood (Section III-C).  From the measurements y [T][ny] and
+ * the filtered moments m [T][nx], P [T][nx][nx] that pks_filter wrote for the
+ * same model, evaluates every factor of p(y_1:T) = prod_k p(y_k | y_1:k-1):
+ *     log p(y_k | y_1:k-1) = log N(y_k; H m^-_k + d, H P^-_k H^T + R),
+ *     m^-_k = F m_{k-1} + u,  P^-_k = F P_{k-1} F^T + Q,
+ * with m_0 = m0, P_0 = P0 at the first step.  Evaluated in double in both
+ * precisions (PKS_MIXED_FP32 widens its float y, m, P).
+ *   ll       DEVICE double [T] or NULL: log p(y_k | y_1:k-1) for every k, or,
+ *            with cumulative != 0, the partial sums log p(y_1:k).
+ *   ll_total DEVICE double [1] or NULL: log p(y_1:T) (0 when T = 0).
+ * At least one of ll, ll_total must be given; cumulative != 0 needs ll.
+ * Outputs must not overlap the inputs or each other.  The sums are taken in
+ * a fixed order (reproducible run to run).  An innovation covariance whose
+ * Cholesky factorisation fails sets the numeric flag (see
+ * pks_read_numeric_status) and gives NaN for that step and every sum over
+ * it; NaN in y gives NaN without the flag.  Same workspace as pks_filter.
+ */
+pks_status pks_loglik(const pks_model *model, int64_t T, const void *y, const void *m, const void *P,
+                      double *ll, double *ll_total, int32_t cumulative, pks_precision prec, void *ws,
+                      size_t ws_bytes, void *stream);
+/*
+ * Batched form: offsets, packing and per-sequence models as in
+ * pks_filter_batched; ll [total], ll_total [B] (0 for an empty sequence); the
+ * partial sums restart at every sequence start.
+ */
+pks_status pks_loglik_batched(const pks_model *model, int32_t B, const int64_t *offsets, int64_t total,
+                              const void *y, const void *m, const void *P, double *ll, double *ll_total,
+                              int32_t cumulative, pks_precision prec, void *ws, size_t ws_bytes,
+                              void *stream);
+/*
  * Plans: the whole filter + smoother of a (batched) problem, with its tile
  * configuration taken from the tuning cache, captured once into a HIP graph
  * bound to these pointers; pks_plan_launch replays it with one

@@ -99,6 +99,13 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.carry1 = o; o = align256(o + rs * mw * (size_t)waves1);
     L.large = o;
     if (!small) o = align256(o + large_ws_bytes(nx, ny, total, prec));
+    const int64_t nblk = ll_blocks(total);
+    L.ll_step = o; o = align256(o + sizeof(double) * (size_t)total);
+    L.ll_cum = o; o = align256(o + sizeof(double) * (size_t)total);
+    L.ll_blk_h = o; o = align256(o + sizeof(int32_t) * (size_t)nblk);
+    L.ll_blk_v = o; o = align256(o + sizeof(double) * (size_t)nblk);
+    L.ll_blk_first = o; o = align256(o + sizeof(int32_t) * (size_t)nblk);
+    L.ll_carry = o; o = align256(o + sizeof(double) * (size_t)nblk);
     L.total = o;
     return L;
 }
@@ -218,6 +225,54 @@ pks_status validate_io(const pks_model* model, int32_t B, const int64_t* offsets
     return PKS_OK;
 }
 
+pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
+                       const void* y, const void* m, const void* P, double* ll, double* tot,
+                       int32_t cumulative, pks_precision prec, void* ws, size_t ws_bytes, bool batched,
+                       hipStream_t s) {
+    pks_status st = check_model(model);
+    if (st) return st;
+    st = check_prec(prec);
+    if (st) return st;
+    if (total < 0) return fail(PKS_E_ARG, "negative number of steps");
+    if (batched) {
+        if (B < 1) return fail(PKS_E_ARG, "B = %d must be >= 1", B);
+        if (!offsets) return fail(PKS_E_ARG, "offsets is NULL");
+    } else if (model->per_sequence) {
+        return fail(PKS_E_ARG, "per_sequence models need a batched call");
+    }
+    if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
+    if (!ll && !tot) return fail(PKS_E_ARG, "ll and ll_total are both NULL");
+    if (cumulative && !ll) return fail(PKS_E_ARG, "cumulative output needs ll");
+    const WsLayout L = ws_layout(model->nx, model->ny, total, B, prec);
+    if (ws_bytes < L.total)
+        return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
+                    ws_bytes, L.total);
+    const size_t rs = rsize(prec), nx = model->nx, ny = model->ny, T = (size_t)total;
+    const size_t by = T * ny * rs, bm = T * nx * rs, bP = T * nx * nx * rs;
+    const size_t bl = T * sizeof(double), bt = (size_t)B * sizeof(double);
+    if (total > 0) {
+        if (!y || !m || !P) return fail(PKS_E_ARG, "y, m and P must not be NULL");
+        if (overlaps(ll, bl, y, by) || overlaps(ll, bl, m, bm) || overlaps(ll, bl, P, bP) ||
+            overlaps(tot, bt, y, by) || overlaps(tot, bt, m, bm) || overlaps(tot, bt, P, bP) ||
+            overlaps(tot, bt, ll, bl))
+            return fail(PKS_E_ARG, "log-likelihood outputs overlap the inputs or each other");
+    }
+    if (total == 0) {
+        if (tot) {
+            const hipError_t e = hipMemsetAsync(tot, 0, bt, s);   // every sequence is empty: log 1
+            if (e != hipSuccess) return hip_fail(e, "clearing ll_total");
+        }
+        return PKS_OK;
+    }
+    const int nmodels = model->per_sequence ? B : 1;
+    hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 1, false, s);
+    if (e != hipSuccess) return hip_fail(e, "precompute kernel");
+    e = launch_loglik(*model, B, batched ? offsets : nullptr, total, y, m, P, ll, tot, cumulative != 0,
+                      prec == PKS_MIXED_FP32, ws, L, s);
+    if (e != hipSuccess) return hip_fail(e, "log-likelihood kernels");
+    return PKS_OK;
+}
+
 void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
 // ---------------------------------------------------------------------------
@@ -317,6 +372,22 @@ pks_status pks_smooth_batched(const pks_model* model, int32_t B, const int64_t* 
     if (st) return st;
     return enqueue(*model, B, offsets, total, nullptr, const_cast<void*>(m), const_cast<void*>(P), ms, Ps, prec,
                    ws, ws_bytes, 2, nullptr, (hipStream_t)stream);
+}
+
+pks_status pks_loglik(const pks_model* model, int64_t T, const void* y, const void* m, const void* P,
+                      double* ll, double* ll_total, int32_t cumulative, pks_precision prec, void* ws,
+                      size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return loglik_impl(model, 1, nullptr, T, y, m, P, ll, ll_total, cumulative, prec, ws, ws_bytes, false,
+                       (hipStream_t)stream);
+}
+
+pks_status pks_loglik_batched(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
+                              const void* y, const void* m, const void* P, double* ll, double* ll_total,
+                              int32_t cumulative, pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return loglik_impl(model, B, offsets, total, y, m, P, ll, ll_total, cumulative, prec, ws, ws_bytes, true,
+                       (hipStream_t)stream);
 }
 
 pks_status pks_read_numeric_status(void* ws, int32_t* first_bad_sequence, void* stream) {

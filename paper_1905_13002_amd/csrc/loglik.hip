@@ -1,0 +1,552 @@
+// loglik.hip -- the marginal likelihood of filtered sequences (Section III-C).
+//
+// p(y_1:n) is the product of the factors p(y_k | y_1:k-1), and each factor is
+// the Gaussian density of y_k under the one-step prediction made from the
+// filtered moments of step k-1 (from the prior x_0 ~ N(m0, P0) at the first
+// step of a sequence):
+//     m^-_k = F m_{k-1} + u,   P^-_k = F P_{k-1} F^T + Q,
+//     y_k | y_1:k-1 ~ N(H m^-_k + d, H P^-_k H^T + R)
+//                   = N(G m_{k-1} + e, G P_{k-1} G^T + S0)
+// with the model constants G = H F, e = H u + d, S0 = H Q H^T + R of the
+// precompute.  Given the filtered moments the factors are independent, so
+// each step is evaluated on its own; the partial likelihoods p(y_1:k) are then
+// a prefix sum of the log factors that restarts at every sequence start (the
+// section's pairwise products of adjacent terms, taken in log space).
+//
+//   log N(r; 0, S) = -(ny log(2 pi) + 2 sum_i log L_ii + |L^-1 r|^2) / 2,
+//   S = L L^T (Cholesky; a pivot that is not positive sets the numeric flag
+//   and gives NaN, a NaN in y gives NaN without the flag).
+// Every factor is evaluated in double; in the mixed mode the float y, m, P are
+// widened first.
+//
+// Kernels
+//   k_ll_small<NX,NY,R,SEG>  nx, ny <= 4: one step per lane; the moments of the
+//                            previous steps are staged through LDS in whole
+//                            rows (coalesced loads, odd row stride).
+//   k_ll_wave<R,SEG>         any size: one wavefront per step; P_{k-1}, G P_{k-1}
+//                            and S in LDS, the Cholesky factorisation and the
+//                            forward substitution row-parallel across lanes.
+//   k_ll_block_scan<SEG>     segmented inclusive prefix sums inside blocks of
+//                            kLLBlock steps; per block its aggregate (whether
+//                            a sequence starts in it, sum since the last start)
+//                            and the position of its first sequence start.
+//   k_ll_top<SEG>            one workgroup: exclusive scan of the block
+//                            aggregates (the carry into each block) and the
+//                            per-sequence totals.
+//   k_ll_fixup               adds each block's carry to its steps before the
+//                            block's first sequence start.
+// The prefix sums use a fixed combination order, so results are reproducible
+// run to run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "pks_internal.h"
+
+namespace pks {
+
+namespace {
+
+constexpr int kLLThreads = 256;                     // per-step kernels, block scan
+constexpr int kLLPerThread = kLLBlock / kLLThreads; // steps per thread in the block scan
+constexpr int kTopThreads = 1024;
+constexpr double kLog2Pi = 1.8378770664093454836;   // log(2 pi)
+
+struct LLArgs {
+    int nx, ny;
+    int64_t total;
+    int32_t B;
+    const int64_t* offsets;        // device [B+1]; nullptr = one sequence
+    int per_sequence;
+    const double* m0;              // model prior(s)
+    const double* P0;
+    const double* consts64;        // per-model constants (G, S0, e used here)
+    int64_t cstride;               // doubles between models' constants (0 = shared)
+    int cG, cS, ce;                // offsets of G, S0, e in a model's constants
+    const void* y;
+    const void* m;                 // filtered moments of every step
+    const void* P;
+    double* step;                  // [total] out: log p(y_k | y_1:k-1)
+    int* status;
+};
+
+// sequence index and first step of step k (k < total)
+template <bool SEG>
+__device__ __forceinline__ int seq_of(const int64_t* off, int B, int64_t k, int64_t& start) {
+    if (!SEG) {
+        start = 0;
+        return 0;
+    }
+    int lo = 0, hi = B;        // offsets[lo] <= k
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    start = off[lo];
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// nx, ny <= 4: one step per lane
+// ---------------------------------------------------------------------------
+template <int NX, int NY, typename R, bool SEG>
+__global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a) {
+    constexpr int n2 = NX * NX, RW = NX + n2;
+    constexpr int ROW = (RW & 1) ? RW : RW + 1;     // odd row stride: lanes hit distinct banks
+    __shared__ R stage[kLLThreads * ROW];
+    const int t = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * kLLThreads;
+    // rows r = 0 .. 255 hold the moments of steps k0-1 .. k0+254
+    const R* gm = static_cast<const R*>(a.m);
+    const R* gP = static_cast<const R*>(a.P);
+    for (int i = t; i < kLLThreads * NX; i += kLLThreads) {
+        const int r = i / NX, c = i - r * NX;
+        const int64_t kk = k0 - 1 + r;
+        if (kk >= 0 && kk < a.total) stage[r * ROW + c] = gm[kk * NX + c];
+    }
+    for (int i = t; i < kLLThreads * n2; i += kLLThreads) {
+        const int r = i / n2, c = i - r * n2;
+        const int64_t kk = k0 - 1 + r;
+        if (kk >= 0 && kk < a.total) stage[r * ROW + NX + c] = gP[kk * n2 + c];
+    }
+    __syncthreads();
+    const int64_t k = k0 + t;
+    if (k >= a.total) return;
+    int64_t start;
+    const int b = seq_of<SEG>(a.offsets, a.B, k, start);
+    const bool first = k == start;
+
+    double m[NX], P[n2];
+    if (first) {
+        const int64_t ps = a.per_sequence ? b : 0;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) m[i] = a.m0[ps * NX + i];
+#pragma unroll
+        for (int i = 0; i < n2; ++i) P[i] = a.P0[ps * n2 + i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) m[i] = (double)stage[t * ROW + i];
+#pragma unroll
+        for (int i = 0; i < n2; ++i) P[i] = (double)stage[t * ROW + NX + i];
+    }
+    const double* cst = a.consts64 + a.cstride * b;
+    double G[NY * NX], S[NY * NY], r[NY];
+#pragma unroll
+    for (int i = 0; i < NY * NX; ++i) G[i] = cst[a.cG + i];
+#pragma unroll
+    for (int i = 0; i < NY * NY; ++i) S[i] = cst[a.cS + i];
+    const R* yk = static_cast<const R*>(a.y) + k * NY;
+#pragma unroll
+    for (int i = 0; i < NY; ++i) {
+        double v = (double)yk[i] - cst[a.ce + i];
+#pragma unroll
+        for (int l = 0; l < NX; ++l) v -= G[i * NX + l] * m[l];
+        r[i] = v;
+    }
+    // S += G P G^T (lower triangle; the Cholesky factorisation reads only it)
+    double T[NY * NX];
+#pragma unroll
+    for (int i = 0; i < NY; ++i)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int l = 0; l < NX; ++l) v += G[i * NX + l] * P[l * NX + j];
+            T[i * NX + j] = v;
+        }
+#pragma unroll
+    for (int i = 0; i < NY; ++i)
+#pragma unroll
+        for (int i2 = 0; i2 <= i; ++i2) {
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < NX; ++j) v += T[i * NX + j] * G[i2 * NX + j];
+            S[i * NY + i2] += v;
+        }
+    // S = L L^T in place (lower), z = L^-1 r in place
+    bool ok = true;
+    double logdet = 0.0, quad = 0.0;
+#pragma unroll
+    for (int j = 0; j < NY; ++j) {
+        double dj = S[j * NY + j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) dj -= S[j * NY + l] * S[j * NY + l];
+        ok = ok && dj > 0.0;
+        const double ljj = sqrt(dj);
+        const double inv = 1.0 / ljj;
+        S[j * NY + j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < NY; ++i) {
+            double v = S[i * NY + j];
+#pragma unroll
+            for (int l = 0; l < j; ++l) v -= S[i * NY + l] * S[j * NY + l];
+            S[i * NY + j] = v * inv;
+        }
+        double zj = r[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) zj -= S[j * NY + l] * r[l];
+        r[j] = zj * inv;
+        quad += r[j] * r[j];
+        logdet += log(ljj);
+    }
+    double ll = -0.5 * (NY * kLog2Pi + quad) - logdet;
+    if (!ok) {
+        ll = __builtin_nan("");
+        atomicMin(a.status, b);
+    }
+    a.step[k] = ll;
+}
+
+// ---------------------------------------------------------------------------
+// any size: one wavefront per step
+// ---------------------------------------------------------------------------
+// Makes one wave's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__host__ __device__ inline int ll_wave_words(int nx, int ny) {
+    // P [nx][nx], T = G P [ny][nx], S [ny][ny], m [nx], r [ny]
+    return nx * nx + ny * nx + ny * ny + nx + ny;
+}
+
+template <typename R, bool SEG>
+__global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
+    extern __shared__ __align__(16) double lds_ll[];
+    const int nx = a.nx, ny = a.ny, n2 = nx * nx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double* P = lds_ll + (size_t)wave * ll_wave_words(nx, ny);
+    double* T = P + n2;
+    double* S = T + ny * nx;
+    double* m = S + ny * ny;
+    double* r = m + nx;
+    const R* gm = static_cast<const R*>(a.m);
+    const R* gP = static_cast<const R*>(a.P);
+    const R* gy = static_cast<const R*>(a.y);
+    for (int64_t k = (int64_t)blockIdx.x * nw + wave; k < a.total; k += (int64_t)gridDim.x * nw) {
+        int64_t start;
+        const int b = seq_of<SEG>(a.offsets, a.B, k, start);
+        const double* cst = a.consts64 + a.cstride * b;
+        const double* G = cst + a.cG;
+        if (k == start) {
+            const int64_t ps = a.per_sequence ? b : 0;
+            for (int i = lane; i < n2; i += 64) P[i] = a.P0[ps * n2 + i];
+            for (int i = lane; i < nx; i += 64) m[i] = a.m0[ps * nx + i];
+        } else {
+            for (int i = lane; i < n2; i += 64) P[i] = (double)gP[(k - 1) * n2 + i];
+            for (int i = lane; i < nx; i += 64) m[i] = (double)gm[(k - 1) * nx + i];
+        }
+        wave_sync();
+        for (int idx = lane; idx < ny * nx; idx += 64) {          // T = G P
+            const int i = idx / nx, j = idx - i * nx;
+            double v = 0.0;
+            for (int l = 0; l < nx; ++l) v += G[i * nx + l] * P[l * nx + j];
+            T[idx] = v;
+        }
+        for (int i = lane; i < ny; i += 64) {                      // r = y - G m - e
+            double v = (double)gy[k * ny + i] - cst[a.ce + i];
+            for (int l = 0; l < nx; ++l) v -= G[i * nx + l] * m[l];
+            r[i] = v;
+        }
+        wave_sync();
+        for (int idx = lane; idx < ny * ny; idx += 64) {          // S = S0 + T G^T (lower)
+            const int i = idx / ny, i2 = idx - i * ny;
+            if (i2 > i) continue;
+            double v = 0.0;
+            for (int j = 0; j < nx; ++j) v += T[i * nx + j] * G[i2 * nx + j];
+            S[idx] = cst[a.cS + idx] + v;
+        }
+        wave_sync();
+        // right-looking Cholesky with the forward substitution of r alongside
+        bool ok = true;
+        double logdet = 0.0, quad = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            const double dj = S[j * ny + j];
+            ok = ok && dj > 0.0;
+            const double ljj = sqrt(dj), inv = 1.0 / ljj;
+            const double zj = r[j] * inv;
+            quad += zj * zj;
+            logdet += log(ljj);
+            wave_sync();                                           // every lane has read row j
+            for (int i = j + 1 + lane; i < ny; i += 64) {
+                const double lij = S[i * ny + j] * inv;
+                S[i * ny + j] = lij;
+                r[i] -= lij * zj;
+            }
+            wave_sync();
+            const int nt = ny - j - 1;
+            for (int idx = lane; idx < nt * nt; idx += 64) {       // trailing lower triangle
+                const int ii = idx / nt, jj = idx - ii * nt;
+                if (jj > ii) continue;
+                const int i = j + 1 + ii, i2 = j + 1 + jj;
+                S[i * ny + i2] -= S[i * ny + j] * S[i2 * ny + j];
+            }
+            wave_sync();
+        }
+        if (lane == 0) {
+            double ll = -0.5 * (ny * kLog2Pi + quad) - logdet;
+            if (!ok) {
+                ll = __builtin_nan("");
+                atomicMin(a.status, b);
+            }
+            a.step[k] = ll;
+        }
+        wave_sync();                                               // LDS reuse by the next step
+    }
+}
+
+// ---------------------------------------------------------------------------
+// segmented prefix sums of the log factors
+// ---------------------------------------------------------------------------
+// (head, value): head = a sequence starts in the range, value = sum since the
+// last start in it (or over all of it).  Associative; left operand first.
+struct Seg {
+    int h;
+    double v;
+};
+__device__ __forceinline__ Seg seg_combine(Seg l, Seg r) {
+    return Seg{l.h | r.h, r.h ? r.v : l.v + r.v};
+}
+
+// inclusive scan over the 64 lanes of a wave
+__device__ __forceinline__ Seg wave_scan(Seg x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        Seg o;
+        o.h = __shfl_up(x.h, d, 64);
+        o.v = __shfl_up(x.v, d, 64);
+        if (lane >= d) x = seg_combine(o, x);
+    }
+    return x;
+}
+
+// Exclusive scan over the block (NT threads): returns the combination of all
+// earlier threads' values (identity for thread 0); *total gets the block's.
+template <int NT>
+__device__ __forceinline__ Seg block_exclusive(Seg x, Seg* total) {
+    __shared__ int sh_h[NT / 64];
+    __shared__ double sh_v[NT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Seg inc = wave_scan(x);
+    Seg ex;
+    ex.h = __shfl_up(inc.h, 1, 64);
+    ex.v = __shfl_up(inc.v, 1, 64);
+    if (lane == 0) ex = Seg{0, 0.0};
+    if (lane == 63) {
+        sh_h[wave] = inc.h;
+        sh_v[wave] = inc.v;
+    }
+    __syncthreads();
+    Seg pre{0, 0.0};
+    for (int w = 0; w < wave; ++w) pre = seg_combine(pre, Seg{sh_h[w], sh_v[w]});
+    Seg all = pre;
+    for (int w = wave; w < NT / 64; ++w) all = seg_combine(all, Seg{sh_h[w], sh_v[w]});
+    *total = all;
+    __syncthreads();                     // the shared words are reused by the next call
+    return seg_combine(pre, ex);
+}
+
+struct LLScanArgs {
+    int64_t total;
+    int32_t B;
+    const int64_t* offsets;
+    const double* step;     // [total] log factors
+    double* cum;            // [total] out: prefix sums inside each block
+    int* blk_h;             // [nblk]
+    double* blk_v;          // [nblk]
+    int* blk_first;         // [nblk] position of the block's first sequence start (kLLBlock: none)
+    double* carry;          // [nblk] sum carried into each block
+    double* tot;            // [B] per-sequence totals (nullptr: not wanted)
+    int64_t nblk;
+};
+
+template <bool SEG>
+__global__ __launch_bounds__(kLLThreads) void k_ll_block_scan(LLScanArgs a) {
+    __shared__ int first_sh;
+    const int t = threadIdx.x;
+    if (t == 0) first_sh = kLLBlock;
+    const int64_t k0 = (int64_t)blockIdx.x * kLLBlock + (int64_t)t * kLLPerThread;
+    double inc[kLLPerThread];
+    int heads = 0;
+    Seg x{0, 0.0};
+    int64_t start = 0, end = a.total;
+    int b = 0;
+    if (SEG && k0 < a.total) {
+        b = seq_of<true>(a.offsets, a.B, k0, start);
+        end = a.offsets[b + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kLLPerThread; ++q) {
+        const int64_t k = k0 + q;
+        double v = 0.0;
+        int h = 0;
+        if (k < a.total) {
+            while (SEG && k >= end) {        // next non-empty sequence
+                ++b;
+                start = end;
+                end = a.offsets[b + 1];
+            }
+            h = k == start;
+            v = a.step[k];
+        }
+        x = seg_combine(x, Seg{h, v});
+        inc[q] = x.v;
+        heads |= h << q;
+    }
+    __syncthreads();                         // first_sh initialised
+    if (heads) atomicMin(&first_sh, t * kLLPerThread + __builtin_ctz(heads));
+    Seg blk;
+    const Seg ex = block_exclusive<kLLThreads>(x, &blk);
+#pragma unroll
+    for (int q = 0; q < kLLPerThread; ++q) {
+        const int64_t k = k0 + q;
+        const bool own = heads & ((2 << q) - 1);   // a start among this thread's steps 0..q
+        if (k < a.total) a.cum[k] = own ? inc[q] : ex.v + inc[q];
+    }
+    if (t == 0) {
+        a.blk_h[blockIdx.x] = blk.h;
+        a.blk_v[blockIdx.x] = blk.v;
+        a.blk_first[blockIdx.x] = first_sh;
+    }
+}
+
+template <bool SEG>
+__global__ __launch_bounds__(kTopThreads) void k_ll_top(LLScanArgs a) {
+    const int t = threadIdx.x;
+    Seg run{0, 0.0};
+    for (int64_t base = 0; base < a.nblk; base += kTopThreads) {
+        const int64_t c = base + t;
+        const Seg x = c < a.nblk ? Seg{a.blk_h[c], a.blk_v[c]} : Seg{0, 0.0};
+        Seg chunk;
+        const Seg ex = block_exclusive<kTopThreads>(x, &chunk);
+        if (c < a.nblk) a.carry[c] = seg_combine(run, ex).v;
+        run = seg_combine(run, chunk);
+    }
+    if (!a.tot) return;
+    __syncthreads();                         // carries written by this workgroup
+    for (int b = t; b < a.B; b += kTopThreads) {
+        const int64_t s = SEG ? a.offsets[b] : 0, e = SEG ? a.offsets[b + 1] : a.total;
+        double v = 0.0;
+        if (e > s) {
+            const int64_t k = e - 1, c = k / kLLBlock;
+            v = a.cum[k];
+            if (s < c * kLLBlock) v += a.carry[c];
+        }
+        a.tot[b] = v;
+    }
+}
+
+__global__ __launch_bounds__(kLLThreads) void k_ll_fixup(LLScanArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * kLLThreads + threadIdx.x;
+    if (k >= a.total) return;
+    const int64_t c = k / kLLBlock;
+    if (k - c * kLLBlock < a.blk_first[c]) a.cum[k] += a.carry[c];
+}
+
+template <int NX, typename R, bool SEG>
+bool launch_small_ny(int ny, const LLArgs& a, dim3 grid, hipStream_t s) {
+    switch (ny) {
+        case 1: hipLaunchKernelGGL((k_ll_small<NX, 1, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
+        case 2: hipLaunchKernelGGL((k_ll_small<NX, 2, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
+        case 3: hipLaunchKernelGGL((k_ll_small<NX, 3, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
+        case 4: hipLaunchKernelGGL((k_ll_small<NX, 4, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
+        default: return false;
+    }
+}
+
+template <typename R, bool SEG>
+bool launch_small_ll(const LLArgs& a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.total + kLLThreads - 1) / kLLThreads));
+    switch (a.nx) {
+        case 1: return launch_small_ny<1, R, SEG>(a.ny, a, grid, s);
+        case 2: return launch_small_ny<2, R, SEG>(a.ny, a, grid, s);
+        case 3: return launch_small_ny<3, R, SEG>(a.ny, a, grid, s);
+        case 4: return launch_small_ny<4, R, SEG>(a.ny, a, grid, s);
+        default: return false;
+    }
+}
+
+template <typename R, bool SEG>
+void launch_steps(const LLArgs& a, hipStream_t s) {
+    prof_begin("k_ll_steps", s);
+    if (!(a.nx <= 4 && a.ny <= 4 && launch_small_ll<R, SEG>(a, s))) {
+        const size_t per_wave = sizeof(double) * (size_t)ll_wave_words(a.nx, a.ny);
+        int waves = (int)std::min<size_t>(4, std::max<size_t>(1, (64 * 1024) / per_wave));
+        const int64_t want = (a.total + waves - 1) / waves;
+        const unsigned grid = (unsigned)std::min<int64_t>(want, 16384);
+        hipLaunchKernelGGL((k_ll_wave<R, SEG>), dim3(grid), dim3(64 * waves), per_wave * waves, s, a);
+    }
+    prof_end(s);
+}
+
+}  // namespace
+
+int64_t ll_blocks(int64_t total) { return (total + kLLBlock - 1) / kLLBlock; }
+
+hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
+                         const void* y, const void* m, const void* P, double* ll, double* tot,
+                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s) {
+    char* base = static_cast<char*>(ws);
+    const ConstLayout CL = const_layout(model.nx, model.ny);
+    LLArgs a{};
+    a.nx = model.nx;
+    a.ny = model.ny;
+    a.total = total;
+    a.B = B;
+    a.offsets = offsets;
+    a.per_sequence = model.per_sequence ? 1 : 0;
+    a.m0 = model.m0;
+    a.P0 = model.P0;
+    a.consts64 = reinterpret_cast<const double*>(base + L.consts64);
+    a.cstride = model.per_sequence ? CL.words : 0;
+    a.cG = CL.G;
+    a.cS = CL.S;
+    a.ce = CL.e;
+    a.y = y;
+    a.m = m;
+    a.P = P;
+    a.status = reinterpret_cast<int*>(base + L.status);
+    // the per-step factors go to the caller's array unless it receives the prefix sums
+    double* ws_step = reinterpret_cast<double*>(base + L.ll_step);
+    a.step = (ll && !cumulative) ? ll : ws_step;
+    const bool seg = offsets != nullptr;
+    if (mixed) {
+        if (seg) launch_steps<float, true>(a, s); else launch_steps<float, false>(a, s);
+    } else {
+        if (seg) launch_steps<double, true>(a, s); else launch_steps<double, false>(a, s);
+    }
+    if (!cumulative && !tot) return hipGetLastError();
+
+    LLScanArgs c{};
+    c.total = total;
+    c.B = seg ? B : 1;
+    c.offsets = offsets;
+    c.step = a.step;
+    c.cum = cumulative ? ll : reinterpret_cast<double*>(base + L.ll_cum);
+    c.blk_h = reinterpret_cast<int*>(base + L.ll_blk_h);
+    c.blk_v = reinterpret_cast<double*>(base + L.ll_blk_v);
+    c.blk_first = reinterpret_cast<int*>(base + L.ll_blk_first);
+    c.carry = reinterpret_cast<double*>(base + L.ll_carry);
+    c.tot = tot;
+    c.nblk = ll_blocks(total);
+    prof_begin("k_ll_block_scan", s);
+    if (seg) hipLaunchKernelGGL(k_ll_block_scan<true>, dim3((unsigned)c.nblk), dim3(kLLThreads), 0, s, c);
+    else hipLaunchKernelGGL(k_ll_block_scan<false>, dim3((unsigned)c.nblk), dim3(kLLThreads), 0, s, c);
+    prof_end(s);
+    prof_begin("k_ll_top", s);
+    if (seg) hipLaunchKernelGGL(k_ll_top<true>, dim3(1), dim3(kTopThreads), 0, s, c);
+    else hipLaunchKernelGGL(k_ll_top<false>, dim3(1), dim3(kTopThreads), 0, s, c);
+    prof_end(s);
+    if (cumulative) {
+        prof_begin("k_ll_fixup", s);
+        hipLaunchKernelGGL(k_ll_fixup, dim3((unsigned)((total + kLLThreads - 1) / kLLThreads)), dim3(kLLThreads),
+                           0, s, c);
+        prof_end(s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pks

@@ -18,11 +18,13 @@ namespace pks {
 //   eta_k = w  + W  y_k,   w  = -W (H u + d),    W = F^T H^T S^-1
 //   b_1   = c1 + K1 y_1,   c1 = m1 - K1 (H m1 + d), m1 = F m0 + u
 // G = H F and S = H Q H^T + R are kept as well: J = F^T H^T S^-1 H F = W G has
-// rank ny, which the single-step combines use.
+// rank ny, which the single-step combines use.  With e = H u + d they also
+// give the one-step predictive density of y_k from the filtered moments of
+// step k-1: N(G m_{k-1} + e, G P_{k-1} G^T + S) (the marginal likelihood).
 // All matrices row-major, full (not packed).
 // ---------------------------------------------------------------------------
 struct ConstLayout {
-    int A, C, J, K, W, c, w, K1, c1, C1, F, Q, u, G, S, words;
+    int A, C, J, K, W, c, w, K1, c1, C1, F, Q, u, G, S, e, words;
 };
 __host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
     ConstLayout L;
@@ -40,6 +42,7 @@ __host__ __device__ inline ConstLayout const_layout(int nx, int ny) {
     L.C1 = o; o += n2;
     L.G = o; o += nm;        // H F         [ny][nx]  (J = W G: the rank-ny factors of J)
     L.S = o; o += ny * ny;   // H Q H^T + R [ny][ny]
+    L.e = o; o += ny;        // H u + d     [ny]
     // smoother constants last: a filter-only precompute writes [0, F)
     L.F = o; o += n2;
     L.Q = o; o += n2;
@@ -71,6 +74,9 @@ struct WsLayout {
     size_t carry;         // per-wave incoming moments, SoA (level 0)
     size_t thr1, agg1, carry1;  // same for level 1 (scan over level-0 aggregates)
     size_t large;         // large-state path scratch
+    size_t ll_step;       // [total] double: log p(y_k | y_1:k-1) when not returned
+    size_t ll_cum;        // [total] double: prefix sums inside blocks of kLLBlock steps
+    size_t ll_blk_h, ll_blk_v, ll_blk_first, ll_carry;   // [blocks] int32 / double
     size_t total;
     // sizes used for capacity checks
     int64_t cap_thr, cap_waves, cap_thr1, cap_waves1;
@@ -131,6 +137,17 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
 // passes: 1 = filter, 2 = smoother, 3 = both (fused where possible)
 hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
+
+// marginal likelihood (loglik.hip)
+constexpr int kLLBlock = 1024;      // steps per block of the prefix sums
+int64_t ll_blocks(int64_t total);
+// Per-step log predictive densities of the filtered sequences (ll: [total] or
+// nullptr), or with `cumulative` their running sums within each sequence, and
+// per-sequence totals (tot: [B] or nullptr).  offsets = nullptr: one sequence.
+// Needs the filter constants of the model in ws (launch_precompute, what 1).
+hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
+                         const void* y, const void* m, const void* P, double* ll, double* tot,
+                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s);
 
 // large-state path (scan_large.hip), 5 <= nx <= 64
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);

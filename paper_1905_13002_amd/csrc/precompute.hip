@@ -195,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     bmm(out + CL.C, Kt, true, T1, false, nx, ny, nx, -1.0, Q);  // Q - K H Q
     bsym(out + CL.C, nx);
     bmm(e, H, false, uz, false, ny, nx, 1, 1.0, dz);          // H u + d
+    bcopy(out + CL.e, e, ny);
     bmm(out + CL.c, Kt, true, e, false, nx, ny, 1, -1.0, uz);  // u - K e
     bmm(out + CL.w, Z, true, e, false, nx, ny, 1, -1.0);       // -W e
 
@@ -413,7 +414,10 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         for (int i = 0; i < n2; ++i) out.put(CL.C + i, X[i]);
         SP::template mm<NY, NX, 1, false, false>(e, H, u);           // H u + d
 #pragma unroll
-        for (int i = 0; i < NY; ++i) e[i] += d[i];
+        for (int i = 0; i < NY; ++i) {
+            e[i] += d[i];
+            out.put(CL.e + i, e[i]);
+        }
         SP::template mm<NX, NY, 1, true, false>(v, Kt, e);
 #pragma unroll
         for (int i = 0; i < NX; ++i) out.put(CL.c + i, u[i] - v[i]);

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "PKS_OK", 1: "PKS_E_ARG", 2: "PKS_E_UNSUPPORTED", 3: "PKS_E_W
 EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smooth",
             "pks_filter_batched", "pks_smooth_batched", "pks_plan_create", "pks_plan_launch",
             "pks_plan_destroy", "pks_autotune", "pks_read_numeric_status", "pks_last_error",
-            "pks_version", "pks_profile_start", "pks_profile_stop"]
+            "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched"]
 
 
 class PksError(RuntimeError):
@@ -59,6 +59,9 @@ def _load():
         "pks_smooth_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_plan_create": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz,
                                            ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
+        "pks_loglik": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz, vp]),
+        "pks_loglik_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz,
+                                              vp]),
         "pks_plan_launch": (ctypes.c_int, [vp, vp]),
         "pks_plan_destroy": (ctypes.c_int, [vp]),
         "pks_autotune": (ctypes.c_int, [i32, i32, i32, i64, ctypes.c_int, ctypes.c_char_p, vp]),
@@ -229,6 +232,39 @@ def smooth_batched(model: DeviceModel, offsets: torch.Tensor, m: torch.Tensor, P
     _check(lib.pks_smooth_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(m), _ptr(P), _ptr(ms_),
                                   _ptr(Ps_), prec, _ptr(ws), ws.numel(), _stream(stream)))
     return ms_, Ps_
+
+
+def loglik(model: DeviceModel, y: torch.Tensor, m: torch.Tensor, P: torch.Tensor, precision="fp64",
+           cumulative=False, steps=True, ws=None, stream=None):
+    """Marginal likelihood from filter outputs: returns (ll [T] or None, total [1]).
+
+    ll holds log p(y_k | y_1:k-1), or log p(y_1:k) when ``cumulative``;
+    total is log p(y_1:T).  ``steps=False`` skips ll (total only)."""
+    prec = _prec(precision)
+    T = y.shape[0]
+    ll = torch.empty(T, dtype=torch.float64, device=y.device) if (steps or cumulative) else None
+    tot = torch.empty(1, dtype=torch.float64, device=y.device)
+    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, y.device)
+    st = model.struct()
+    _check(lib.pks_loglik(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ll), _ptr(tot),
+                          1 if cumulative else 0, prec, _ptr(ws), ws.numel(), _stream(stream)))
+    return ll, tot
+
+
+def loglik_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, m: torch.Tensor,
+                   P: torch.Tensor, precision="fp64", cumulative=False, steps=True, ws=None, stream=None):
+    """Batched marginal likelihood: returns (ll [total] or None, totals [B])."""
+    prec = _prec(precision)
+    B = offsets.shape[0] - 1
+    total = y.shape[0]
+    ll = torch.empty(total, dtype=torch.float64, device=y.device) if (steps or cumulative) else None
+    tot = torch.empty(B, dtype=torch.float64, device=y.device)
+    ws = ws if ws is not None else workspace(model.nx, model.ny, total, B, prec, y.device)
+    st = model.struct()
+    _check(lib.pks_loglik_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P),
+                                  _ptr(ll), _ptr(tot), 1 if cumulative else 0, prec, _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return ll, tot
 
 
 class Plan:

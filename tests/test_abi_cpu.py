@@ -129,3 +129,39 @@ def test_plan_and_tuner_argument_errors():
         if old is not None:
             os.environ["PKS_TUNE_CACHE"] = old
     assert lib.pks_autotune(0, 2, 1, 1000, 0, b"/tmp/x.json", None) == pks.PKS_E_ARG
+
+
+def test_loglik_argument_errors():
+    m = fake_model()
+    wsb = lib.pks_workspace_bytes(4, 2, 16, 1, 0)
+    y, mm, P, ll, tot, ws = (FAKE + 0x1000000, FAKE + 0x2000000, FAKE + 0x3000000, FAKE + 0x4000000,
+                             FAKE + 0x5000000, FAKE + 0x8000000)
+    call = lambda **kw: lib.pks_loglik(
+        kw.get("model", ctypes.byref(m)), kw.get("T", 16), kw.get("y", y), kw.get("m", mm), kw.get("P", P),
+        kw.get("ll", ll), kw.get("tot", tot), kw.get("cum", 0), kw.get("prec", 0), kw.get("ws", ws),
+        kw.get("wsb", wsb), None)
+    assert call(model=None) == pks.PKS_E_ARG
+    assert call(ll=None, tot=None) == pks.PKS_E_ARG              # no output
+    assert call(ll=None, cum=1) == pks.PKS_E_ARG                 # prefix sums need ll
+    assert call(y=None) == pks.PKS_E_ARG
+    assert call(P=None) == pks.PKS_E_ARG
+    assert call(T=-1) == pks.PKS_E_ARG
+    assert call(prec=2) == pks.PKS_E_ARG
+    assert call(ws=None) == pks.PKS_E_ARG
+    assert call(wsb=wsb - 1) == pks.PKS_E_WORKSPACE
+    assert call(ll=y + 8) == pks.PKS_E_ARG                       # ll overlaps y
+    assert call(tot=ll + 8) == pks.PKS_E_ARG                     # total overlaps ll
+    assert call(model=ctypes.byref(fake_model(per_sequence=1))) == pks.PKS_E_ARG
+    mb = fake_model(per_sequence=1)
+    wsb3 = lib.pks_workspace_bytes(4, 2, 100, 3, 0)
+    assert lib.pks_loglik_batched(ctypes.byref(mb), 0, FAKE, 100, y, mm, P, ll, tot, 0, 0, ws, wsb3,
+                                  None) == pks.PKS_E_ARG
+    assert lib.pks_loglik_batched(ctypes.byref(mb), 3, None, 100, y, mm, P, ll, tot, 0, 0, ws, wsb3,
+                                  None) == pks.PKS_E_ARG
+
+
+def test_workspace_covers_loglik_buffers():
+    # two doubles per step (factors and block prefix sums) plus the block aggregates
+    a = lib.pks_workspace_bytes(4, 2, 1 << 20, 1, 0)
+    b = lib.pks_workspace_bytes(4, 2, 2 << 20, 1, 0)
+    assert b - a >= 16 * (1 << 20)
