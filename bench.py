@@ -11,6 +11,12 @@ FP32 mode is measured the same way and reported beside it, with the maximum
 per-step relative error of every result against the sequential FP64 oracle.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2|4]
+    python bench.py --op loglik [--workload 2|4]
+
+With --op loglik a step is instead one evaluation of the marginal likelihood
+(Section III-C) from filtered moments already in HBM: every factor
+log p(y_k | y_1:k-1), every partial sum log p(y_1:k) and the totals
+(pks_loglik with cumulative output).
 
 Prints exactly one JSON line.
 """
@@ -67,6 +73,16 @@ def kernel_model(nx, ny, rs):
         "k_smoother_reduce": per_step["reduce_s"], "k_large_smoother_reduce": per_step["reduce_s"],
         "k_smoother_down": per_step["down_s"], "k_large_smoother_down": per_step["down_s"],
     }
+
+
+def ll_kernel_model(nx, ny, rs):
+    """Per-step algorithmic work of the likelihood kernels: the factor kernel
+    reads y_k and the moments of step k-1 and writes one double; its flops are
+    G P G^T (lower half), the residual, a Cholesky factorisation and one
+    triangular solve.  The block scan reads and writes one double per step."""
+    flops = 2 * ny * nx * nx + ny * (ny + 1) * nx + 2 * ny * nx + ny ** 3 / 3 + ny * ny + 6 * ny
+    k = dict(bytes=(ny + nx + nx * nx) * rs + 8, flops=flops)
+    return {"k_ll_steps": k, "k_ll_block_scan": dict(bytes=16, flops=1), "k_ll_fixup": dict(bytes=16, flops=1)}
 
 
 KERNEL_SOURCES = ["paper_1905_13002_amd/csrc/small_ops.hpp", "paper_1905_13002_amd/csrc/scan_small_impl.hpp"]
@@ -194,13 +210,16 @@ def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def summarize_trace(base, wid):
-    """Write profiles/<workload>_kernels.md from a rocprofv3 kernel trace of
-    `bench.py --workload wid` under `base` (calls and mean duration per kernel)."""
+def summarize_trace(base, wid, op="filter_smooth"):
+    """Write profiles/<workload>_kernels.md (loglik_<workload>_kernels.md for
+    --op loglik) from a rocprofv3 kernel trace of `bench.py --workload wid`
+    under `base` (calls and mean duration per kernel)."""
     import sqlite3
     import re
     from paper_1905_13002_amd import workloads as wl
     name = wl.WORKLOAD_NAMES[wid]
+    ll = op == "loglik"
+    opt = " --op loglik" if ll else ""
     db = [f for f in sorted(os.listdir(base)) if f.endswith("_results.db")]
     if not db:
         raise FileNotFoundError("no *_results.db under %s" % base)
@@ -212,19 +231,22 @@ def summarize_trace(base, wid):
         n = m.group(1) if m else n
         if n.startswith("k_"):
             rows.append((n, int(calls), float(avg), float(tot)))
-    cmd = ("rocprofv3 --kernel-trace --stats -d %s -o trace -- python bench.py --workload %d --steps 2 --warmup 1 "
-           "--no-cpu-baseline" % (base.rstrip("/"), wid))
-    lines = ["# Kernel profile: %s, filter + smoother" % name, "",
+    cmd = ("rocprofv3 --kernel-trace --stats -d %s -o trace -- python bench.py --workload %d%s --steps 2 "
+           "--warmup 1 --no-cpu-baseline" % (base.rstrip("/"), wid, opt))
+    what = "marginal likelihood (filter, then factors + partial sums + totals)" if ll else "filter + smoother"
+    lines = ["# Kernel profile: %s, %s" % (name, what), "",
              "`rocprofv3` kernel trace on one MI355X, library built from this tree.  Commands (repository root):", "",
-             "```", cmd, "python bench.py --summarize-trace %s --workload %d" % (base.rstrip("/"), wid), "```", "",
+             "```", cmd, "python bench.py --summarize-trace %s --workload %d%s" % (base.rstrip("/"), wid, opt),
+             "```", "",
              "The bench runs the FP64 path and then the mixed path (warm-up, timed passes and one pass with HIP "
              "events each); `avg_us` is the mean kernel duration over all dispatches, `total_ms` the sum.", "",
              "| kernel | calls | avg_us | total_ms |", "|---|---:|---:|---:|"]
     for n, calls, avg, tot in rows:
         lines.append("| `%s` | %d | %.1f | %.2f |" % (n, calls, avg, tot / 1e3))
-    with open(os.path.join(ROOT, "profiles", "%s_kernels.md" % name), "w") as fh:
+    out = ("loglik_" if ll else "") + name
+    with open(os.path.join(ROOT, "profiles", "%s_kernels.md" % out), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    print("wrote profiles/%s_kernels.md" % name)
+    print("wrote profiles/%s_kernels.md" % out)
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -244,6 +266,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--op", default="filter_smooth", choices=["filter_smooth", "loglik"],
+                    help="what a timed step runs (default: the filter + smoother pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -257,7 +281,7 @@ def main():
         summarize_profiles(args.summarize_profiles, "cv_T1048576")
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.workload)
+        summarize_trace(args.summarize_trace, args.workload, args.op)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -283,6 +307,9 @@ def main():
         del src, dst
     w = wl.workload(args.workload)
     progress("workload %s generated (%d steps, %d sequences)" % (w.name, w.total, w.B))
+    if args.op == "loglik":
+        bench_loglik(args, w, np, torch, oracle, pks, wl, dev)
+        return
     T = w.total
     nx, ny = w.model.nx, w.model.ny
     batched = w.B > 1
@@ -451,6 +478,114 @@ def main():
             "roofline": rlm,
             "kernels_ms": {k: round(v, 4) for k, v in kernm.items()},
         },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
+    T, B = w.total, w.B
+    nx, ny = w.model.nx, w.model.ny
+    batched = B > 1
+    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence)
+    off = torch.as_tensor(w.offsets).to(dev) if batched else None
+    results = {}
+    for prec in ("fp64", "mixed"):
+        rdt = torch.float64 if prec == "fp64" else torch.float32
+        y = torch.as_tensor(w.y).to(dev, rdt)
+        ws = pks.workspace(nx, ny, T, B, prec, dev)
+        if batched:
+            m, P = pks.filter_batched(dm, off, y, prec, ws=ws)
+            step = lambda: pks.loglik_batched(dm, off, y, m, P, prec, cumulative=True, ws=ws)
+        else:
+            m, P = pks.filter(dm, y, prec, ws=ws)
+            step = lambda: pks.loglik(dm, y, m, P, prec, cumulative=True, ws=ws)
+        sec = time_steps(step, args.steps, args.warmup, torch)
+        pks.profile_start()
+        for _ in range(args.steps):
+            out = step()
+        prof = pks.profile_stop()
+        torch.cuda.synchronize()
+        results[prec] = dict(sec=sec, prof=prof, cum=out[0].cpu().numpy(), tot=out[1].cpu().numpy())
+        progress("%s timed: %.4f ms per evaluation" % (prec, sec * 1e3))
+
+    # accuracy: the oracle's factors summed per sequence (sampled sequences when batched)
+    sample = list(range(B)) if not batched else sorted(set([0, B - 1] + list(range(0, B, max(1, B // 64)))))
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        yy = w.y if prec == "fp64" else w.y.astype(np.float32).astype(np.float64)
+        e_tot, e_cum = 0.0, 0.0
+        for b in sample:
+            mo = w.model_of(b) if batched else w.model
+            s_ = w.seq(b) if batched else slice(0, T)
+            ref = oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, yy[s_], smooth=False, loglik=True)["ll"]
+            rc = np.cumsum(ref)
+            g = results[prec]["cum"][s_]
+            e_cum = max(e_cum, float(np.max(np.abs(g - rc) / np.maximum(1.0, np.abs(rc)))))
+            e_tot = max(e_tot, abs(results[prec]["tot"][b] - rc[-1]) / max(1.0, abs(rc[-1])))
+        errs[prec] = dict(total=float("%.3e" % e_tot), partial_sums=float("%.3e" % e_cum))
+        progress("%s checked against the oracle on %d sequences" % (prec, len(sample)))
+
+    def roofline(prec):
+        rs = 8 if prec == "fp64" else 4
+        km = ll_kernel_model(nx, ny, rs)["k_ll_steps"]
+        prof = results[prec]["prof"]
+        per_launch = {k: tot / max(1, n) for k, (tot, n) in prof.items()}
+        dur_s = per_launch["k_ll_steps"] * 1e-3
+        ach = km["bytes"] * T / dur_s / 1e9
+        rl = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                  frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel="k_ll_steps",
+                  kernel_ms=round(per_launch["k_ll_steps"], 4), algorithmic_bytes_per_launch=km["bytes"] * T,
+                  algorithmic_flops_per_launch=km["flops"] * T)
+        return per_launch, rl
+
+    kern64, rl64 = roofline("fp64")
+    kernm, rlm = roofline("mixed")
+    cpu = None
+    if not args.no_cpu_baseline:
+        nsteps, dt, nseq = 0, 0.0, 0
+        t_start = time.perf_counter()
+        while time.perf_counter() - t_start < args.cpu_seconds:
+            for b in (sample if batched else [0]):
+                mo = w.model_of(b) if batched else w.model
+                s_ = w.seq(b) if batched else slice(0, T)
+                offs = np.array([0, s_.stop - s_.start])
+                t0 = time.perf_counter()
+                ll = oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y[s_], smooth=False, loglik=True)["ll"]
+                oracle.loglik_prefix(ll, offs)
+                dt += time.perf_counter() - t0
+                nsteps += s_.stop - s_.start
+                nseq += 1
+                if time.perf_counter() - t_start > args.cpu_seconds:
+                    break
+        cpu = dict(value=nsteps / dt, unit="time steps/s", cores=1, kind="oracle",
+                   sample="%d sequence runs (%d steps): sequential C FP64 Kalman filter with the per-step "
+                          "factors, then their running sums; 1 thread; includes the filter, which the GPU "
+                          "figure does not" % (nseq, nsteps))
+        progress("oracle baseline on the host: %.3e steps/s" % cpu["value"])
+    sec64, secm = results["fp64"]["sec"], results["mixed"]["sec"]
+    line = {
+        "metric": "log-likelihood time steps/sec (every factor, partial sum and total from filtered moments)",
+        "value": T / sec64,
+        "unit": "time steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded simulation of the model)",
+        "config": {"workload": w.name, "T": T, "B": B, "nx": nx, "ny": ny,
+                   "path": "pks_loglik_batched" if batched else "pks_loglik", "cumulative": True},
+        "max_rel_err": errs["fp64"],
+        "err_sample": "all steps" if not batched else "%d of %d sequences" % (len(sample), B),
+        "roofline": rl64,
+        "kernels_ms": {k: round(v, 4) for k, v in kern64.items()},
+        "mixed": {"value": T / secm, "ms_per_step": secm * 1e3, "dtype": "f32 inputs, f64 arithmetic",
+                  "max_rel_err": errs["mixed"], "roofline": rlm,
+                  "kernels_ms": {k: round(v, 4) for k, v in kernm.items()}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
