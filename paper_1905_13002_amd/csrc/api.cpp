@@ -106,6 +106,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.ll_blk_v = o; o = align256(o + sizeof(double) * (size_t)nblk);
     L.ll_blk_first = o; o = align256(o + sizeof(int32_t) * (size_t)nblk);
     L.ll_carry = o; o = align256(o + sizeof(double) * (size_t)nblk);
+    L.ll_tile_seq = o; o = align256(o + sizeof(int32_t) * (size_t)(total / 256 + 2));
     L.total = o;
     return L;
 }

@@ -20,12 +20,17 @@
 // widened first.
 //
 // Kernels
-//   k_ll_small<NX,NY,R,SEG>  nx, ny <= 4: one step per lane; the moments of the
-//                            previous steps are staged through LDS in whole
-//                            rows (coalesced loads, odd row stride).
+//   k_ll_small<NX,NY,R,SEG>  nx, ny <= 4: one step per lane, persistent over
+//                            tiles of 256 steps; the moments of the previous
+//                            steps are loaded coalesced and staged through LDS
+//                            (odd row stride), the next tile's loads in flight
+//                            while the current one is evaluated.
 //   k_ll_wave<R,SEG>         any size: one wavefront per step; P_{k-1}, G P_{k-1}
 //                            and S in LDS, the Cholesky factorisation and the
 //                            forward substitution row-parallel across lanes.
+//   k_ll_tile_seq            batched: the sequence of every tile's first step
+//                            (one search each), so that a lane only searches
+//                            between two neighbouring entries.
 //   k_ll_block_scan<SEG>     segmented inclusive prefix sums inside blocks of
 //                            kLLBlock steps; per block its aggregate (whether
 //                            a sequence starts in it, sum since the last start)
@@ -47,8 +52,9 @@ namespace pks {
 
 namespace {
 
-constexpr int kLLThreads = 256;                     // per-step kernels, block scan
-constexpr int kLLPerThread = kLLBlock / kLLThreads; // steps per thread in the block scan
+constexpr int kLLThreads = 256;                     // per-step kernels (a tile of 256 steps)
+constexpr int kScanThreads = 1024;                  // block scan
+constexpr int kLLPerThread = kLLBlock / kScanThreads; // steps per thread in the block scan
 constexpr int kTopThreads = 1024;
 constexpr double kLog2Pi = 1.8378770664093454836;   // log(2 pi)
 
@@ -68,6 +74,7 @@ struct LLArgs {
     const void* P;
     double* step;                  // [total] out: log p(y_k | y_1:k-1)
     int* status;
+    const int* tile_seq;           // [tiles + 1] sequence of each tile's first step (batched)
 };
 
 // sequence index and first step of step k (k < total)
@@ -86,36 +93,42 @@ __device__ __forceinline__ int seq_of(const int64_t* off, int B, int64_t k, int6
     return lo;
 }
 
+// Sequence of step k when it is known to lie in [lo, hi] (from the tile table).
+template <bool SEG>
+__device__ __forceinline__ int seq_between(const int64_t* off, int lo, int hi, int64_t k, int64_t& start) {
+    if (!SEG) {
+        start = 0;
+        return 0;
+    }
+    ++hi;                       // invariant: off[lo] <= k < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    start = off[lo];
+    return lo;
+}
+
+// tile_seq[i] = sequence of step 256 i (i < tiles), tile_seq[tiles] = sequence
+// of the last step: every step of tile i belongs to a sequence in
+// [tile_seq[i], tile_seq[i + 1]].  One independent search per entry.
+__global__ __launch_bounds__(kLLThreads) void k_ll_tile_seq(const int64_t* off, int B, int64_t total,
+                                                             int64_t tiles, int* tile_seq) {
+    const int64_t i = (int64_t)blockIdx.x * kLLThreads + threadIdx.x;
+    if (i > tiles) return;
+    const int64_t k = i < tiles ? i * kLLThreads : total - 1;
+    int64_t start;
+    tile_seq[i] = seq_of<true>(off, B, k, start);
+}
+
 // ---------------------------------------------------------------------------
 // nx, ny <= 4: one step per lane
 // ---------------------------------------------------------------------------
+// The log factor of step k from the filtered moments of step k-1 (row: m then
+// P, in LDS) or, at a sequence start, from the prior of its model.
 template <int NX, int NY, typename R, bool SEG>
-__global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a) {
-    constexpr int n2 = NX * NX, RW = NX + n2;
-    constexpr int ROW = (RW & 1) ? RW : RW + 1;     // odd row stride: lanes hit distinct banks
-    __shared__ R stage[kLLThreads * ROW];
-    const int t = threadIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.x * kLLThreads;
-    // rows r = 0 .. 255 hold the moments of steps k0-1 .. k0+254
-    const R* gm = static_cast<const R*>(a.m);
-    const R* gP = static_cast<const R*>(a.P);
-    for (int i = t; i < kLLThreads * NX; i += kLLThreads) {
-        const int r = i / NX, c = i - r * NX;
-        const int64_t kk = k0 - 1 + r;
-        if (kk >= 0 && kk < a.total) stage[r * ROW + c] = gm[kk * NX + c];
-    }
-    for (int i = t; i < kLLThreads * n2; i += kLLThreads) {
-        const int r = i / n2, c = i - r * n2;
-        const int64_t kk = k0 - 1 + r;
-        if (kk >= 0 && kk < a.total) stage[r * ROW + NX + c] = gP[kk * n2 + c];
-    }
-    __syncthreads();
-    const int64_t k = k0 + t;
-    if (k >= a.total) return;
-    int64_t start;
-    const int b = seq_of<SEG>(a.offsets, a.B, k, start);
-    const bool first = k == start;
-
+__device__ __forceinline__ void ll_step_small(const LLArgs& a, int64_t k, int b, bool first, const R* row) {
+    constexpr int n2 = NX * NX;
     double m[NX], P[n2];
     if (first) {
         const int64_t ps = a.per_sequence ? b : 0;
@@ -125,9 +138,9 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a) {
         for (int i = 0; i < n2; ++i) P[i] = a.P0[ps * n2 + i];
     } else {
 #pragma unroll
-        for (int i = 0; i < NX; ++i) m[i] = (double)stage[t * ROW + i];
+        for (int i = 0; i < NX; ++i) m[i] = (double)row[i];
 #pragma unroll
-        for (int i = 0; i < n2; ++i) P[i] = (double)stage[t * ROW + NX + i];
+        for (int i = 0; i < n2; ++i) P[i] = (double)row[NX + i];
     }
     const double* cst = a.consts64 + a.cstride * b;
     double G[NY * NX], S[NY * NY], r[NY];
@@ -197,6 +210,62 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a) {
     a.step[k] = ll;
 }
 
+// Persistent over tiles of 256 steps: the moments of the steps before a tile
+// (rows r = 0 .. 255 hold steps k0-1 .. k0+254) are loaded coalesced into
+// registers, stored to an LDS stage with an odd row stride, and read back one
+// row per lane.  The loads of the next tile are issued before the current
+// tile is evaluated, so they are in flight during its arithmetic.
+template <int NX, int NY, typename R, bool SEG>
+__global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a, int64_t ntiles) {
+    constexpr int n2 = NX * NX, RW = NX + n2;
+    constexpr int ROW = (RW & 1) ? RW : RW + 1;     // odd row stride: lanes hit distinct banks
+    __shared__ R stage[kLLThreads * ROW];
+    const int t = threadIdx.x;
+    const R* gm = static_cast<const R*>(a.m);
+    const R* gP = static_cast<const R*>(a.P);
+    // thread t carries words t + 256 j of the tile's m block (j < NX) and P block (j < n2)
+    R buf[RW];
+    auto load = [&](int64_t tile) {
+        const int64_t k0 = tile * kLLThreads;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            const int i = t + kLLThreads * j, r = i / NX;
+            const int64_t kk = k0 - 1 + r;
+            buf[j] = (kk >= 0 && kk < a.total) ? gm[(k0 - 1) * NX + i] : R(0);
+        }
+#pragma unroll
+        for (int j = 0; j < n2; ++j) {
+            const int i = t + kLLThreads * j, r = i / n2;
+            const int64_t kk = k0 - 1 + r;
+            buf[NX + j] = (kk >= 0 && kk < a.total) ? gP[(k0 - 1) * n2 + i] : R(0);
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) load(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+            const int i = t + kLLThreads * j, r = i / NX;
+            stage[r * ROW + (i - r * NX)] = buf[j];
+        }
+#pragma unroll
+        for (int j = 0; j < n2; ++j) {
+            const int i = t + kLLThreads * j, r = i / n2;
+            stage[r * ROW + NX + (i - r * n2)] = buf[NX + j];
+        }
+        __syncthreads();
+        if (tile + gridDim.x < ntiles) load(tile + gridDim.x);
+        const int64_t k0 = tile * kLLThreads, k = k0 + t;
+        if (k < a.total) {
+            int64_t start;
+            const int b = SEG ? seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k, start)
+                              : seq_between<false>(a.offsets, 0, 0, k, start);
+            ll_step_small<NX, NY, R, SEG>(a, k, b, k == start, stage + t * ROW);
+        }
+        __syncthreads();                            // the stage is rewritten next
+    }
+}
+
 // ---------------------------------------------------------------------------
 // any size: one wavefront per step
 // ---------------------------------------------------------------------------
@@ -227,7 +296,9 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
     const R* gy = static_cast<const R*>(a.y);
     for (int64_t k = (int64_t)blockIdx.x * nw + wave; k < a.total; k += (int64_t)gridDim.x * nw) {
         int64_t start;
-        const int b = seq_of<SEG>(a.offsets, a.B, k, start);
+        const int64_t tile = k / kLLThreads;
+        const int b = SEG ? seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k, start)
+                          : seq_between<false>(a.offsets, 0, 0, k, start);
         const double* cst = a.consts64 + a.cstride * b;
         const double* G = cst + a.cG;
         if (k == start) {
@@ -361,10 +432,11 @@ struct LLScanArgs {
     double* carry;          // [nblk] sum carried into each block
     double* tot;            // [B] per-sequence totals (nullptr: not wanted)
     int64_t nblk;
+    const int* tile_seq;    // as in LLArgs
 };
 
 template <bool SEG>
-__global__ __launch_bounds__(kLLThreads) void k_ll_block_scan(LLScanArgs a) {
+__global__ __launch_bounds__(kScanThreads) void k_ll_block_scan(LLScanArgs a) {
     __shared__ int first_sh;
     const int t = threadIdx.x;
     if (t == 0) first_sh = kLLBlock;
@@ -375,7 +447,8 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_block_scan(LLScanArgs a) {
     int64_t start = 0, end = a.total;
     int b = 0;
     if (SEG && k0 < a.total) {
-        b = seq_of<true>(a.offsets, a.B, k0, start);
+        const int64_t tile = k0 / kLLThreads;
+        b = seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k0, start);
         end = a.offsets[b + 1];
     }
 #pragma unroll
@@ -399,7 +472,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_block_scan(LLScanArgs a) {
     __syncthreads();                         // first_sh initialised
     if (heads) atomicMin(&first_sh, t * kLLPerThread + __builtin_ctz(heads));
     Seg blk;
-    const Seg ex = block_exclusive<kLLThreads>(x, &blk);
+    const Seg ex = block_exclusive<kScanThreads>(x, &blk);
 #pragma unroll
     for (int q = 0; q < kLLPerThread; ++q) {
         const int64_t k = k0 + q;
@@ -446,25 +519,52 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_fixup(LLScanArgs a) {
     if (k - c * kLLBlock < a.blk_first[c]) a.cum[k] += a.carry[c];
 }
 
+int device_cus() {
+    static int cus = 0;
+    if (cus <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Persistent grid: as many workgroups as fit on the device at once, but no
+// more than there are tiles, with the tiles spread evenly over them.
+template <int NX, int NY, typename R, bool SEG>
+void launch_small_kernel(const LLArgs& a, hipStream_t s) {
+    static int per_cu = 0;
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ll_small<NX, NY, R, SEG>, kLLThreads, 0) !=
+                hipSuccess || per_cu <= 0)
+            per_cu = 1;
+    }
+    const int64_t ntiles = (a.total + kLLThreads - 1) / kLLThreads;
+    const int64_t slots = (int64_t)per_cu * device_cus();
+    const int64_t rounds = (ntiles + slots - 1) / slots;
+    const int64_t grid = (ntiles + rounds - 1) / rounds;
+    hipLaunchKernelGGL((k_ll_small<NX, NY, R, SEG>), dim3((unsigned)grid), dim3(kLLThreads), 0, s, a, ntiles);
+}
+
 template <int NX, typename R, bool SEG>
-bool launch_small_ny(int ny, const LLArgs& a, dim3 grid, hipStream_t s) {
+bool launch_small_ny(int ny, const LLArgs& a, hipStream_t s) {
     switch (ny) {
-        case 1: hipLaunchKernelGGL((k_ll_small<NX, 1, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
-        case 2: hipLaunchKernelGGL((k_ll_small<NX, 2, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
-        case 3: hipLaunchKernelGGL((k_ll_small<NX, 3, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
-        case 4: hipLaunchKernelGGL((k_ll_small<NX, 4, R, SEG>), grid, dim3(kLLThreads), 0, s, a); return true;
+        case 1: launch_small_kernel<NX, 1, R, SEG>(a, s); return true;
+        case 2: launch_small_kernel<NX, 2, R, SEG>(a, s); return true;
+        case 3: launch_small_kernel<NX, 3, R, SEG>(a, s); return true;
+        case 4: launch_small_kernel<NX, 4, R, SEG>(a, s); return true;
         default: return false;
     }
 }
 
 template <typename R, bool SEG>
 bool launch_small_ll(const LLArgs& a, hipStream_t s) {
-    const dim3 grid((unsigned)((a.total + kLLThreads - 1) / kLLThreads));
     switch (a.nx) {
-        case 1: return launch_small_ny<1, R, SEG>(a.ny, a, grid, s);
-        case 2: return launch_small_ny<2, R, SEG>(a.ny, a, grid, s);
-        case 3: return launch_small_ny<3, R, SEG>(a.ny, a, grid, s);
-        case 4: return launch_small_ny<4, R, SEG>(a.ny, a, grid, s);
+        case 1: return launch_small_ny<1, R, SEG>(a.ny, a, s);
+        case 2: return launch_small_ny<2, R, SEG>(a.ny, a, s);
+        case 3: return launch_small_ny<3, R, SEG>(a.ny, a, s);
+        case 4: return launch_small_ny<4, R, SEG>(a.ny, a, s);
         default: return false;
     }
 }
@@ -513,6 +613,15 @@ hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offse
     double* ws_step = reinterpret_cast<double*>(base + L.ll_step);
     a.step = (ll && !cumulative) ? ll : ws_step;
     const bool seg = offsets != nullptr;
+    const int64_t tiles = (total + kLLThreads - 1) / kLLThreads;
+    int* tile_seq = reinterpret_cast<int*>(base + L.ll_tile_seq);
+    a.tile_seq = tile_seq;
+    if (seg) {
+        prof_begin("k_ll_tile_seq", s);
+        hipLaunchKernelGGL(k_ll_tile_seq, dim3((unsigned)((tiles + 1 + kLLThreads - 1) / kLLThreads)),
+                           dim3(kLLThreads), 0, s, offsets, B, total, tiles, tile_seq);
+        prof_end(s);
+    }
     if (mixed) {
         if (seg) launch_steps<float, true>(a, s); else launch_steps<float, false>(a, s);
     } else {
@@ -532,9 +641,10 @@ hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offse
     c.carry = reinterpret_cast<double*>(base + L.ll_carry);
     c.tot = tot;
     c.nblk = ll_blocks(total);
+    c.tile_seq = tile_seq;
     prof_begin("k_ll_block_scan", s);
-    if (seg) hipLaunchKernelGGL(k_ll_block_scan<true>, dim3((unsigned)c.nblk), dim3(kLLThreads), 0, s, c);
-    else hipLaunchKernelGGL(k_ll_block_scan<false>, dim3((unsigned)c.nblk), dim3(kLLThreads), 0, s, c);
+    if (seg) hipLaunchKernelGGL(k_ll_block_scan<true>, dim3((unsigned)c.nblk), dim3(kScanThreads), 0, s, c);
+    else hipLaunchKernelGGL(k_ll_block_scan<false>, dim3((unsigned)c.nblk), dim3(kScanThreads), 0, s, c);
     prof_end(s);
     prof_begin("k_ll_top", s);
     if (seg) hipLaunchKernelGGL(k_ll_top<true>, dim3(1), dim3(kTopThreads), 0, s, c);

@@ -77,6 +77,7 @@ struct WsLayout {
     size_t ll_step;       // [total] double: log p(y_k | y_1:k-1) when not returned
     size_t ll_cum;        // [total] double: prefix sums inside blocks of kLLBlock steps
     size_t ll_blk_h, ll_blk_v, ll_blk_first, ll_carry;   // [blocks] int32 / double
+    size_t ll_tile_seq;   // [total / 256 + 2] int32: sequence of each 256-step tile's first step
     size_t total;
     // sizes used for capacity checks
     int64_t cap_thr, cap_waves, cap_thr1, cap_waves1;
@@ -139,7 +140,7 @@ hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
 
 // marginal likelihood (loglik.hip)
-constexpr int kLLBlock = 1024;      // steps per block of the prefix sums
+constexpr int kLLBlock = 4096;      // steps per block of the prefix sums
 int64_t ll_blocks(int64_t total);
 // Per-step log predictive densities of the filtered sequences (ll: [total] or
 // nullptr), or with `cumulative` their running sums within each sequence, and

@@ -279,3 +279,17 @@ def test_loglik_cv_T2pow20(pks, precision):
     against the oracle."""
     w = wl.workload(2)
     check_ll(pks, w.model, w.y, precision, what="cv T=2^20")
+
+
+def test_loglik_runs_of_empty_sequences(pks):
+    """Long runs of zero-length sequences between and inside tiles: the tile
+    table brackets a lane's search over hundreds of equal offsets."""
+    rng = np.random.default_rng(21)
+    model = wl.random_small_model(3, 2, rng)
+    lengths = [0] * 700 + [5000] + [0] * 300 + [1] + [0] * 50 + [300] + [0] * 9
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    y, _ = wl.simulate(model, int(offsets[-1]), rng)
+    check_ll(pks, model, y, "fp64", offsets=offsets, what="empty runs")
+    model6 = wl.random_stable_model(6, 2, rng, radius=0.9)
+    y6, _ = wl.simulate(model6, int(offsets[-1]), rng)
+    check_ll(pks, model6, y6, "fp64", offsets=offsets, what="empty runs 6x2")
