@@ -169,6 +169,42 @@ pks_status pks_loglik_batched(const pks_model *model, int32_t B, const int64_t *
                               int32_t cumulative, pks_precision prec, void *ws, size_t ws_bytes,
                               void *stream);
 /*
+ * Time-varying linear/Gaussian model (Section IV in its general form):
+ *     x_k = F_{k-1} x_{k-1} + u_{k-1} + q_{k-1},  q_{k-1} ~ N(0, Q_{k-1}),
+ *     y_k = H_k x_k + d_k + r_k,                  r_k ~ N(0, R_k),
+ * for k = 1..T, with x_0 ~ N(m0, P0).  Every matrix pointer is a DEVICE
+ * pointer to T stacked double matrices; row k-1 holds the step-k quantities:
+ *   F [T][nx][nx] (F_{k-1}: the transition INTO step k), Q [T][nx][nx],
+ *   u [T][nx] or NULL, H [T][ny][nx], R [T][ny][ny], d [T][ny] or NULL;
+ *   m0 [nx], P0 [nx][nx] as for pks_model.
+ * The smoothing element of step k (Lemma 3) uses the transition out of it,
+ * row k (F_k, Q_k, u_k); row 0 is used by the filter only.  Every step's
+ * Lemma 1 element is built from its own rows, so the workspace holds one
+ * block of constants per step: size it with pks_workspace_bytes_tv.  Single
+ * sequence; a failing factorisation flags sequence 0 and gives NaN outputs
+ * from that step on.
+ */
+typedef struct {
+    int32_t nx, ny;
+    const double *F, *u, *Q;
+    const double *H, *d, *R;
+    const double *m0, *P0;
+} pks_model_tv;
+/* Workspace bytes for the time-varying calls below (T <= 2^31 - 1); 0 if invalid. */
+size_t pks_workspace_bytes_tv(int32_t nx, int32_t ny, int64_t T, pks_precision prec);
+/* pks_filter, pks_smooth, pks_filter_smooth and pks_loglik for a time-varying
+ * model: same arrays, conventions and errors as their time-invariant forms. */
+pks_status pks_filter_tv(const pks_model_tv *model, int64_t T, const void *y, void *m, void *P,
+                         pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+pks_status pks_smooth_tv(const pks_model_tv *model, int64_t T, const void *m, const void *P, void *ms,
+                         void *Ps, pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+pks_status pks_filter_smooth_tv(const pks_model_tv *model, int64_t T, const void *y, void *m, void *P,
+                                void *ms, void *Ps, pks_precision prec, void *ws, size_t ws_bytes,
+                                void *stream);
+pks_status pks_loglik_tv(const pks_model_tv *model, int64_t T, const void *y, const void *m, const void *P,
+                         double *ll, double *ll_total, int32_t cumulative, pks_precision prec, void *ws,
+                         size_t ws_bytes, void *stream);
+/*
  * Plans: the whole filter + smoother of a (batched) problem, with its tile
  * configuration taken from the tuning cache, captured once into a HIP graph
  * bound to these pointers; pks_plan_launch replays it with one

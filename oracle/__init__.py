@@ -7,6 +7,8 @@ with the HIP library (``paper_1905_13002_amd``) and imports nothing from it.
 * :func:`kf_rts` / :func:`kf_rts_batched` wrap ``kfrts.c`` (plain C, FP64,
   built with ``gcc -O3 -ffp-contract=off``): the textbook recursions that the
   paper's parallel method reproduces exactly (Theorems 1 and 2).
+* :func:`kf_rts_tv` runs the same recursion on a time-varying model (one
+  row of F, u, Q, H, d, R per step; Section IV's general model).
 * ``loglik=True`` adds the per-step factors log p(y_k | y_1:k-1) of the
   marginal likelihood (Section III-C); :func:`loglik_prefix` turns them into
   log p(y_1:k) and the per-sequence totals log p(y_1:n).
@@ -48,6 +50,8 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_kf_rts.restype = ctypes.c_int
         lib.oracle_kf_rts.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long] + [dp] * 16
+        lib.oracle_kf_rts_tv.restype = ctypes.c_int
+        lib.oracle_kf_rts_tv.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long] + [dp] * 16
         lib.oracle_kf_rts_batched.restype = ctypes.c_int
         lib.oracle_kf_rts_batched.argtypes = (
             [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_long), ctypes.c_int]
@@ -93,6 +97,40 @@ def kf_rts(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False, 
     ll = np.empty(T) if loglik else None
     st = lib.oracle_kf_rts(nx, ny, T, _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0),
                            _p(y), _p(m), _p(P), _p(ms), _p(Ps), _p(mp), _p(Pp), _p(ll))
+    if st:
+        raise OracleError("oracle: Cholesky failed (code %d)" % st)
+    out = {"m": m, "P": P}
+    if smooth:
+        out.update(ms=ms, Ps=Ps)
+    if predicted:
+        out.update(mp=mp, Pp=Pp)
+    if loglik:
+        out["ll"] = ll
+    return out
+
+
+def kf_rts_tv(F, Q, H, R, m0, P0, y, u=None, d=None, smooth=True, predicted=False, loglik=False):
+    """Time-varying model: F [T,nx,nx], Q [T,nx,nx], H [T,ny,nx], R [T,ny,ny],
+    u [T,nx], d [T,ny] hold one row per step (row k-1: the transition into
+    step k and the measurement model of step k).  Same outputs as kf_rts."""
+    lib = _load()
+    F, Q, H, R, m0, P0, y = map(_f64, (F, Q, H, R, m0, P0, y))
+    u, d = _f64(u), _f64(d)
+    nx, ny = F.shape[-1], H.shape[-2]
+    y = y.reshape(-1, ny)
+    T = y.shape[0]
+    for a, shape in ((F, (T, nx, nx)), (Q, (T, nx, nx)), (H, (T, ny, nx)), (R, (T, ny, ny))):
+        if a.shape != shape:
+            raise ValueError("time-varying model arrays must be %s, got %s" % (shape, a.shape))
+    m = np.empty((T, nx))
+    P = np.empty((T, nx, nx))
+    ms = np.empty((T, nx)) if smooth else None
+    Ps = np.empty((T, nx, nx)) if smooth else None
+    mp = np.empty((T, nx)) if predicted else None
+    Pp = np.empty((T, nx, nx)) if predicted else None
+    ll = np.empty(T) if loglik else None
+    st = lib.oracle_kf_rts_tv(nx, ny, T, _p(F), _p(u), _p(Q), _p(H), _p(d), _p(R), _p(m0), _p(P0),
+                              _p(y), _p(m), _p(P), _p(ms), _p(Ps), _p(mp), _p(Pp), _p(ll))
     if st:
         raise OracleError("oracle: Cholesky failed (code %d)" % st)
     out = {"m": m, "P": P}

@@ -129,13 +129,19 @@ static void chol_solve(int n, int r, const double *L, double *B)
  * (innovation covariance S_k in the filter, P^-_{k+1} in the smoother, the
  * latter reported as T + k).
  */
-int oracle_kf_rts(int nx, int ny, long T,
-                  const double *F, const double *u, const double *Q,
-                  const double *H, const double *d, const double *R,
-                  const double *m0, const double *P0,
-                  const double *y,
-                  double *m, double *P, double *ms, double *Ps,
-                  double *mp_out, double *Pp_out, double *ll)
+/*
+ * The recursion with per-step model rows: step k (0-based) predicts with
+ * F + k*sF, u + k*su, Q + k*sQ and updates with H + k*sH, d + k*sd, R + k*sR;
+ * the RTS step at k uses the transition out of it, row k+1.  All strides 0:
+ * one time-invariant model.
+ */
+static int kf_rts_rows(int nx, int ny, long T,
+                       const double *F, long sF, const double *u, long su, const double *Q, long sQ,
+                       const double *H, long sH, const double *d, long sd, const double *R, long sR,
+                       const double *m0, const double *P0,
+                       const double *y,
+                       double *m, double *P, double *ms, double *Ps,
+                       double *mp_out, double *Pp_out, double *ll)
 {
     if (T <= 0) return 0;
     const int n2 = nx * nx;
@@ -165,7 +171,11 @@ int oracle_kf_rts(int nx, int ny, long T,
     int status = 0;
 
     const double *mprev = m0, *Pprev = P0;
+    const double *F0 = F, *u0 = u, *Q0 = Q, *H0 = H, *d0 = d, *R0 = R;
     for (long k = 0; k < T; ++k) {
+        F = F0 + k * sF; Q = Q0 + k * sQ; H = H0 + k * sH; R = R0 + k * sR;
+        u = u0 ? u0 + k * su : NULL;
+        d = d0 ? d0 + k * sd : NULL;
         double *mk = m + (size_t)k * nx, *Pk = P + (size_t)k * n2;
         double *mpk = mp + (size_t)k * nx, *Ppk = Pp + (size_t)k * n2;
         /* prediction: m^- = F m + u, P^- = F P F^T + Q */
@@ -216,6 +226,7 @@ int oracle_kf_rts(int nx, int ny, long T,
             const double *mpn = mp + (size_t)(k + 1) * nx, *Ppn = Pp + (size_t)(k + 1) * n2;
             const double *msn = ms + (size_t)(k + 1) * nx, *Psn = Ps + (size_t)(k + 1) * n2;
             double *msk = ms + (size_t)k * nx, *Psk = Ps + (size_t)k * n2;
+            F = F0 + (k + 1) * sF;            /* the transition out of step k */
             /* G = P_k F^T (P^-_{k+1})^{-1}:  P^-_{k+1} G^T = F P_k */
             memcpy(D, Ppn, sizeof(double) * n2);
             if (cholesky(nx, D)) { status = (int)(T + k + 1); goto done; }
@@ -240,6 +251,36 @@ done:
     free(work);
     free(own);
     return status;
+}
+
+int oracle_kf_rts(int nx, int ny, long T,
+                  const double *F, const double *u, const double *Q,
+                  const double *H, const double *d, const double *R,
+                  const double *m0, const double *P0,
+                  const double *y,
+                  double *m, double *P, double *ms, double *Ps,
+                  double *mp_out, double *Pp_out, double *ll)
+{
+    return kf_rts_rows(nx, ny, T, F, 0, u, 0, Q, 0, H, 0, d, 0, R, 0, m0, P0, y, m, P, ms, Ps,
+                       mp_out, Pp_out, ll);
+}
+
+/*
+ * Time-varying model (Section IV in its general form): F, u, Q, H, d, R hold
+ * one row per step; row k-1 holds F_{k-1}, u_{k-1}, Q_{k-1} (the transition
+ * into step k) and H_k, d_k, R_k.  Same outputs and return codes.
+ */
+int oracle_kf_rts_tv(int nx, int ny, long T,
+                     const double *F, const double *u, const double *Q,
+                     const double *H, const double *d, const double *R,
+                     const double *m0, const double *P0,
+                     const double *y,
+                     double *m, double *P, double *ms, double *Ps,
+                     double *mp_out, double *Pp_out, double *ll)
+{
+    const long n2 = (long)nx * nx;
+    return kf_rts_rows(nx, ny, T, F, n2, u, nx, Q, n2, H, (long)ny * nx, d, ny, R, (long)ny * ny, m0, P0,
+                       y, m, P, ms, Ps, mp_out, Pp_out, ll);
 }
 
 /* ---- many independent sequences ----------------------------------------- */

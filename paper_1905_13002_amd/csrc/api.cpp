@@ -107,6 +107,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.ll_blk_first = o; o = align256(o + sizeof(int32_t) * (size_t)nblk);
     L.ll_carry = o; o = align256(o + sizeof(double) * (size_t)nblk);
     L.ll_tile_seq = o; o = align256(o + sizeof(int32_t) * (size_t)(total / 256 + 2));
+    L.tv_offsets = o; o = align256(o + 2 * sizeof(int64_t));
     L.total = o;
     return L;
 }
@@ -115,7 +116,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
 // scan argument assembly
 // ---------------------------------------------------------------------------
 ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
-                        pks_precision prec, void* ws, const WsLayout& L, TileConfig cfg) {
+                        pks_precision prec, void* ws, const WsLayout& L, TileConfig cfg, bool tv) {
     ScanArgs a{};
     char* base = static_cast<char*>(ws);
     const ConstLayout CL = const_layout(model.nx, model.ny);
@@ -124,7 +125,8 @@ ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offset
     a.total = total;
     a.B = B;
     a.offsets = offsets;
-    a.model_stride = model.per_sequence ? CL.words : 0;
+    a.model_stride = (model.per_sequence && !tv) ? CL.words : 0;
+    a.step_stride = tv ? CL.words : 0;
     a.consts = prec == PKS_FP64 ? (const void*)(base + L.consts64) : (const void*)(base + L.consts32);
     a.consts64 = reinterpret_cast<const double*>(base + L.consts64);
     a.thr = base + L.thr;
@@ -143,16 +145,17 @@ ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offset
     }
     a.status = reinterpret_cast<int*>(base + L.status);
     a.model_fail = reinterpret_cast<const int*>(base + L.model_fail);
-    a.nmodels = model.per_sequence ? B : 1;
+    // a time-varying precompute flags failing steps itself: nothing to collect
+    a.nmodels = tv ? 0 : (model.per_sequence ? B : 1);
     return a;
 }
 
 // Enqueue the requested passes.  passes: 1 = filter, 2 = smoother, 3 = both.
 pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
                    const void* y, void* m, void* P, void* ms, void* Ps, pks_precision prec,
-                   void* ws, size_t ws_bytes, int passes, const TileConfig* forced, hipStream_t s) {
-    const int nmodels = model.per_sequence ? B : 1;
-    const WsLayout L = ws_layout(model.nx, model.ny, total, B, prec);
+                   void* ws, size_t ws_bytes, int passes, const TileConfig* forced, hipStream_t s, bool tv) {
+    const int nmodels = tv ? (int)total : (model.per_sequence ? B : 1);
+    const WsLayout L = ws_layout(model.nx, model.ny, total, tv ? nmodels : B, prec);
     if (ws_bytes < L.total)
         return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
                     ws_bytes, L.total);
@@ -162,9 +165,12 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
     if (cfg.ept < kMinEpt) cfg.ept = kMinEpt;
     hipError_t e = launch_precompute(model.nx, model.ny, nmodels, model, ws, L, mixed, passes,
-                                     (passes & 1) != 0, s);
+                                     (passes & 1) != 0, s, tv);
     if (e != hipSuccess) return hip_fail(e, "precompute kernel");
-    ScanArgs a = make_scan_args(model, B, offsets, total, prec, ws, L, cfg);
+    // a time-varying model runs as one packed sequence (offsets {0, T}, written
+    // by the precompute's preparation kernel) through the per-step-constant kernels
+    if (tv) offsets = reinterpret_cast<const int64_t*>(static_cast<char*>(ws) + L.tv_offsets);
+    ScanArgs a = make_scan_args(model, B, offsets, total, prec, ws, L, cfg, tv);
     a.y = y;
     a.m = m;
     a.P = P;
@@ -229,7 +235,7 @@ pks_status validate_io(const pks_model* model, int32_t B, const int64_t* offsets
 pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
                        const void* y, const void* m, const void* P, double* ll, double* tot,
                        int32_t cumulative, pks_precision prec, void* ws, size_t ws_bytes, bool batched,
-                       hipStream_t s) {
+                       hipStream_t s, bool tv = false) {
     pks_status st = check_model(model);
     if (st) return st;
     st = check_prec(prec);
@@ -244,7 +250,7 @@ pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets
     if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
     if (!ll && !tot) return fail(PKS_E_ARG, "ll and ll_total are both NULL");
     if (cumulative && !ll) return fail(PKS_E_ARG, "cumulative output needs ll");
-    const WsLayout L = ws_layout(model->nx, model->ny, total, B, prec);
+    const WsLayout L = ws_layout(model->nx, model->ny, total, tv ? (int32_t)total : B, prec);
     if (ws_bytes < L.total)
         return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
                     ws_bytes, L.total);
@@ -265,11 +271,11 @@ pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets
         }
         return PKS_OK;
     }
-    const int nmodels = model->per_sequence ? B : 1;
-    hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 1, false, s);
+    const int nmodels = tv ? (int)total : (model->per_sequence ? B : 1);
+    hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 1, false, s, tv);
     if (e != hipSuccess) return hip_fail(e, "precompute kernel");
     e = launch_loglik(*model, B, batched ? offsets : nullptr, total, y, m, P, ll, tot, cumulative != 0,
-                      prec == PKS_MIXED_FP32, ws, L, s);
+                      prec == PKS_MIXED_FP32, ws, L, s, tv);
     if (e != hipSuccess) return hip_fail(e, "log-likelihood kernels");
     return PKS_OK;
 }
@@ -389,6 +395,74 @@ pks_status pks_loglik_batched(const pks_model* model, int32_t B, const int64_t* 
     g_last_error.clear();
     return loglik_impl(model, B, offsets, total, y, m, P, ll, ll_total, cumulative, prec, ws, ws_bytes, true,
                        (hipStream_t)stream);
+}
+
+// ---- time-varying models --------------------------------------------------
+namespace {
+constexpr int64_t kMaxStepsTv = 0x7fffffff;   // one constant block per step, indexed by int32
+
+pks_status tv_model(const pks_model_tv* t, int64_t T, pks_model* out) {
+    if (!t) return fail(PKS_E_ARG, "model is NULL");
+    if (T > kMaxStepsTv) return fail(PKS_E_UNSUPPORTED, "time-varying models support at most 2^31 - 1 steps");
+    out->nx = t->nx;
+    out->ny = t->ny;
+    out->F = t->F; out->u = t->u; out->Q = t->Q;
+    out->H = t->H; out->d = t->d; out->R = t->R;
+    out->m0 = t->m0; out->P0 = t->P0;
+    out->per_sequence = 0;
+    return PKS_OK;
+}
+}  // namespace
+
+size_t pks_workspace_bytes_tv(int32_t nx, int32_t ny, int64_t T, pks_precision prec) {
+    if (nx < 1 || nx > 64 || ny < 1 || ny > 64 || T < 0 || T > kMaxStepsTv) return 0;
+    if (prec != PKS_FP64 && prec != PKS_MIXED_FP32) return 0;
+    return ws_layout(nx, ny, T, (int32_t)std::max<int64_t>(T, 1), prec).total;
+}
+
+pks_status pks_filter_tv(const pks_model_tv* model, int64_t T, const void* y, void* m, void* P,
+                         pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, T, &mo);
+    if (!st) st = validate_io(&mo, 1, nullptr, T, y, m, P, nullptr, nullptr, prec, ws, 1, false);
+    if (st) return st;
+    return enqueue(mo, 1, nullptr, T, y, m, P, nullptr, nullptr, prec, ws, ws_bytes, 1, nullptr,
+                   (hipStream_t)stream, true);
+}
+
+pks_status pks_smooth_tv(const pks_model_tv* model, int64_t T, const void* m, const void* P, void* ms,
+                         void* Ps, pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, T, &mo);
+    if (!st) st = validate_io(&mo, 1, nullptr, T, nullptr, m, P, ms, Ps, prec, ws, 2, false);
+    if (st) return st;
+    return enqueue(mo, 1, nullptr, T, nullptr, const_cast<void*>(m), const_cast<void*>(P), ms, Ps, prec, ws,
+                   ws_bytes, 2, nullptr, (hipStream_t)stream, true);
+}
+
+pks_status pks_filter_smooth_tv(const pks_model_tv* model, int64_t T, const void* y, void* m, void* P,
+                                void* ms, void* Ps, pks_precision prec, void* ws, size_t ws_bytes,
+                                void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, T, &mo);
+    if (!st) st = validate_io(&mo, 1, nullptr, T, y, m, P, ms, Ps, prec, ws, 3, false);
+    if (st) return st;
+    return enqueue(mo, 1, nullptr, T, y, m, P, ms, Ps, prec, ws, ws_bytes, 3, nullptr, (hipStream_t)stream,
+                   true);
+}
+
+pks_status pks_loglik_tv(const pks_model_tv* model, int64_t T, const void* y, const void* m, const void* P,
+                         double* ll, double* ll_total, int32_t cumulative, pks_precision prec, void* ws,
+                         size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, T, &mo);
+    if (st) return st;
+    return loglik_impl(&mo, 1, nullptr, T, y, m, P, ll, ll_total, cumulative, prec, ws, ws_bytes, false,
+                       (hipStream_t)stream, true);
 }
 
 pks_status pks_read_numeric_status(void* ws, int32_t* first_bad_sequence, void* stream) {

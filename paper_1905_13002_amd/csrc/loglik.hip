@@ -68,6 +68,7 @@ struct LLArgs {
     const double* P0;
     const double* consts64;        // per-model constants (G, S0, e used here)
     int64_t cstride;               // doubles between models' constants (0 = shared)
+    int64_t sstride;               // doubles between steps' constants (time-varying model; else 0)
     int cG, cS, ce;                // offsets of G, S0, e in a model's constants
     const void* y;
     const void* m;                 // filtered moments of every step
@@ -142,7 +143,7 @@ __device__ __forceinline__ void ll_step_small(const LLArgs& a, int64_t k, int b,
 #pragma unroll
         for (int i = 0; i < n2; ++i) P[i] = (double)row[NX + i];
     }
-    const double* cst = a.consts64 + a.cstride * b;
+    const double* cst = a.consts64 + a.cstride * b + k * a.sstride;
     double G[NY * NX], S[NY * NY], r[NY];
 #pragma unroll
     for (int i = 0; i < NY * NX; ++i) G[i] = cst[a.cG + i];
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
         const int64_t tile = k / kLLThreads;
         const int b = SEG ? seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k, start)
                           : seq_between<false>(a.offsets, 0, 0, k, start);
-        const double* cst = a.consts64 + a.cstride * b;
+        const double* cst = a.consts64 + a.cstride * b + k * a.sstride;
         const double* G = cst + a.cG;
         if (k == start) {
             const int64_t ps = a.per_sequence ? b : 0;
@@ -588,7 +589,7 @@ int64_t ll_blocks(int64_t total) { return (total + kLLBlock - 1) / kLLBlock; }
 
 hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
                          const void* y, const void* m, const void* P, double* ll, double* tot,
-                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s) {
+                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s, bool tv) {
     char* base = static_cast<char*>(ws);
     const ConstLayout CL = const_layout(model.nx, model.ny);
     LLArgs a{};
@@ -601,7 +602,8 @@ hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offse
     a.m0 = model.m0;
     a.P0 = model.P0;
     a.consts64 = reinterpret_cast<const double*>(base + L.consts64);
-    a.cstride = model.per_sequence ? CL.words : 0;
+    a.cstride = (model.per_sequence && !tv) ? CL.words : 0;
+    a.sstride = tv ? CL.words : 0;
     a.cG = CL.G;
     a.cS = CL.S;
     a.ce = CL.e;

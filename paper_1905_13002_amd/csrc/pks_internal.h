@@ -78,6 +78,7 @@ struct WsLayout {
     size_t ll_cum;        // [total] double: prefix sums inside blocks of kLLBlock steps
     size_t ll_blk_h, ll_blk_v, ll_blk_first, ll_carry;   // [blocks] int32 / double
     size_t ll_tile_seq;   // [total / 256 + 2] int32: sequence of each 256-step tile's first step
+    size_t tv_offsets;    // int64 {0, T}: a time-varying model's one sequence, for the SEG kernels
     size_t total;
     // sizes used for capacity checks
     int64_t cap_thr, cap_waves, cap_thr1, cap_waves1;
@@ -94,6 +95,7 @@ struct ScanArgs {
     int32_t B;                   // sequences
     const int64_t* offsets;      // device [B+1]; nullptr = one sequence [0, total)
     int64_t model_stride;        // R words between models in consts (0 = shared)
+    int64_t step_stride;         // R words between steps' constants (time-varying model; else 0)
     const void* consts;          // R-typed constants of model 0
     const double* consts64;      // the same constants in double (S is always read in double)
     const void* y;               // filter input  [total][ny]
@@ -117,6 +119,16 @@ struct ScanArgs {
     int nmodels;
 };
 
+// Offset (in words) of the constants of step k of sequence b: one block per
+// model (one per sequence), or one block per step for a time-varying model.
+// The single-sequence kernels (SEG = false) serve one time-invariant model
+// only, so their constants stay at offset 0 and loop-invariant; a
+// time-varying model runs through the SEG kernels as one packed sequence.
+template <bool SEG>
+__host__ __device__ __forceinline__ int64_t const_offset(const ScanArgs& a, int b, int64_t k) {
+    return SEG ? (int64_t)b * a.model_stride + k * a.step_stride : 0;
+}
+
 // Tile configuration chosen for a launch.
 struct TileConfig {
     int ept;      // elements per thread, level 0 (4, 8, 16)
@@ -133,8 +145,13 @@ void prof_end(hipStream_t s);
 bool small_supported(int nx);
 // Model precompute (one workgroup per model); also prepares the numeric flag
 // (cleared when `reset`, or when the workspace was never prepared).
+// Time-varying models (`tv`): the arrays of `model` hold one row per step and
+// every step gets its own constants (nmodels = steps): the filter constants of
+// step k from row k, the smoother's F, Q, u from row k + 1; the prior is
+// shared, and a failing factorisation flags sequence 0 directly.
 hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model,
-                             void* ws, const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s);
+                             void* ws, const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s,
+                             bool tv = false);
 // passes: 1 = filter, 2 = smoother, 3 = both (fused where possible)
 hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
@@ -148,7 +165,8 @@ int64_t ll_blocks(int64_t total);
 // Needs the filter constants of the model in ws (launch_precompute, what 1).
 hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
                          const void* y, const void* m, const void* P, double* ll, double* tot,
-                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s);
+                         bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s,
+                         bool tv = false);
 
 // large-state path (scan_large.hip), 5 <= nx <= 64
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);

@@ -10,9 +10,11 @@ TileConfig tuned_config(int nx, int ny, int32_t B, int64_t total, pks_precision 
                         const char* path = nullptr);
 
 // Enqueue passes (1 = filter, 2 = smoother, 3 = both) of a validated request.
+// tv: `model` holds one row per step (time-varying; single sequence).
 pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
                    const void* y, void* m, void* P, void* ms, void* Ps, pks_precision prec,
-                   void* ws, size_t ws_bytes, int passes, const TileConfig* forced, hipStream_t s);
+                   void* ws, size_t ws_bytes, int passes, const TileConfig* forced, hipStream_t s,
+                   bool tv = false);
 
 pks_status validate_io(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
                        const void* y, const void* m, const void* P, const void* ms, const void* Ps,

@@ -37,7 +37,41 @@ struct PrecomputeArgs {
     int what;   // 1: filter constants, 2: smoother constants (F, Q, u), 3: both
     int reset;  // clear the numeric flag first
     int use_lds;  // temporaries and outputs in LDS (small models), copied out at the end
+    int tv;       // time-varying model: one row of F, u, Q, H, d, R per step, model index = step
 };
+
+// Rows of the model arrays that model (or step) b reads: its filter constants
+// (F, u, Q, H, d, R), its prior (m0, P0) and its smoother constants (F, Q, u).
+// A time-varying model's step b predicts with the transition into step b and
+// its smoothing element uses the transition out of it (row b + 1; the last
+// step has none and never uses it); the prior is shared.
+struct Rows {
+    size_t f, p, s;
+};
+__device__ __forceinline__ Rows model_rows(const PrecomputeArgs& a, int b, int nmodels) {
+    Rows r;
+    const size_t ps = a.per_sequence ? 1 : 0;
+    if (a.tv) {
+        r.f = (size_t)b;
+        r.p = 0;
+        r.s = (size_t)(b + 1 < nmodels ? b + 1 : b);
+    } else {
+        r.f = r.p = r.s = ps * (size_t)b;
+    }
+    return r;
+}
+
+// Before a time-varying precompute: clears the numeric flag (same rule as the
+// precompute's own preparation; its workgroups then set the flag directly)
+// and writes the offsets {0, T} of the model's one sequence.
+__global__ void k_status_prepare(int* status, int reset, int64_t* offsets, int64_t T) {
+    if (reset || status[1] != kStatusMagic) {
+        status[0] = kStatusOk;
+        status[1] = kStatusMagic;
+    }
+    offsets[0] = 0;
+    offsets[1] = T;
+}
 
 // out[m x n] = op(A) op(B); A is [m x k] (or [k x m] if ta), B is [k x n] (or [n x k] if tb)
 __device__ void bmm(double* out, const double* A, bool ta, const double* B, bool tb, int m, int k, int n,
@@ -127,7 +161,7 @@ __device__ void btranspose(double* dst, const double* src, int rows, int cols) {
 __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     extern __shared__ double lds[];
     const int b = blockIdx.x;
-    if (b == 0 && threadIdx.x == 0) {
+    if (b == 0 && threadIdx.x == 0 && !a.tv) {
         // status[0] = first failing sequence (kStatusOk = none), status[1] = magic;
         // a workspace that was never prepared (wrong magic) starts clean.
         if (a.reset || a.status[1] != kStatusMagic) {
@@ -136,15 +170,15 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
         }
     }
     const int nx = a.nx, ny = a.ny, n2 = nx * nx, nm = nx * ny, m2 = ny * ny;
-    const int ps = a.per_sequence ? 1 : 0;
-    const double* F = a.F + (size_t)ps * b * n2;
-    const double* Q = a.Q + (size_t)ps * b * n2;
-    const double* H = a.H + (size_t)ps * b * nm;
-    const double* R = a.R + (size_t)ps * b * m2;
-    const double* m0 = a.m0 + (size_t)ps * b * nx;
-    const double* P0 = a.P0 + (size_t)ps * b * n2;
-    const double* u = a.u ? a.u + (size_t)ps * b * nx : nullptr;
-    const double* d = a.d ? a.d + (size_t)ps * b * ny : nullptr;
+    const Rows rw = model_rows(a, b, gridDim.x);
+    const double* F = a.F + rw.f * n2;
+    const double* Q = a.Q + rw.f * n2;
+    const double* H = a.H + rw.f * nm;
+    const double* R = a.R + rw.f * m2;
+    const double* m0 = a.m0 + rw.p * nx;
+    const double* P0 = a.P0 + rw.p * n2;
+    const double* u = a.u ? a.u + rw.f * nx : nullptr;
+    const double* d = a.d ? a.d + rw.f * ny : nullptr;
     const ConstLayout CL = const_layout(nx, ny);
     double* gout = a.consts64 + (size_t)b * a.cw;
     double* out = a.use_lds ? lds : gout;
@@ -199,7 +233,8 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     bmm(out + CL.c, Kt, true, e, false, nx, ny, 1, -1.0, uz);  // u - K e
     bmm(out + CL.w, Z, true, e, false, nx, ny, 1, -1.0);       // -W e
 
-    // ---- k = 1 element ----
+    // ---- k = 1 element (a time-varying model needs it at its first step only) ----
+    if (!a.tv || b == 0) {
     bmm(m1, F, false, m0, false, nx, nx, 1, 1.0, uz);        // F m0 + u
     bmm(V, F, false, P0, false, nx, nx, nx);                 // F P0
     bmm(P1, V, false, F, true, nx, nx, nx, 1.0, Q);          // F P0 F^T + Q
@@ -218,19 +253,24 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     bmm(out + CL.C1, U, false, K1t, false, nx, ny, nx, -1.0, P1);  // P1 - K1 S1 K1^T
     bsym(out + CL.C1, nx);
     }
+    }
 
     // ---- smoother constants ----
     if (a.what & 2) {
-        bcopy(out + CL.F, F, n2);
-        bcopy(out + CL.Q, Q, n2);
-        bcopy(out + CL.u, uz, nx);
+        bcopy(out + CL.F, a.F + rw.s * n2, n2);
+        bcopy(out + CL.Q, a.Q + rw.s * n2, n2);
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) out[CL.u + i] = a.u ? a.u[rw.s * nx + i] : 0.0;
+        __syncthreads();
     }
 
     if (!ok) {
         for (int i = threadIdx.x; i < CL.words; i += blockDim.x) out[i] = __builtin_nan("");
         __syncthreads();
     }
-    if ((a.what & 1) && threadIdx.x == 0) a.model_fail[b] = ok ? 0 : 1;
+    if ((a.what & 1) && threadIdx.x == 0) {
+        a.model_fail[b] = ok ? 0 : 1;
+        if (a.tv && !ok) atomicMin(a.status, 0);
+    }
     if (a.use_lds) {
         const int lo = (a.what & 1) ? 0 : CL.F;
         const int hi = (a.what & 2) ? CL.words : CL.F;
@@ -341,7 +381,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     // factors S = H Q H^T + R, so it alone decides whether the model failed.
     const int part = blockIdx.x & 1;
     const int b = (blockIdx.x >> 1) * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !a.tv) {
         if (a.reset || a.status[1] != kStatusMagic) {
             a.status[0] = kStatusOk;
             a.status[1] = kStatusMagic;
@@ -349,25 +389,25 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     }
     if (b >= nmodels) return;
     constexpr int n2 = NX * NX, nm = NX * NY, m2 = NY * NY;
-    const int ps = a.per_sequence ? 1 : 0;
+    const Rows rw = model_rows(a, b, nmodels);
     double F[n2], Q[n2], H[nm], R[m2], m0[NX], P0[n2], u[NX], d[NY];
 #pragma unroll
     for (int i = 0; i < n2; ++i) {
-        F[i] = a.F[(size_t)ps * b * n2 + i];
-        Q[i] = a.Q[(size_t)ps * b * n2 + i];
-        P0[i] = a.P0[(size_t)ps * b * n2 + i];
+        F[i] = a.F[rw.f * n2 + i];
+        Q[i] = a.Q[rw.f * n2 + i];
+        P0[i] = a.P0[rw.p * n2 + i];
     }
 #pragma unroll
-    for (int i = 0; i < nm; ++i) H[i] = a.H[(size_t)ps * b * nm + i];
+    for (int i = 0; i < nm; ++i) H[i] = a.H[rw.f * nm + i];
 #pragma unroll
-    for (int i = 0; i < m2; ++i) R[i] = a.R[(size_t)ps * b * m2 + i];
+    for (int i = 0; i < m2; ++i) R[i] = a.R[rw.f * m2 + i];
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-        m0[i] = a.m0[(size_t)ps * b * NX + i];
-        u[i] = a.u ? a.u[(size_t)ps * b * NX + i] : 0.0;
+        m0[i] = a.m0[rw.p * NX + i];
+        u[i] = a.u ? a.u[rw.f * NX + i] : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < NY; ++i) d[i] = a.d ? a.d[(size_t)ps * b * NY + i] : 0.0;
+    for (int i = 0; i < NY; ++i) d[i] = a.d ? a.d[rw.f * NY + i] : 0.0;
 
     const ConstLayout CL = const_layout(NX, NY);
     DualOut out{a.consts64 + (size_t)b * a.cw, a.mixed ? a.consts32 + (size_t)b * a.cw : nullptr};
@@ -425,7 +465,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
 #pragma unroll
         for (int i = 0; i < NX; ++i) out.put(CL.w + i, -v[i]);
     }
-    if ((a.what & 1) && part == 1) {
+    if ((a.what & 1) && part == 1 && (!a.tv || b == 0)) {
         // k = 1: one prediction from the prior and one update
         double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm], X[n2], v[NX];
         SP::template mm<NX, NX, 1, false, false>(m1, F, m0);
@@ -473,14 +513,15 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         for (int i = 0; i < n2; ++i) out.put(CL.C1 + i, X[i]);
     }
     if ((a.what & 1) && part == 1) a.model_fail[b] = ok ? 0 : 1;
+    if (a.tv && !ok) atomicMin(a.status, 0);          // either half of a failing step
     if ((a.what & 2) && part == 1) {
 #pragma unroll
         for (int i = 0; i < n2; ++i) {
-            out.put(CL.F + i, F[i]);
-            out.put(CL.Q + i, Q[i]);
+            out.put(CL.F + i, a.F[rw.s * n2 + i]);
+            out.put(CL.Q + i, a.Q[rw.s * n2 + i]);
         }
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out.put(CL.u + i, u[i]);
+        for (int i = 0; i < NX; ++i) out.put(CL.u + i, a.u ? a.u[rw.s * NX + i] : 0.0);
     }
     if (!ok) {
         // NaN in the fields this half owns (constants A .. w and G, S; or the
@@ -518,7 +559,7 @@ bool launch_small_pre(int nx, int ny, PrecomputeArgs a, int nmodels, hipStream_t
 }  // namespace
 
 hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model, void* ws,
-                             const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s) {
+                             const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s, bool tv) {
     PrecomputeArgs a;
     a.nx = nx;
     a.ny = ny;
@@ -537,6 +578,10 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
     a.mixed = mixed ? 1 : 0;
     a.what = what;
     a.reset = reset ? 1 : 0;
+    a.tv = tv ? 1 : 0;
+    if (tv)
+        hipLaunchKernelGGL(k_status_prepare, dim3(1), dim3(1), 0, s, a.status, a.reset,
+                           reinterpret_cast<int64_t*>(base + L.tv_offsets), (int64_t)nmodels);
     // Small models keep every temporary in LDS and run as one wave (barriers
     // are then nearly free); large ones use 256 threads and workspace scratch.
     const size_t lds_bytes = sizeof(double) * (size_t)(a.cw + a.sw);

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_reduce(LargeArgs la) 
     SeqL s = seq_at<SEG>(a, k0);
     for (int64_t k = k0; k < k1; ++k) {
         seq_fwd<SEG>(a, s, k);
-        const int64_t moff = SEG ? s.b * a.model_stride : 0;
+        const int64_t moff = const_offset<SEG>(a, s.b, k);
         const R* cst = static_cast<const R*>(a.consts) + moff;
         const bool first = k == s.start;
         build_fvec<R>(c, cst, CL, y + k * a.ny, first);
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void k_large_filter_down(LargeArgs la) {
     SeqL s = seq_at<SEG>(a, k0);
     for (int64_t k = k0; k < k1; ++k) {
         seq_fwd<SEG>(a, s, k);
-        const int64_t moff = SEG ? s.b * a.model_stride : 0;
+        const int64_t moff = const_offset<SEG>(a, s.b, k);
         const R* cst = static_cast<const R*>(a.consts) + moff;
         const bool first = k == s.start;
         build_fvec<R>(c, cst, CL, y + k * a.ny, first);
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_reduce(LargeArgs la
     SeqL s = seq_at<SEG>(a, k0);
     for (int64_t k = k0; k < k1; ++k) {
         seq_fwd<SEG>(a, s, k);
-        const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+        const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
         load_moments<R>(c, a, k, mom);
         const bool last = k == s.end - 1;
         if (last) {
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
     SeqL s = seq_at<SEG>(a, k1 - 1);
     for (int64_t k = k1 - 1; k >= k0; --k) {
         seq_bwd<SEG>(a, s, k);
-        const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+        const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
         // the filtered moments of step k are read where the filter wrote them
         const R* mk = static_cast<const R*>(a.m) + k * n;
         const R* Pk = static_cast<const R*>(a.P) + k * n2;

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
             const int64_t k = k0 + e;
             if (k < a.total) {
                 seq_forward<SEG>(a, s, k);
-                const int64_t moff = SEG ? s.b * a.model_stride : 0;
+                const int64_t moff = const_offset<SEG>(a, s.b, k);
                 const R* cst = static_cast<const R*>(a.consts) + moff;
                 const bool first = k == s.start;
                 FElem<N, R> x;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         const int64_t k = k0 + e;
         if (k < a.total) {
             seq_forward<SEG>(a, s, k);
-            const int64_t moff = SEG ? s.b * a.model_stride : 0;
+            const int64_t moff = const_offset<SEG>(a, s.b, k);
             const R* cst = static_cast<const R*>(a.consts) + moff;
             const bool first = k == s.start;
             FElem<N, R> x;
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
         const int64_t k = k0 + e;
         if (k < a.total) {
             seq_forward<SEG>(a, s, k);
-            const int64_t moff = SEG ? s.b * a.model_stride : 0;
+            const int64_t moff = const_offset<SEG>(a, s.b, k);
             const R* cst = static_cast<const R*>(a.consts) + moff;
             const bool first = k == s.start;
             {
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
             const Moments<N, R> x = xn;
             if (k > k0) load_moments_step(m, P, k - 1, xn);
             seq_backward<SEG>(a, s, k);
-            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
             SElem<N, R> el;
             make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
             if (k == klast) acc = el;
@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
         }
         if (k <= klast) {
             seq_backward<SEG>(a, s, k);
-            const R* cst = static_cast<const R*>(a.consts) + (SEG ? s.b * a.model_stride : 0);
+            const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
             SElem<N, R> el;
             make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
             scarry<N, R, SEG>(el, Y);

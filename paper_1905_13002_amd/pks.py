@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "PKS_OK", 1: "PKS_E_ARG", 2: "PKS_E_UNSUPPORTED", 3: "PKS_E_W
 EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smooth",
             "pks_filter_batched", "pks_smooth_batched", "pks_plan_create", "pks_plan_launch",
             "pks_plan_destroy", "pks_autotune", "pks_read_numeric_status", "pks_last_error",
-            "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched"]
+            "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched",
+            "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv"]
 
 
 class PksError(RuntimeError):
@@ -43,6 +44,13 @@ class pks_model(ctypes.Structure):
                 ("per_sequence", ctypes.c_int32)]
 
 
+class pks_model_tv(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("F", ctypes.c_void_p), ("u", ctypes.c_void_p), ("Q", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("d", ctypes.c_void_p), ("R", ctypes.c_void_p),
+                ("m0", ctypes.c_void_p), ("P0", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libpks.so not found at %s: build it with "
@@ -50,7 +58,13 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     mp = ctypes.POINTER(pks_model)
+    mt = ctypes.POINTER(pks_model_tv)
     sig = {
+        "pks_workspace_bytes_tv": (sz, [i32, i32, i64, ctypes.c_int]),
+        "pks_filter_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_smooth_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_filter_smooth_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_loglik_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz, vp]),
         "pks_workspace_bytes": (sz, [i32, i32, i64, i32, ctypes.c_int]),
         "pks_filter": (ctypes.c_int, [mp, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_smooth": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
@@ -124,6 +138,7 @@ class DeviceModel:
     u: Optional[torch.Tensor] = None
     d: Optional[torch.Tensor] = None
     per_sequence: bool = False
+    time_varying: bool = False      # F, Q, H, R, u, d hold one row per step
 
     @property
     def nx(self):
@@ -133,32 +148,46 @@ class DeviceModel:
     def ny(self):
         return self.H.shape[-2]
 
-    def struct(self) -> pks_model:
-        s = pks_model()
+    def struct(self):
+        s = pks_model_tv() if self.time_varying else pks_model()
         s.nx, s.ny = self.nx, self.ny
         for f in ("F", "Q", "H", "R", "m0", "P0", "u", "d"):
             t = getattr(self, f)
             setattr(s, f, None if t is None else t.data_ptr())
-        s.per_sequence = 1 if self.per_sequence else 0
+        if not self.time_varying:
+            s.per_sequence = 1 if self.per_sequence else 0
         return s
 
 
-def to_device(model, device="cuda", per_sequence: bool = False) -> DeviceModel:
+def to_device(model, device="cuda", per_sequence: bool = False, time_varying: bool = False) -> DeviceModel:
     """Copy a workloads.Model (numpy) to the device as float64 tensors."""
     cv = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
     return DeviceModel(cv(model.F), cv(model.Q), cv(model.H), cv(model.R), cv(model.m0), cv(model.P0),
-                       cv(model.u), cv(model.d), per_sequence)
+                       cv(model.u), cv(model.d), per_sequence, time_varying)
 
 
-def workspace_bytes(nx: int, ny: int, total: int, B: int = 1, precision="fp64") -> int:
-    n = lib.pks_workspace_bytes(nx, ny, int(total), int(B), _prec(precision))
+def workspace_bytes(nx: int, ny: int, total: int, B: int = 1, precision="fp64", time_varying=False) -> int:
+    if time_varying:
+        n = lib.pks_workspace_bytes_tv(nx, ny, int(total), _prec(precision))
+    else:
+        n = lib.pks_workspace_bytes(nx, ny, int(total), int(B), _prec(precision))
     if n == 0:
         raise PksError(PKS_E_ARG, "invalid problem shape")
     return int(n)
 
 
-def workspace(nx, ny, total, B=1, precision="fp64", device="cuda") -> torch.Tensor:
-    return torch.empty(workspace_bytes(nx, ny, total, B, precision), dtype=torch.uint8, device=device)
+def workspace(nx, ny, total, B=1, precision="fp64", device="cuda", time_varying=False) -> torch.Tensor:
+    return torch.empty(workspace_bytes(nx, ny, total, B, precision, time_varying), dtype=torch.uint8,
+                       device=device)
+
+
+def _single_only(model: "DeviceModel"):
+    if model.time_varying:
+        raise ValueError("time-varying models run as single sequences (filter, smooth, filter_smooth, loglik)")
+
+
+def _ws_for(model: "DeviceModel", total, B, prec, device):
+    return workspace(model.nx, model.ny, total, B, prec, device, model.time_varying)
 
 
 def _out(shape, prec, device):
@@ -171,10 +200,10 @@ def filter(model: DeviceModel, y: torch.Tensor, precision="fp64", ws=None, out=N
     T = y.shape[0]
     m, P = out if out is not None else (_out((T, model.nx), prec, y.device),
                                          _out((T, model.nx, model.nx), prec, y.device))
-    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, y.device)
+    ws = ws if ws is not None else _ws_for(model, T, 1, prec, y.device)
     ms = model.struct()
-    _check(lib.pks_filter(ctypes.byref(ms), T, _ptr(y), _ptr(m), _ptr(P), prec, _ptr(ws), ws.numel(),
-                          _stream(stream)))
+    fn = lib.pks_filter_tv if model.time_varying else lib.pks_filter
+    _check(fn(ctypes.byref(ms), T, _ptr(y), _ptr(m), _ptr(P), prec, _ptr(ws), ws.numel(), _stream(stream)))
     return m, P
 
 
@@ -184,10 +213,11 @@ def smooth(model: DeviceModel, m: torch.Tensor, P: torch.Tensor, precision="fp64
     prec = _prec(precision)
     T = m.shape[0]
     ms_, Ps_ = out if out is not None else (torch.empty_like(m), torch.empty_like(P))
-    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, m.device)
+    ws = ws if ws is not None else _ws_for(model, T, 1, prec, m.device)
     st = model.struct()
-    _check(lib.pks_smooth(ctypes.byref(st), T, _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec, _ptr(ws),
-                          ws.numel(), _stream(stream)))
+    fn = lib.pks_smooth_tv if model.time_varying else lib.pks_smooth
+    _check(fn(ctypes.byref(st), T, _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec, _ptr(ws), ws.numel(),
+              _stream(stream)))
     return ms_, Ps_
 
 
@@ -200,15 +230,17 @@ def filter_smooth(model: DeviceModel, y: torch.Tensor, precision="fp64", ws=None
         out = (_out((T, nx), prec, y.device), _out((T, nx, nx), prec, y.device),
                _out((T, nx), prec, y.device), _out((T, nx, nx), prec, y.device))
     m, P, ms_, Ps_ = out
-    ws = ws if ws is not None else workspace(nx, model.ny, T, 1, prec, y.device)
+    ws = ws if ws is not None else _ws_for(model, T, 1, prec, y.device)
     st = model.struct()
-    _check(lib.pks_filter_smooth(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec,
-                                 _ptr(ws), ws.numel(), _stream(stream)))
+    fn = lib.pks_filter_smooth_tv if model.time_varying else lib.pks_filter_smooth
+    _check(fn(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec, _ptr(ws), ws.numel(),
+              _stream(stream)))
     return m, P, ms_, Ps_
 
 
 def filter_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, precision="fp64", ws=None,
                    out=None, stream=None):
+    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = y.shape[0]
@@ -223,6 +255,7 @@ def filter_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, p
 
 def smooth_batched(model: DeviceModel, offsets: torch.Tensor, m: torch.Tensor, P: torch.Tensor,
                    precision="fp64", ws=None, out=None, stream=None):
+    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = m.shape[0]
@@ -244,16 +277,18 @@ def loglik(model: DeviceModel, y: torch.Tensor, m: torch.Tensor, P: torch.Tensor
     T = y.shape[0]
     ll = torch.empty(T, dtype=torch.float64, device=y.device) if (steps or cumulative) else None
     tot = torch.empty(1, dtype=torch.float64, device=y.device)
-    ws = ws if ws is not None else workspace(model.nx, model.ny, T, 1, prec, y.device)
+    ws = ws if ws is not None else _ws_for(model, T, 1, prec, y.device)
     st = model.struct()
-    _check(lib.pks_loglik(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ll), _ptr(tot),
-                          1 if cumulative else 0, prec, _ptr(ws), ws.numel(), _stream(stream)))
+    fn = lib.pks_loglik_tv if model.time_varying else lib.pks_loglik
+    _check(fn(ctypes.byref(st), T, _ptr(y), _ptr(m), _ptr(P), _ptr(ll), _ptr(tot), 1 if cumulative else 0, prec,
+              _ptr(ws), ws.numel(), _stream(stream)))
     return ll, tot
 
 
 def loglik_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, m: torch.Tensor,
                    P: torch.Tensor, precision="fp64", cumulative=False, steps=True, ws=None, stream=None):
     """Batched marginal likelihood: returns (ll [total] or None, totals [B])."""
+    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = y.shape[0]
@@ -272,6 +307,7 @@ class Plan:
 
     def __init__(self, model: DeviceModel, y: torch.Tensor, offsets: Optional[torch.Tensor] = None,
                  precision="fp64", tune_cache: Optional[str] = None, stream=None):
+        _single_only(model)
         prec = _prec(precision)
         self.prec = prec
         self.model = model

@@ -15,6 +15,13 @@ Workloads (ids 1..5):
   4  4096 constant-velocity sequences of uneven length (256..16384) with
      per-sequence q in [0.1, 10] and r in [0.01, 1]
   5  64 sequences of a shared nx = 64, ny = 32 random stable model, T = 8192
+  6  time-varying model: 2-D constant-velocity tracking sampled at irregular
+     times (dt_k ~ U(0.05, 0.15), so F_{k-1} and Q_{k-1} change every step),
+     q = 1, sigma^2 = 0.25, T = 2**20
+
+A time-varying model is a Model whose F, Q, H, R (and u, d) carry a leading
+[T] axis: row k-1 holds the transition into step k (F_{k-1}, Q_{k-1}, u_{k-1})
+and the measurement model of step k (H_k, R_k, d_k).
 """
 from __future__ import annotations
 
@@ -69,6 +76,7 @@ class Workload:
     per_sequence: bool = False
     x: Optional[np.ndarray] = None      # simulated states (kept only when asked)
     meta: dict = field(default_factory=dict)
+    time_varying: bool = False          # model rows per step (single sequence)
 
     @property
     def B(self) -> int:
@@ -163,6 +171,49 @@ def random_small_model(nx: int, ny: int, rng: np.random.Generator,
     return Model(F, Q, H, R, m0, P0, u, d)
 
 
+def cv_model_tv(dts: np.ndarray, q: float = 1.0, r: float = 0.25, m0=None, P0=None) -> Model:
+    """Constant-velocity model sampled at irregular times: step k moves by
+    dts[k-1] (F_{k-1}, Q_{k-1} of the white-acceleration model for that
+    interval), H and R = r I unchanged.  Arrays carry a leading [T] axis."""
+    dts = np.asarray(dts, dtype=np.float64)
+    T = dts.shape[0]
+    I2 = np.eye(2)
+    F = np.zeros((T, 4, 4))
+    F[:, :2, :2] = I2
+    F[:, 2:, 2:] = I2
+    F[:, :2, 2:] = dts[:, None, None] * I2
+    Q = np.zeros((T, 4, 4))
+    Q[:, :2, :2] = (q * dts ** 3 / 3)[:, None, None] * I2
+    Q[:, :2, 2:] = (q * dts ** 2 / 2)[:, None, None] * I2
+    Q[:, 2:, :2] = (q * dts ** 2 / 2)[:, None, None] * I2
+    Q[:, 2:, 2:] = (q * dts)[:, None, None] * I2
+    H = np.broadcast_to(np.hstack([I2, np.zeros((2, 2))]), (T, 2, 4)).copy()
+    R = np.broadcast_to(r * I2, (T, 2, 2)).copy()
+    m0 = np.zeros(4) if m0 is None else np.asarray(m0, dtype=np.float64)
+    P0 = np.eye(4) if P0 is None else np.asarray(P0, dtype=np.float64)
+    return Model(F, Q, H, R, m0, P0)
+
+
+def random_tv_model(nx: int, ny: int, T: int, rng: np.random.Generator, radius: float = 0.97,
+                    with_offsets: bool = True) -> Model:
+    """A generic time-varying model: per step a random F_{k-1} (spectral radius
+    <= radius), SPD Q_{k-1}, R_k, a random H_k and (optionally) u_{k-1}, d_k."""
+    F = rng.standard_normal((T, nx, nx)) / np.sqrt(nx)
+    rad = np.max(np.abs(np.linalg.eigvals(F)), axis=1)
+    F = radius * F / np.maximum(1.0, rad)[:, None, None]
+    Bq = rng.standard_normal((T, nx, nx))
+    Q = Bq @ np.swapaxes(Bq, 1, 2) / nx + 0.05 * np.eye(nx)
+    H = rng.standard_normal((T, ny, nx)) / np.sqrt(nx)
+    Br = rng.standard_normal((T, ny, ny))
+    R = Br @ np.swapaxes(Br, 1, 2) / ny + 0.2 * np.eye(ny)
+    m0 = rng.standard_normal(nx) if with_offsets else np.zeros(nx)
+    B0 = rng.standard_normal((nx, nx))
+    P0 = B0 @ B0.T / nx + 0.3 * np.eye(nx)
+    u = 0.3 * rng.standard_normal((T, nx)) if with_offsets else None
+    d = 0.3 * rng.standard_normal((T, ny)) if with_offsets else None
+    return Model(F, Q, H, R, m0, P0, u, d)
+
+
 # ---------------------------------------------------------------------------
 # simulation
 # ---------------------------------------------------------------------------
@@ -189,6 +240,46 @@ def simulate(model: Model, T: int, rng: np.random.Generator, keep_states: bool =
         xs[k] = x
     y = xs @ model.H.T + d + rn
     return y, (xs if keep_states else None)
+
+
+def simulate_tv(model: Model, rng: np.random.Generator, keep_states: bool = False):
+    """Simulate a time-varying model over its T rows: returns (y [T,ny], x or None)."""
+    T, nx, ny = model.F.shape[0], model.nx, model.ny
+    x = model.m0 + _chol_psd(model.P0) @ rng.standard_normal(nx)
+    w, V = np.linalg.eigh(0.5 * (model.Q + np.swapaxes(model.Q, 1, 2)))
+    LQ = V * np.sqrt(np.clip(w, 0.0, None))[:, None, :]
+    w, V = np.linalg.eigh(0.5 * (model.R + np.swapaxes(model.R, 1, 2)))
+    LR = V * np.sqrt(np.clip(w, 0.0, None))[:, None, :]
+    qn = np.einsum("kij,kj->ki", LQ, rng.standard_normal((T, nx)))
+    rn = np.einsum("kij,kj->ki", LR, rng.standard_normal((T, ny)))
+    u = np.zeros((T, nx)) if model.u is None else model.u
+    d = np.zeros((T, ny)) if model.d is None else model.d
+    xs = np.empty((T, nx))
+    for k in range(T):
+        x = model.F[k] @ x + u[k] + qn[k]
+        xs[k] = x
+    y = np.einsum("kij,kj->ki", model.H, xs) + d + rn
+    return y, (xs if keep_states else None)
+
+
+def simulate_cv_tv(dts: np.ndarray, q: float, r: float, rng: np.random.Generator, keep_states: bool = False):
+    """Constant-velocity simulation at irregular intervals dts, vectorised: per
+    axis the interval's noise (q dt^3/3, q dt^2/2; q dt^2/2, q dt) is drawn
+    through its closed-form Cholesky factor."""
+    dts = np.asarray(dts, dtype=np.float64)
+    T = dts.shape[0]
+    x0 = rng.standard_normal(4)                              # m0 = 0, P0 = I
+    z = rng.standard_normal((T, 2, 2))                       # [k, axis, (pos, vel)]
+    l11 = np.sqrt(q * dts ** 3 / 3)
+    l21 = np.sqrt(3 * q * dts) / 2
+    l22 = np.sqrt(q * dts / 4)
+    qp = l11[:, None] * z[:, :, 0]
+    qv = l21[:, None] * z[:, :, 0] + l22[:, None] * z[:, :, 1]
+    v = x0[2:] + np.cumsum(qv, axis=0)
+    v_prev = np.vstack([x0[2:][None, :], v[:-1]])
+    p = x0[:2] + np.cumsum(dts[:, None] * v_prev + qp, axis=0)
+    y = p + np.sqrt(r) * rng.standard_normal((T, 2))
+    return y, (np.hstack([p, v]) if keep_states else None)
 
 
 def simulate_cv(q: float, r: float, T: int, rng: np.random.Generator, dt: float = 0.1,
@@ -219,6 +310,7 @@ WORKLOAD_NAMES = {
     3: "random_nx16_ny8_T65536",
     4: "cv_batched_B4096_uneven",
     5: "random_nx64_ny32_B64_T8192",
+    6: "cv_irregular_T1048576",
 }
 
 
@@ -290,6 +382,15 @@ def workload(wid: int, keep_states: bool = False, T: Optional[int] = None,
         if keep_states:
             xs[:] = Xs.reshape(B * T, nx)
         return Workload(WORKLOAD_NAMES[5], model, ys, offsets, False, xs)
+    if wid == 6:
+        T = T if T is not None else 1 << 20
+        rng = rng_for(6, 0)
+        dts = rng.uniform(0.05, 0.15, size=T)
+        model = cv_model_tv(dts, 1.0, 0.25)
+        y, x = simulate_cv_tv(dts, 1.0, 0.25, rng_for(6, 1), keep_states)
+        w = _single(WORKLOAD_NAMES[6], model, y, x, q=1.0, r=0.25)
+        w.time_varying = True
+        return w
     raise ValueError("unknown workload %r" % wid)
 
 

@@ -83,3 +83,60 @@ def joint_loglik(F, Q, H, R, m0, P0, y, u=None, d=None):
         assert sign > 0
         out[k] = -0.5 * (n * np.log(2.0 * np.pi) + logdet + r @ np.linalg.solve(SigY[:n, :n], r))
     return out
+
+
+def joint_moments_tv(F, Q, H, R, m0, P0, u=None, d=None):
+    """Joint moments of X = (x_1..x_T), Y = (y_1..y_T) for per-step matrices:
+    F[k-1], Q[k-1], u[k-1] carry x_{k-1} to x_k, H[k-1], R[k-1], d[k-1]
+    measure x_k.  x_k = Phi_k x_0 + sum_{i<k} Psi_{k,i} (u_i + q_i) with
+    Phi_k = F[k-1] ... F[0] and Psi_{k,i} = F[k-1] ... F[i+1]."""
+    T, nx = F.shape[0], F.shape[-1]
+    ny = H.shape[-2]
+    u = np.zeros((T, nx)) if u is None else np.asarray(u, float)
+    d = np.zeros((T, ny)) if d is None else np.asarray(d, float)
+    Phi = np.zeros((T * nx, nx))
+    G = np.zeros((T * nx, T * nx))
+    for k in range(T):                      # block k holds x_{k+1}
+        Phi[k * nx:(k + 1) * nx] = F[k] @ (Phi[(k - 1) * nx:k * nx] if k else np.eye(nx))
+        for i in range(k + 1):              # q_i, u_i enter x_{i+1} and later
+            G[k * nx:(k + 1) * nx, i * nx:(i + 1) * nx] = (
+                np.eye(nx) if i == k else F[k] @ G[(k - 1) * nx:k * nx, i * nx:(i + 1) * nx])
+    muX = Phi @ m0 + G @ u.reshape(-1)
+    SigW = np.zeros((T * nx, T * nx))
+    Hb = np.zeros((T * ny, T * nx))
+    Rb = np.zeros((T * ny, T * ny))
+    for k in range(T):
+        SigW[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] = Q[k]
+        Hb[k * ny:(k + 1) * ny, k * nx:(k + 1) * nx] = H[k]
+        Rb[k * ny:(k + 1) * ny, k * ny:(k + 1) * ny] = R[k]
+    SigX = Phi @ P0 @ Phi.T + G @ SigW @ G.T
+    muY = Hb @ muX + d.reshape(-1)
+    SigY = Hb @ SigX @ Hb.T + Rb
+    SigXY = SigX @ Hb.T
+    return muX, SigX, muY, SigY, SigXY
+
+
+def posterior_tv(F, Q, H, R, m0, P0, y, u=None, d=None):
+    """posterior() for per-step matrices; also returns log p(y_1:k) for every k."""
+    y = np.asarray(y, float)
+    T, ny = y.shape
+    nx = F.shape[-1]
+    muX, SigX, muY, SigY, SigXY = joint_moments_tv(F, Q, H, R, m0, P0, u, d)
+    Yv = y.reshape(-1)
+    mean = muX + SigXY @ np.linalg.solve(SigY, Yv - muY)
+    cov = SigX - SigXY @ np.linalg.solve(SigY, SigXY.T)
+    ms = mean.reshape(T, nx)
+    Ps = np.stack([cov[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] for k in range(T)])
+    m = np.empty((T, nx))
+    P = np.empty((T, nx, nx))
+    ll = np.empty(T)
+    for k in range(T):
+        n = (k + 1) * ny
+        sl = slice(k * nx, (k + 1) * nx)
+        SY = SigY[:n, :n]
+        SXY = SigXY[sl, :n]
+        r = Yv[:n] - muY[:n]
+        m[k] = muX[sl] + SXY @ np.linalg.solve(SY, r)
+        P[k] = SigX[sl, sl] - SXY @ np.linalg.solve(SY, SXY.T)
+        ll[k] = -0.5 * (n * np.log(2 * np.pi) + np.linalg.slogdet(SY)[1] + r @ np.linalg.solve(SY, r))
+    return m, P, ms, Ps, ll

@@ -165,3 +165,25 @@ def test_workspace_covers_loglik_buffers():
     a = lib.pks_workspace_bytes(4, 2, 1 << 20, 1, 0)
     b = lib.pks_workspace_bytes(4, 2, 2 << 20, 1, 0)
     assert b - a >= 16 * (1 << 20)
+
+
+def test_time_varying_argument_errors():
+    assert lib.pks_workspace_bytes_tv(4, 2, 100, 0) > lib.pks_workspace_bytes(4, 2, 100, 1, 0)
+    for bad in ((0, 2, 10, 0), (4, 65, 10, 0), (4, 2, -1, 0), (4, 2, 1 << 31, 0), (4, 2, 10, 5)):
+        assert lib.pks_workspace_bytes_tv(*bad) == 0
+    t = pks.pks_model_tv()
+    t.nx, t.ny = 4, 2
+    for i, f in enumerate(("F", "Q", "H", "R", "m0", "P0")):
+        setattr(t, f, FAKE + 0x100000 * (i + 1))
+    wsb = lib.pks_workspace_bytes_tv(4, 2, 16, 0)
+    y, m, P, ws = FAKE + 0x1000000, FAKE + 0x2000000, FAKE + 0x3000000, FAKE + 0x8000000
+    assert lib.pks_filter_tv(None, 16, y, m, P, 0, ws, wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_filter_tv(ctypes.byref(t), 16, y, m, P, 0, ws, wsb - 1, None) == pks.PKS_E_WORKSPACE
+    assert lib.pks_filter_tv(ctypes.byref(t), 1 << 31, y, m, P, 0, ws, 1 << 40, None) == pks.PKS_E_UNSUPPORTED
+    assert lib.pks_filter_tv(ctypes.byref(t), 16, y, y + 8, P, 0, ws, wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_smooth_tv(ctypes.byref(t), 16, m, P, None, FAKE + 0x4000000, 0, ws, wsb, None) == pks.PKS_E_ARG
+    t.Q = None
+    assert lib.pks_filter_smooth_tv(ctypes.byref(t), 16, y, m, P, FAKE + 0x4000000, FAKE + 0x5000000, 0, ws,
+                                    wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_loglik_tv(ctypes.byref(t), 16, y, m, P, FAKE + 0x4000000, None, 0, 0, ws, wsb,
+                             None) == pks.PKS_E_ARG

@@ -16,7 +16,7 @@ import scipy.linalg
 import oracle
 from oracle import elements as el
 from paper_1905_13002_amd import workloads as wl
-from tests.dense_posterior import joint_loglik, posterior
+from tests.dense_posterior import joint_loglik, posterior, posterior_tv
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -495,3 +495,59 @@ def test_oracle_loglik_batched_restarts_per_sequence():
         sl = slice(offsets[b], offsets[b + 1])
         assert np.max(np.abs(cum[sl] - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
         assert tot[b] == cum[offsets[b + 1] - 1]
+
+
+# ---------------------------------------------------------------------------
+# time-varying models (Section IV's general model, one row per step)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,T", [(1, 1, 7), (2, 1, 12), (3, 2, 15), (4, 2, 10), (5, 3, 8)])
+def test_oracle_tv_matches_dense_joint_posterior(nx, ny, T):
+    """Per-step F, Q, u, H, R, d: the recursion against the dense joint
+    Gaussian built from the products F_{k-1} ... F_i, including the
+    log-likelihood of every prefix."""
+    rng = np.random.default_rng(3000 + 31 * nx + ny + T)
+    model = wl.random_tv_model(nx, ny, T, rng)
+    y, _ = wl.simulate_tv(model, rng)
+    out = oracle.kf_rts_tv(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, u=model.u, d=model.d,
+                           loglik=True)
+    m, P, ms, Ps, ll = posterior_tv(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, model.u, model.d)
+    for key, ref in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps)):
+        assert nerr(out[key], ref) < 1e-10, key
+    cum, _ = oracle.loglik_prefix(out["ll"])
+    assert np.max(np.abs(cum - ll) / np.maximum(1.0, np.abs(ll))) < 1e-10
+
+
+def test_oracle_tv_irregular_cv_matches_dense():
+    w = wl.workload(6, T=25)
+    mo = w.model
+    out = oracle.kf_rts_tv(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y, loglik=True)
+    m, P, ms, Ps, ll = posterior_tv(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y)
+    for key, ref in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps)):
+        assert nerr(out[key], ref) < 1e-10, key
+
+
+def test_oracle_tv_with_equal_rows_is_the_time_invariant_recursion():
+    """Every row the same model: bitwise the time-invariant result."""
+    rng = np.random.default_rng(12)
+    mo = wl.random_small_model(3, 2, rng)
+    T = 50
+    y, _ = wl.simulate(mo, T, rng)
+    rep = lambda a: np.broadcast_to(a, (T,) + a.shape).copy()
+    tv = oracle.kf_rts_tv(rep(mo.F), rep(mo.Q), rep(mo.H), rep(mo.R), mo.m0, mo.P0, y, u=rep(mo.u),
+                          d=rep(mo.d), loglik=True)
+    ti = run(mo, y, loglik=True)
+    for key in ("m", "P", "ms", "Ps", "ll"):
+        assert np.array_equal(tv[key], ti[key]), key
+
+
+def test_irregular_cv_model_constants():
+    """Workload 6's per-step model is the constant-velocity model of its own
+    interval (the Section V matrices with dt_k in place of dt)."""
+    w = wl.workload(6, T=5)
+    dts = w.model.F[:, 0, 2].copy()
+    for k in range(5):
+        ref = wl.cv_model(1.0, 0.25, dt=dts[k])
+        assert np.allclose(w.model.F[k], ref.F, rtol=0, atol=0)
+        assert np.allclose(w.model.Q[k], ref.Q, rtol=1e-15, atol=0)
+    assert np.all((dts >= 0.05) & (dts <= 0.15))
