@@ -54,9 +54,15 @@ def op_flops(n, ny):
                 s_elem=8.33 * n ** 3 + 6 * n * n, s_full=6 * n ** 3 + 2 * n * n, s_carry=4 * n ** 3 + 2 * n * n)
 
 
-def kernel_model(nx, ny, rs):
+def kernel_model(nx, ny, rs, tv=False):
     mom = (nx + nx * nx) * rs
     f = op_flops(nx, ny)
+    # time-varying model: the precompute builds every step's constants from its
+    # own model rows (F, Q, u, H, d, R in; the Lemma 1 factors S = L L^T, K,
+    # A, C, J, W and the first-step element are counted as products/solves)
+    rows = (2 * nx * nx + nx + ny * nx + ny + ny * ny) * 8
+    pre_flops = (2 * ny * nx * nx + 2 * ny * ny * nx + ny ** 3 / 3 + 4 * ny * ny * nx
+                 + 3 * 2 * nx * nx * ny + 2 * nx * nx * nx)
     per_step = {
         "reduce_f": dict(bytes=ny * rs, flops=f["f_full"] + f["f_elem"]),
         "down_f": dict(bytes=ny * rs + mom, flops=f["f_carry"] + f["f_elem"]),
@@ -66,13 +72,16 @@ def kernel_model(nx, ny, rs):
         # are written once and folded into smoothing elements from registers
         "down_f_reduce_s": dict(bytes=ny * rs + mom, flops=f["f_carry"] + f["f_elem"] + f["s_elem"] + f["s_full"]),
     }
-    return {
+    out = {
         "k_filter_down_smooth_reduce": per_step["down_f_reduce_s"],
         "k_filter_reduce": per_step["reduce_f"], "k_large_filter_reduce": per_step["reduce_f"],
         "k_filter_down": per_step["down_f"], "k_large_filter_down": per_step["down_f"],
         "k_smoother_reduce": per_step["reduce_s"], "k_large_smoother_reduce": per_step["reduce_s"],
         "k_smoother_down": per_step["down_s"], "k_large_smoother_down": per_step["down_s"],
     }
+    if tv:
+        out["k_precompute"] = dict(bytes=rows, flops=pre_flops)
+    return out
 
 
 def ll_kernel_model(nx, ny, rs):
@@ -265,7 +274,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--op", default="filter_smooth", choices=["filter_smooth", "loglik"],
                     help="what a timed step runs (default: the filter + smoother pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -313,7 +322,8 @@ def main():
     T = w.total
     nx, ny = w.model.nx, w.model.ny
     batched = w.B > 1
-    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence)
+    tv = w.time_varying
+    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence, time_varying=tv)
     off = torch.as_tensor(w.offsets).to(dev) if batched else None
 
     results = {}
@@ -324,7 +334,7 @@ def main():
         P = torch.empty((T, nx, nx), dtype=rdt, device=dev)
         ms = torch.empty_like(m)
         Ps = torch.empty_like(P)
-        ws = pks.workspace(nx, ny, T, w.B, prec, dev)
+        ws = pks.workspace(nx, ny, T, w.B, prec, dev, time_varying=tv)
         if batched:
             plan = pks.Plan(dm, y, off, prec)
             m, P, ms, Ps = plan.m, plan.P, plan.ms, plan.Ps
@@ -362,7 +372,8 @@ def main():
     def ref_for(prec, b=None):
         yy = w.y if prec == "fp64" else w.y.astype(np.float32).astype(np.float64)
         if b is None:
-            return oracle.kf_rts(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, yy)
+            run = oracle.kf_rts_tv if tv else oracle.kf_rts
+            return run(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, yy)
         mo = w.model_of(b)
         return oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, yy[w.seq(b)])
 
@@ -387,7 +398,7 @@ def main():
     # roofline of the dominant kernel (FP64 headline)
     def roofline(prec):
         rs = 8 if prec == "fp64" else 4
-        model = kernel_model(nx, ny, rs)
+        model = kernel_model(nx, ny, rs, tv)
         prof = results[prec]["prof"]
         per_launch = {k: tot / max(1, n) for k, (tot, n) in prof.items()}
         dom = max(per_launch, key=per_launch.get)
@@ -437,9 +448,10 @@ def main():
         else:
             times = []
             t_start = time.perf_counter()
+            run = oracle.kf_rts_tv if tv else oracle.kf_rts
             while True:
                 t0 = time.perf_counter()
-                oracle.kf_rts(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, w.y)
+                run(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, w.y)
                 times.append(time.perf_counter() - t0)
                 if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 50:
                     break
@@ -465,8 +477,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded simulation of the model)",
-        "config": {"workload": w.name, "T": T, "B": w.B, "nx": nx, "ny": ny,
-                   "path": "plan (hipGraph)" if batched else "pks_filter_smooth"},
+        "config": {"workload": w.name, "T": T, "B": w.B, "nx": nx, "ny": ny, "time_varying": tv,
+                   "path": "plan (hipGraph)" if batched else ("pks_filter_smooth_tv" if tv else "pks_filter_smooth")},
         "max_rel_err": {k: float("%.3e" % v) for k, v in errs["fp64"].items()},
         "err_sample": "all steps" if not batched else "%d of %d sequences" % (len(sample), w.B),
         "roofline": rl64,
@@ -487,13 +499,15 @@ def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
     T, B = w.total, w.B
     nx, ny = w.model.nx, w.model.ny
     batched = B > 1
-    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence)
+    tv = w.time_varying
+    dm = pks.to_device(w.model, device=dev, per_sequence=w.per_sequence, time_varying=tv)
     off = torch.as_tensor(w.offsets).to(dev) if batched else None
+    orun = oracle.kf_rts_tv if tv else oracle.kf_rts
     results = {}
     for prec in ("fp64", "mixed"):
         rdt = torch.float64 if prec == "fp64" else torch.float32
         y = torch.as_tensor(w.y).to(dev, rdt)
-        ws = pks.workspace(nx, ny, T, B, prec, dev)
+        ws = pks.workspace(nx, ny, T, B, prec, dev, time_varying=tv)
         if batched:
             m, P = pks.filter_batched(dm, off, y, prec, ws=ws)
             step = lambda: pks.loglik_batched(dm, off, y, m, P, prec, cumulative=True, ws=ws)
@@ -518,7 +532,7 @@ def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
         for b in sample:
             mo = w.model_of(b) if batched else w.model
             s_ = w.seq(b) if batched else slice(0, T)
-            ref = oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, yy[s_], smooth=False, loglik=True)["ll"]
+            ref = orun(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, yy[s_], smooth=False, loglik=True)["ll"]
             rc = np.cumsum(ref)
             g = results[prec]["cum"][s_]
             e_cum = max(e_cum, float(np.max(np.abs(g - rc) / np.maximum(1.0, np.abs(rc)))))
@@ -551,7 +565,7 @@ def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
                 s_ = w.seq(b) if batched else slice(0, T)
                 offs = np.array([0, s_.stop - s_.start])
                 t0 = time.perf_counter()
-                ll = oracle.kf_rts(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y[s_], smooth=False, loglik=True)["ll"]
+                ll = orun(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y[s_], smooth=False, loglik=True)["ll"]
                 oracle.loglik_prefix(ll, offs)
                 dt += time.perf_counter() - t0
                 nsteps += s_.stop - s_.start
@@ -577,8 +591,9 @@ def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded simulation of the model)",
-        "config": {"workload": w.name, "T": T, "B": B, "nx": nx, "ny": ny,
-                   "path": "pks_loglik_batched" if batched else "pks_loglik", "cumulative": True},
+        "config": {"workload": w.name, "T": T, "B": B, "nx": nx, "ny": ny, "time_varying": tv,
+                   "path": "pks_loglik_batched" if batched else ("pks_loglik_tv" if tv else "pks_loglik"),
+                   "cumulative": True},
         "max_rel_err": errs["fp64"],
         "err_sample": "all steps" if not batched else "%d of %d sequences" % (len(sample), B),
         "roofline": rl64,
