@@ -362,13 +362,43 @@ struct SmallPre {
     }
 };
 
-// writes a constant in double and, for the mixed mode, in float
-struct DualOut {
-    double* d;
-    float* f;
-    __device__ __forceinline__ void put(int i, double v) const {
-        d[i] = v;
-        if (f) f[i] = (float)v;
+// Makes one wave's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Writes the constants of the wave's 64 models field by field: every lane
+// puts the n words of one field of its own model into an LDS stage, then the
+// wave stores them with consecutive lanes on consecutive words (runs of n
+// words per model) instead of one store per word that touches 64 models'
+// lines; in the mixed mode a float copy goes out alongside.  A model whose
+// factorisation failed writes NaN.  Every lane of the wave must call emit.
+template <int MAXN>
+struct WaveWriter {
+    double* stg;          // LDS [64][MAXN + 1]
+    double* d;            // constants of the wave's first model
+    float* f;             // their float copy (mixed mode) or nullptr
+    int cw;               // words per model
+    int nvalid;           // models of this wave that exist
+    template <int N>
+    __device__ __forceinline__ void emit(int off, const double (&v)[N], bool ok) const {
+        static_assert(N <= MAXN, "field larger than the stage");
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int i = 0; i < N; ++i) stg[lane * (MAXN + 1) + i] = ok ? v[i] : __builtin_nan("");
+        wave_sync_lds();
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const int e = r * 64 + lane, bl = e / N, i = e - bl * N;
+            if (bl < nvalid) {
+                const double x = stg[bl * (MAXN + 1) + i];
+                d[(size_t)bl * cw + off + i] = x;
+                if (f) f[(size_t)bl * cw + off + i] = (float)x;
+            }
+        }
+        wave_sync_lds();          // the stage is refilled by the next field
     }
 };
 
@@ -379,17 +409,21 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     // concurrently: even blocks derive the shared constants of the steps k > 1,
     // odd blocks the first-step element (and copy F, Q, u).  The odd half also
     // factors S = H Q H^T + R, so it alone decides whether the model failed.
+    constexpr int n2 = NX * NX, nm = NX * NY, m2 = NY * NY;
+    constexpr int MAXN = n2 > nm ? (n2 > m2 ? n2 : m2) : (nm > m2 ? nm : m2);
+    __shared__ double stg[64 * (MAXN + 1)];
     const int part = blockIdx.x & 1;
-    const int b = (blockIdx.x >> 1) * blockDim.x + threadIdx.x;
+    const int b0 = (blockIdx.x >> 1) * blockDim.x;
+    const int b = b0 + threadIdx.x;
+    const bool active = b < nmodels;
     if (blockIdx.x == 0 && threadIdx.x == 0 && !a.tv) {
         if (a.reset || a.status[1] != kStatusMagic) {
             a.status[0] = kStatusOk;
             a.status[1] = kStatusMagic;
         }
     }
-    if (b >= nmodels) return;
-    constexpr int n2 = NX * NX, nm = NX * NY, m2 = NY * NY;
-    const Rows rw = model_rows(a, b, nmodels);
+    // lanes past the last model repeat its arithmetic and write nothing
+    const Rows rw = model_rows(a, active ? b : nmodels - 1, nmodels);
     double F[n2], Q[n2], H[nm], R[m2], m0[NX], P0[n2], u[NX], d[NY];
 #pragma unroll
     for (int i = 0; i < n2; ++i) {
@@ -410,10 +444,12 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     for (int i = 0; i < NY; ++i) d[i] = a.d ? a.d[rw.f * NY + i] : 0.0;
 
     const ConstLayout CL = const_layout(NX, NY);
-    DualOut out{a.consts64 + (size_t)b * a.cw, a.mixed ? a.consts32 + (size_t)b * a.cw : nullptr};
+    const int nvalid = nmodels - b0 < 64 ? nmodels - b0 : 64;
+    const WaveWriter<MAXN> out{stg, a.consts64 + (size_t)b0 * a.cw,
+                               a.mixed ? a.consts32 + (size_t)b0 * a.cw : nullptr, a.cw, nvalid};
     bool ok = true;
     if ((a.what & 1) && part == 0) {
-        double T1[nm], S[m2], Lc[m2], Kt[nm], G[nm], Z[nm], X[n2], e[NY], v[NX];
+        double T1[nm], S[m2], Lc[m2], Kt[nm], G[nm], Z[nm], X[n2], e[NY], v[NX], col[nm];
         SP::template mm<NY, NX, NX, false, false>(T1, H, Q);          // H Q
         SP::template mm<NY, NX, NY, false, true>(S, T1, H);           // H Q H^T
 #pragma unroll
@@ -424,50 +460,50 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         for (int i = 0; i < nm; ++i) Kt[i] = T1[i];
         SP::template solve<NY, NX>(Lc, Kt);                           // K^T = S^-1 H Q
         SP::template mm<NY, NX, NX, false, false>(G, H, F);           // H F
+        out.emit(CL.G, G, ok);
+        out.emit(CL.S, S, ok);
 #pragma unroll
-        for (int i = 0; i < nm; ++i) {
-            Z[i] = G[i];
-            out.put(CL.G + i, G[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < m2; ++i) out.put(CL.S + i, S[i]);
+        for (int i = 0; i < nm; ++i) Z[i] = G[i];
         SP::template solve<NY, NX>(Lc, Z);                            // S^-1 H F
 #pragma unroll
         for (int i = 0; i < NY; ++i)
 #pragma unroll
-            for (int j = 0; j < NX; ++j) {
-                out.put(CL.K + j * NY + i, Kt[i * NX + j]);
-                out.put(CL.W + j * NY + i, Z[i * NX + j]);
-            }
+            for (int j = 0; j < NX; ++j) col[j * NY + i] = Kt[i * NX + j];
+        out.emit(CL.K, col, ok);
+#pragma unroll
+        for (int i = 0; i < NY; ++i)
+#pragma unroll
+            for (int j = 0; j < NX; ++j) col[j * NY + i] = Z[i * NX + j];
+        out.emit(CL.W, col, ok);
         SP::template mm<NX, NY, NX, true, false>(X, G, Z);           // F^T H^T S^-1 H F
         SP::template sym<NX>(X);
-#pragma unroll
-        for (int i = 0; i < n2; ++i) out.put(CL.J + i, X[i]);
+        out.emit(CL.J, X, ok);
         SP::template mm<NX, NY, NX, true, false>(X, Kt, G);          // K H F
 #pragma unroll
-        for (int i = 0; i < n2; ++i) out.put(CL.A + i, F[i] - X[i]);
+        for (int i = 0; i < n2; ++i) X[i] = F[i] - X[i];
+        out.emit(CL.A, X, ok);
         SP::template mm<NX, NY, NX, true, false>(X, Kt, T1);         // K H Q
 #pragma unroll
         for (int i = 0; i < n2; ++i) X[i] = Q[i] - X[i];
         SP::template sym<NX>(X);
-#pragma unroll
-        for (int i = 0; i < n2; ++i) out.put(CL.C + i, X[i]);
+        out.emit(CL.C, X, ok);
         SP::template mm<NY, NX, 1, false, false>(e, H, u);           // H u + d
 #pragma unroll
-        for (int i = 0; i < NY; ++i) {
-            e[i] += d[i];
-            out.put(CL.e + i, e[i]);
-        }
+        for (int i = 0; i < NY; ++i) e[i] += d[i];
+        out.emit(CL.e, e, ok);
         SP::template mm<NX, NY, 1, true, false>(v, Kt, e);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out.put(CL.c + i, u[i] - v[i]);
+        for (int i = 0; i < NX; ++i) v[i] = u[i] - v[i];
+        out.emit(CL.c, v, ok);
         SP::template mm<NX, NY, 1, true, false>(v, Z, e);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out.put(CL.w + i, -v[i]);
+        for (int i = 0; i < NX; ++i) v[i] = -v[i];
+        out.emit(CL.w, v, ok);
     }
-    if ((a.what & 1) && part == 1 && (!a.tv || b == 0)) {
+    // a time-varying model needs the first-step element at step 0 only (wave 0)
+    if ((a.what & 1) && part == 1 && (!a.tv || b0 == 0)) {
         // k = 1: one prediction from the prior and one update
-        double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm], X[n2], v[NX];
+        double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm], X[n2], v[NX], col[nm];
         SP::template mm<NX, NX, 1, false, false>(m1, F, m0);
 #pragma unroll
         for (int i = 0; i < NX; ++i) m1[i] += u[i];
@@ -497,40 +533,37 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
 #pragma unroll
         for (int i = 0; i < NY; ++i)
 #pragma unroll
-            for (int j = 0; j < NX; ++j) out.put(CL.K1 + j * NY + i, K1t[i * NX + j]);
+            for (int j = 0; j < NX; ++j) col[j * NY + i] = K1t[i * NX + j];
+        out.emit(CL.K1, col, ok);
         SP::template mm<NY, NX, 1, false, false>(e1, H, m1);
 #pragma unroll
         for (int i = 0; i < NY; ++i) e1[i] += d[i];
         SP::template mm<NX, NY, 1, true, false>(v, K1t, e1);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out.put(CL.c1 + i, m1[i] - v[i]);
+        for (int i = 0; i < NX; ++i) v[i] = m1[i] - v[i];
+        out.emit(CL.c1, v, ok);
         SP::template mm<NX, NY, NY, true, false>(U, K1t, S1);        // K1 S1
         SP::template mm<NX, NY, NX, false, false>(X, U, K1t);        // K1 S1 K1^T
 #pragma unroll
         for (int i = 0; i < n2; ++i) X[i] = P1[i] - X[i];
         SP::template sym<NX>(X);
-#pragma unroll
-        for (int i = 0; i < n2; ++i) out.put(CL.C1 + i, X[i]);
+        out.emit(CL.C1, X, ok);
     }
-    if ((a.what & 1) && part == 1) a.model_fail[b] = ok ? 0 : 1;
-    if (a.tv && !ok) atomicMin(a.status, 0);          // either half of a failing step
+    if (active) {
+        if ((a.what & 1) && part == 1) a.model_fail[b] = ok ? 0 : 1;
+        if (a.tv && !ok) atomicMin(a.status, 0);          // either half of a failing step
+    }
     if ((a.what & 2) && part == 1) {
+        double X[n2], v[NX];
 #pragma unroll
-        for (int i = 0; i < n2; ++i) {
-            out.put(CL.F + i, a.F[rw.s * n2 + i]);
-            out.put(CL.Q + i, a.Q[rw.s * n2 + i]);
-        }
+        for (int i = 0; i < n2; ++i) X[i] = a.F[rw.s * n2 + i];
+        out.emit(CL.F, X, true);
 #pragma unroll
-        for (int i = 0; i < NX; ++i) out.put(CL.u + i, a.u ? a.u[rw.s * NX + i] : 0.0);
-    }
-    if (!ok) {
-        // NaN in the fields this half owns (constants A .. w and G, S; or the
-        // first-step K1, c1, C1).  Every filtered prefix holds the first-step
-        // element, so all of a failing sequence's outputs come out NaN.
-        const int lo = part == 0 ? CL.A : CL.K1, hi = part == 0 ? CL.K1 : CL.G;
-        for (int i = lo; i < hi; ++i) out.put(i, __builtin_nan(""));
-        if (part == 0)
-            for (int i = CL.G; i < CL.F; ++i) out.put(i, __builtin_nan(""));
+        for (int i = 0; i < n2; ++i) X[i] = a.Q[rw.s * n2 + i];
+        out.emit(CL.Q, X, true);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) v[i] = a.u ? a.u[rw.s * NX + i] : 0.0;
+        out.emit(CL.u, v, true);
     }
 }
 
