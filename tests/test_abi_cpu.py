@@ -187,3 +187,23 @@ def test_time_varying_argument_errors():
                                     wsb, None) == pks.PKS_E_ARG
     assert lib.pks_loglik_tv(ctypes.byref(t), 16, y, m, P, FAKE + 0x4000000, None, 0, 0, ws, wsb,
                              None) == pks.PKS_E_ARG
+
+
+def test_time_varying_batched_argument_errors():
+    t = pks.pks_model_tv()
+    t.nx, t.ny = 3, 2
+    for i, f in enumerate(("F", "Q", "H", "R", "m0", "P0")):
+        setattr(t, f, FAKE + 0x100000 * (i + 1))
+    t.per_sequence = 1
+    wsb = lib.pks_workspace_bytes_tv(3, 2, 100, 0)
+    y, m, P, ws = FAKE + 0x1000000, FAKE + 0x2000000, FAKE + 0x3000000, FAKE + 0x8000000
+    # per-sequence priors need a batched call
+    assert lib.pks_filter_tv(ctypes.byref(t), 100, y, m, P, 0, ws, wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_filter_tv_batched(ctypes.byref(t), 0, FAKE, 100, y, m, P, 0, ws, wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_filter_tv_batched(ctypes.byref(t), 3, None, 100, y, m, P, 0, ws, wsb, None) == pks.PKS_E_ARG
+    assert lib.pks_filter_tv_batched(ctypes.byref(t), 3, FAKE, 100, y, m, P, 0, ws, wsb - 1,
+                                     None) == pks.PKS_E_WORKSPACE
+    assert lib.pks_smooth_tv_batched(ctypes.byref(t), 3, FAKE, 100, m, P, m + 8, FAKE + 0x4000000, 0, ws, wsb,
+                                     None) == pks.PKS_E_ARG
+    assert lib.pks_loglik_tv_batched(ctypes.byref(t), 3, FAKE, 100, y, m, P, None, None, 0, 0, ws, wsb,
+                                     None) == pks.PKS_E_ARG
