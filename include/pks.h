@@ -176,19 +176,22 @@ pks_status pks_loglik_batched(const pks_model *model, int32_t B, const int64_t *
  * pointer to T stacked double matrices; row k-1 holds the step-k quantities:
  *   F [T][nx][nx] (F_{k-1}: the transition INTO step k), Q [T][nx][nx],
  *   u [T][nx] or NULL, H [T][ny][nx], R [T][ny][ny], d [T][ny] or NULL;
- *   m0 [nx], P0 [nx][nx] as for pks_model.
+ *   m0 [nx], P0 [nx][nx] as for pks_model; per_sequence = 1 (batched calls
+ *   only): m0 [B][nx], P0 [B][nx][nx] hold one prior per sequence.
  * The smoothing element of step k (Lemma 3) uses the transition out of it,
  * row k (F_k, Q_k, u_k); row 0 is used by the filter only.  Every step's
  * Lemma 1 element is built from its own rows, so the workspace holds one
- * block of constants per step: size it with pks_workspace_bytes_tv.  Single
- * sequence; a failing factorisation flags sequence 0 and gives NaN outputs
- * from that step on.
+ * block of constants per step: size it with pks_workspace_bytes_tv (total
+ * steps).  Batched calls pack the sequences' rows like y (row i belongs to
+ * the step in row i of y), each sequence starting from its prior.  A failing
+ * factorisation flags its sequence and gives NaN outputs from that step on.
  */
 typedef struct {
     int32_t nx, ny;
     const double *F, *u, *Q;
     const double *H, *d, *R;
     const double *m0, *P0;
+    int32_t per_sequence;
 } pks_model_tv;
 /* Workspace bytes for the time-varying calls below (T <= 2^31 - 1); 0 if invalid. */
 size_t pks_workspace_bytes_tv(int32_t nx, int32_t ny, int64_t T, pks_precision prec);
@@ -204,6 +207,17 @@ pks_status pks_filter_smooth_tv(const pks_model_tv *model, int64_t T, const void
 pks_status pks_loglik_tv(const pks_model_tv *model, int64_t T, const void *y, const void *m, const void *P,
                          double *ll, double *ll_total, int32_t cumulative, pks_precision prec, void *ws,
                          size_t ws_bytes, void *stream);
+/* Packed time-varying sequences: offsets and outputs as in pks_filter_batched
+ * and pks_loglik_batched; the model rows are packed like y. */
+pks_status pks_filter_tv_batched(const pks_model_tv *model, int32_t B, const int64_t *offsets, int64_t total,
+                                 const void *y, void *m, void *P, pks_precision prec, void *ws, size_t ws_bytes,
+                                 void *stream);
+pks_status pks_smooth_tv_batched(const pks_model_tv *model, int32_t B, const int64_t *offsets, int64_t total,
+                                 const void *m, const void *P, void *ms, void *Ps, pks_precision prec, void *ws,
+                                 size_t ws_bytes, void *stream);
+pks_status pks_loglik_tv_batched(const pks_model_tv *model, int32_t B, const int64_t *offsets, int64_t total,
+                                 const void *y, const void *m, const void *P, double *ll, double *ll_total,
+                                 int32_t cumulative, pks_precision prec, void *ws, size_t ws_bytes, void *stream);
 /*
  * Plans: the whole filter + smoother of a (batched) problem, with its tile
  * configuration taken from the tuning cache, captured once into a HIP graph

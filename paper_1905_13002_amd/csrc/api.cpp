@@ -165,11 +165,12 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
     if (cfg.ept < kMinEpt) cfg.ept = kMinEpt;
     hipError_t e = launch_precompute(model.nx, model.ny, nmodels, model, ws, L, mixed, passes,
-                                     (passes & 1) != 0, s, tv);
+                                     (passes & 1) != 0, s, tv, tv ? offsets : nullptr, B);
     if (e != hipSuccess) return hip_fail(e, "precompute kernel");
-    // a time-varying model runs as one packed sequence (offsets {0, T}, written
-    // by the precompute's preparation kernel) through the per-step-constant kernels
-    if (tv) offsets = reinterpret_cast<const int64_t*>(static_cast<char*>(ws) + L.tv_offsets);
+    // a single time-varying sequence runs as one packed sequence (offsets {0, T},
+    // written by the precompute's preparation kernel) through the per-step-constant
+    // kernels; packed time-varying sequences keep the caller's offsets
+    if (tv && !offsets) offsets = reinterpret_cast<const int64_t*>(static_cast<char*>(ws) + L.tv_offsets);
     ScanArgs a = make_scan_args(model, B, offsets, total, prec, ws, L, cfg, tv);
     a.y = y;
     a.m = m;
@@ -272,7 +273,9 @@ pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets
         return PKS_OK;
     }
     const int nmodels = tv ? (int)total : (model->per_sequence ? B : 1);
-    hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 1, false, s, tv);
+    // only G, S, e of every model (or step) are read: precompute mode 4
+    hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 4, false, s, tv,
+                                     (tv && batched) ? offsets : nullptr, B);
     if (e != hipSuccess) return hip_fail(e, "precompute kernel");
     e = launch_loglik(*model, B, batched ? offsets : nullptr, total, y, m, P, ll, tot, cumulative != 0,
                       prec == PKS_MIXED_FP32, ws, L, s, tv);
@@ -409,7 +412,7 @@ pks_status tv_model(const pks_model_tv* t, int64_t T, pks_model* out) {
     out->F = t->F; out->u = t->u; out->Q = t->Q;
     out->H = t->H; out->d = t->d; out->R = t->R;
     out->m0 = t->m0; out->P0 = t->P0;
-    out->per_sequence = 0;
+    out->per_sequence = t->per_sequence;
     return PKS_OK;
 }
 }  // namespace
@@ -452,6 +455,41 @@ pks_status pks_filter_smooth_tv(const pks_model_tv* model, int64_t T, const void
     if (st) return st;
     return enqueue(mo, 1, nullptr, T, y, m, P, ms, Ps, prec, ws, ws_bytes, 3, nullptr, (hipStream_t)stream,
                    true);
+}
+
+pks_status pks_filter_tv_batched(const pks_model_tv* model, int32_t B, const int64_t* offsets, int64_t total,
+                                 const void* y, void* m, void* P, pks_precision prec, void* ws, size_t ws_bytes,
+                                 void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, total, &mo);
+    if (!st) st = validate_io(&mo, B, offsets, total, y, m, P, nullptr, nullptr, prec, ws, 1, true);
+    if (st) return st;
+    return enqueue(mo, B, offsets, total, y, m, P, nullptr, nullptr, prec, ws, ws_bytes, 1, nullptr,
+                   (hipStream_t)stream, true);
+}
+
+pks_status pks_smooth_tv_batched(const pks_model_tv* model, int32_t B, const int64_t* offsets, int64_t total,
+                                 const void* m, const void* P, void* ms, void* Ps, pks_precision prec, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, total, &mo);
+    if (!st) st = validate_io(&mo, B, offsets, total, nullptr, m, P, ms, Ps, prec, ws, 2, true);
+    if (st) return st;
+    return enqueue(mo, B, offsets, total, nullptr, const_cast<void*>(m), const_cast<void*>(P), ms, Ps, prec, ws,
+                   ws_bytes, 2, nullptr, (hipStream_t)stream, true);
+}
+
+pks_status pks_loglik_tv_batched(const pks_model_tv* model, int32_t B, const int64_t* offsets, int64_t total,
+                                 const void* y, const void* m, const void* P, double* ll, double* ll_total,
+                                 int32_t cumulative, pks_precision prec, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    pks_model mo;
+    pks_status st = tv_model(model, total, &mo);
+    if (st) return st;
+    return loglik_impl(&mo, B, offsets, total, y, m, P, ll, ll_total, cumulative, prec, ws, ws_bytes, true,
+                       (hipStream_t)stream, true);
 }
 
 pks_status pks_loglik_tv(const pks_model_tv* model, int64_t T, const void* y, const void* m, const void* P,

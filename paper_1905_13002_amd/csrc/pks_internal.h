@@ -148,10 +148,11 @@ bool small_supported(int nx);
 // Time-varying models (`tv`): the arrays of `model` hold one row per step and
 // every step gets its own constants (nmodels = steps): the filter constants of
 // step k from row k, the smoother's F, Q, u from row k + 1; the prior is
-// shared, and a failing factorisation flags sequence 0 directly.
+// shared, or one per packed sequence (tv_offsets [B+1], model.per_sequence),
+// and a failing factorisation flags its sequence directly.
 hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model,
                              void* ws, const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s,
-                             bool tv = false);
+                             bool tv = false, const int64_t* tv_offsets = nullptr, int32_t B = 1);
 // passes: 1 = filter, 2 = smoother, 3 = both (fused where possible)
 hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
@@ -162,7 +163,7 @@ int64_t ll_blocks(int64_t total);
 // Per-step log predictive densities of the filtered sequences (ll: [total] or
 // nullptr), or with `cumulative` their running sums within each sequence, and
 // per-sequence totals (tot: [B] or nullptr).  offsets = nullptr: one sequence.
-// Needs the filter constants of the model in ws (launch_precompute, what 1).
+// Needs G, S, e of the model in ws (launch_precompute, what 4).
 hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total,
                          const void* y, const void* m, const void* P, double* ll, double* tot,
                          bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s,

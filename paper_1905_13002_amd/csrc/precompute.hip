@@ -34,17 +34,36 @@ struct PrecomputeArgs {
     int* status;
     int* model_fail;
     int mixed;
-    int what;   // 1: filter constants, 2: smoother constants (F, Q, u), 3: both
+    int what;   // 1: filter constants, 2: smoother constants (F, Q, u), 3: both,
+                // 4: only G, S, e (the one-step predictive density; small models)
     int reset;  // clear the numeric flag first
     int use_lds;  // temporaries and outputs in LDS (small models), copied out at the end
     int tv;       // time-varying model: one row of F, u, Q, H, d, R per step, model index = step
+    const int64_t* offsets;   // time-varying, batched: [B+1] packed sequences (else nullptr)
+    int B;
 };
+
+// Sequence holding step k of packed sequences (offsets[lo] <= k < offsets[lo + 1]).
+__device__ __forceinline__ int seq_of_step(const int64_t* off, int B, int64_t k) {
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Sequence of step b of a time-varying model (0 for a single sequence).
+__device__ __forceinline__ int tv_seq(const PrecomputeArgs& a, int b) {
+    return a.offsets ? seq_of_step(a.offsets, a.B, b) : 0;
+}
 
 // Rows of the model arrays that model (or step) b reads: its filter constants
 // (F, u, Q, H, d, R), its prior (m0, P0) and its smoother constants (F, Q, u).
 // A time-varying model's step b predicts with the transition into step b and
 // its smoothing element uses the transition out of it (row b + 1; the last
-// step has none and never uses it); the prior is shared.
+// step of a sequence never uses it); its prior is the shared one, or that of
+// its sequence when packed sequences carry one prior each (per_sequence).
 struct Rows {
     size_t f, p, s;
 };
@@ -53,7 +72,7 @@ __device__ __forceinline__ Rows model_rows(const PrecomputeArgs& a, int b, int n
     const size_t ps = a.per_sequence ? 1 : 0;
     if (a.tv) {
         r.f = (size_t)b;
-        r.p = 0;
+        r.p = a.per_sequence ? (size_t)tv_seq(a, b) : 0;
         r.s = (size_t)(b + 1 < nmodels ? b + 1 : b);
     } else {
         r.f = r.p = r.s = ps * (size_t)b;
@@ -234,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     bmm(out + CL.w, Z, true, e, false, nx, ny, 1, -1.0);       // -W e
 
     // ---- k = 1 element (a time-varying model needs it at its first step only) ----
-    if (!a.tv || b == 0) {
+    if (!a.tv || b == 0 || (a.offsets && a.offsets[tv_seq(a, b)] == b)) {
     bmm(m1, F, false, m0, false, nx, nx, 1, 1.0, uz);        // F m0 + u
     bmm(V, F, false, P0, false, nx, nx, nx);                 // F P0
     bmm(P1, V, false, F, true, nx, nx, nx, 1.0, Q);          // F P0 F^T + Q
@@ -269,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_precompute(PrecomputeArgs a) {
     }
     if ((a.what & 1) && threadIdx.x == 0) {
         a.model_fail[b] = ok ? 0 : 1;
-        if (a.tv && !ok) atomicMin(a.status, 0);
+        if (a.tv && !ok) atomicMin(a.status, tv_seq(a, b));
     }
     if (a.use_lds) {
         const int lo = (a.what & 1) ? 0 : CL.F;
@@ -448,6 +467,22 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     const WaveWriter<MAXN> out{stg, a.consts64 + (size_t)b0 * a.cw,
                                a.mixed ? a.consts32 + (size_t)b0 * a.cw : nullptr, a.cw, nvalid};
     bool ok = true;
+    if (a.what == 4 && part == 0) {
+        double T1[nm], S[m2], Lc[m2], G[nm], e[NY];
+        SP::template mm<NY, NX, NX, false, false>(T1, H, Q);          // H Q
+        SP::template mm<NY, NX, NY, false, true>(S, T1, H);           // H Q H^T
+#pragma unroll
+        for (int i = 0; i < m2; ++i) S[i] += R[i];
+        SP::template sym<NY>(S);
+        ok = SP::template chol<NY>(S, Lc);
+        SP::template mm<NY, NX, NX, false, false>(G, H, F);           // H F
+        SP::template mm<NY, NX, 1, false, false>(e, H, u);           // H u + d
+#pragma unroll
+        for (int i = 0; i < NY; ++i) e[i] += d[i];
+        out.emit(CL.G, G, ok);
+        out.emit(CL.S, S, ok);
+        out.emit(CL.e, e, ok);
+    }
     if ((a.what & 1) && part == 0) {
         double T1[nm], S[m2], Lc[m2], Kt[nm], G[nm], Z[nm], X[n2], e[NY], v[NX], col[nm];
         SP::template mm<NY, NX, NX, false, false>(T1, H, Q);          // H Q
@@ -500,8 +535,9 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
         for (int i = 0; i < NX; ++i) v[i] = -v[i];
         out.emit(CL.w, v, ok);
     }
-    // a time-varying model needs the first-step element at step 0 only (wave 0)
-    if ((a.what & 1) && part == 1 && (!a.tv || b0 == 0)) {
+    // a time-varying model needs the first-step element at each sequence start
+    // only: step 0 (wave 0) of a single sequence, every step of packed ones
+    if ((a.what & 1) && part == 1 && (!a.tv || b0 == 0 || a.offsets)) {
         // k = 1: one prediction from the prior and one update
         double m1[NX], V[n2], P1[n2], T2[nm], S1[m2], L1[m2], K1t[nm], e1[NY], U[nm], X[n2], v[NX], col[nm];
         SP::template mm<NX, NX, 1, false, false>(m1, F, m0);
@@ -551,7 +587,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     }
     if (active) {
         if ((a.what & 1) && part == 1) a.model_fail[b] = ok ? 0 : 1;
-        if (a.tv && !ok) atomicMin(a.status, 0);          // either half of a failing step
+        if (a.tv && !ok) atomicMin(a.status, tv_seq(a, b));   // either half of a failing step
     }
     if ((a.what & 2) && part == 1) {
         double X[n2], v[NX];
@@ -592,7 +628,8 @@ bool launch_small_pre(int nx, int ny, PrecomputeArgs a, int nmodels, hipStream_t
 }  // namespace
 
 hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& model, void* ws,
-                             const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s, bool tv) {
+                             const WsLayout& L, bool mixed, int what, bool reset, hipStream_t s, bool tv,
+                             const int64_t* tv_offsets, int32_t B) {
     PrecomputeArgs a;
     a.nx = nx;
     a.ny = ny;
@@ -612,6 +649,8 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
     a.what = what;
     a.reset = reset ? 1 : 0;
     a.tv = tv ? 1 : 0;
+    a.offsets = tv ? tv_offsets : nullptr;
+    a.B = B;
     if (tv)
         hipLaunchKernelGGL(k_status_prepare, dim3(1), dim3(1), 0, s, a.status, a.reset,
                            reinterpret_cast<int64_t*>(base + L.tv_offsets), (int64_t)nmodels);
@@ -621,8 +660,10 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
     a.use_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
     const int threads = (a.use_lds && nx <= 16 && ny <= 16) ? 64 : kThreads;
     prof_begin("k_precompute", s);
-    if (!(nx <= 4 && ny <= 4 && launch_small_pre(nx, ny, a, nmodels, s)))
+    if (!(nx <= 4 && ny <= 4 && launch_small_pre(nx, ny, a, nmodels, s))) {
+        if (a.what == 4) a.what = 1;     // the cooperative kernel derives G, S, e with the rest
         hipLaunchKernelGGL(k_precompute, dim3(nmodels), dim3(threads), a.use_lds ? lds_bytes : 0, s, a);
+    }
     prof_end(s);
     return hipGetLastError();
 }

@@ -27,7 +27,8 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_filter_batched", "pks_smooth_batched", "pks_plan_create", "pks_plan_launch",
             "pks_plan_destroy", "pks_autotune", "pks_read_numeric_status", "pks_last_error",
             "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched",
-            "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv"]
+            "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv",
+            "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched"]
 
 
 class PksError(RuntimeError):
@@ -48,7 +49,7 @@ class pks_model_tv(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("F", ctypes.c_void_p), ("u", ctypes.c_void_p), ("Q", ctypes.c_void_p),
                 ("H", ctypes.c_void_p), ("d", ctypes.c_void_p), ("R", ctypes.c_void_p),
-                ("m0", ctypes.c_void_p), ("P0", ctypes.c_void_p)]
+                ("m0", ctypes.c_void_p), ("P0", ctypes.c_void_p), ("per_sequence", ctypes.c_int32)]
 
 
 def _load():
@@ -65,6 +66,10 @@ def _load():
         "pks_smooth_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_filter_smooth_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_loglik_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz, vp]),
+        "pks_filter_tv_batched": (ctypes.c_int, [mt, i32, vp, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_smooth_tv_batched": (ctypes.c_int, [mt, i32, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
+        "pks_loglik_tv_batched": (ctypes.c_int, [mt, i32, vp, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz,
+                                                 vp]),
         "pks_workspace_bytes": (sz, [i32, i32, i64, i32, ctypes.c_int]),
         "pks_filter": (ctypes.c_int, [mp, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_smooth": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
@@ -154,8 +159,7 @@ class DeviceModel:
         for f in ("F", "Q", "H", "R", "m0", "P0", "u", "d"):
             t = getattr(self, f)
             setattr(s, f, None if t is None else t.data_ptr())
-        if not self.time_varying:
-            s.per_sequence = 1 if self.per_sequence else 0
+        s.per_sequence = 1 if self.per_sequence else 0
         return s
 
 
@@ -183,7 +187,7 @@ def workspace(nx, ny, total, B=1, precision="fp64", device="cuda", time_varying=
 
 def _single_only(model: "DeviceModel"):
     if model.time_varying:
-        raise ValueError("time-varying models run as single sequences (filter, smooth, filter_smooth, loglik)")
+        raise ValueError("time-varying models are not captured into plans: use the eager calls")
 
 
 def _ws_for(model: "DeviceModel", total, B, prec, device):
@@ -240,30 +244,30 @@ def filter_smooth(model: DeviceModel, y: torch.Tensor, precision="fp64", ws=None
 
 def filter_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, precision="fp64", ws=None,
                    out=None, stream=None):
-    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = y.shape[0]
     nx = model.nx
     m, P = out if out is not None else (_out((total, nx), prec, y.device), _out((total, nx, nx), prec, y.device))
-    ws = ws if ws is not None else workspace(nx, model.ny, total, B, prec, y.device)
+    ws = ws if ws is not None else _ws_for(model, total, B, prec, y.device)
     st = model.struct()
-    _check(lib.pks_filter_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P), prec,
-                                  _ptr(ws), ws.numel(), _stream(stream)))
+    fn = lib.pks_filter_tv_batched if model.time_varying else lib.pks_filter_batched
+    _check(fn(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P), prec, _ptr(ws), ws.numel(),
+              _stream(stream)))
     return m, P
 
 
 def smooth_batched(model: DeviceModel, offsets: torch.Tensor, m: torch.Tensor, P: torch.Tensor,
                    precision="fp64", ws=None, out=None, stream=None):
-    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = m.shape[0]
     ms_, Ps_ = out if out is not None else (torch.empty_like(m), torch.empty_like(P))
-    ws = ws if ws is not None else workspace(model.nx, model.ny, total, B, prec, m.device)
+    ws = ws if ws is not None else _ws_for(model, total, B, prec, m.device)
     st = model.struct()
-    _check(lib.pks_smooth_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(m), _ptr(P), _ptr(ms_),
-                                  _ptr(Ps_), prec, _ptr(ws), ws.numel(), _stream(stream)))
+    fn = lib.pks_smooth_tv_batched if model.time_varying else lib.pks_smooth_batched
+    _check(fn(ctypes.byref(st), B, _ptr(offsets), total, _ptr(m), _ptr(P), _ptr(ms_), _ptr(Ps_), prec, _ptr(ws),
+              ws.numel(), _stream(stream)))
     return ms_, Ps_
 
 
@@ -288,17 +292,16 @@ def loglik(model: DeviceModel, y: torch.Tensor, m: torch.Tensor, P: torch.Tensor
 def loglik_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, m: torch.Tensor,
                    P: torch.Tensor, precision="fp64", cumulative=False, steps=True, ws=None, stream=None):
     """Batched marginal likelihood: returns (ll [total] or None, totals [B])."""
-    _single_only(model)
     prec = _prec(precision)
     B = offsets.shape[0] - 1
     total = y.shape[0]
     ll = torch.empty(total, dtype=torch.float64, device=y.device) if (steps or cumulative) else None
     tot = torch.empty(B, dtype=torch.float64, device=y.device)
-    ws = ws if ws is not None else workspace(model.nx, model.ny, total, B, prec, y.device)
+    ws = ws if ws is not None else _ws_for(model, total, B, prec, y.device)
     st = model.struct()
-    _check(lib.pks_loglik_batched(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P),
-                                  _ptr(ll), _ptr(tot), 1 if cumulative else 0, prec, _ptr(ws), ws.numel(),
-                                  _stream(stream)))
+    fn = lib.pks_loglik_tv_batched if model.time_varying else lib.pks_loglik_batched
+    _check(fn(ctypes.byref(st), B, _ptr(offsets), total, _ptr(y), _ptr(m), _ptr(P), _ptr(ll), _ptr(tot),
+              1 if cumulative else 0, prec, _ptr(ws), ws.numel(), _stream(stream)))
     return ll, tot
 
 

@@ -293,3 +293,27 @@ def test_loglik_runs_of_empty_sequences(pks):
     model6 = wl.random_stable_model(6, 2, rng, radius=0.9)
     y6, _ = wl.simulate(model6, int(offsets[-1]), rng)
     check_ll(pks, model6, y6, "fp64", offsets=offsets, what="empty runs 6x2")
+
+
+def test_loglik_cv_T2pow23(pks):
+    """T = 2^23 (2048 blocks of the prefix sums, so the top-level scan runs
+    over several chunks): every partial sum against the oracle's running sum
+    (bar: 1e-9 of the running sum of |factors|)."""
+    w = wl.workload(1, T=1 << 23)
+    ref = oracle.kf_rts(w.model.F, w.model.Q, w.model.H, w.model.R, w.model.m0, w.model.P0, w.y, smooth=False,
+                        loglik=True)["ll"]
+    rc = np.cumsum(ref)
+    bar = 1e-9 * np.cumsum(np.abs(ref))
+    dm = pks.to_device(w.model)
+    yd = torch.as_tensor(w.y).cuda()
+    m, P = pks.filter(dm, yd, "fp64")
+    cum, tot = pks.loglik(dm, yd, m, P, "fp64", cumulative=True)
+    steps, tot2 = pks.loglik(dm, yd, m, P, "fp64")
+    torch.cuda.synchronize()
+    cum, tot, steps = cum.cpu().numpy(), tot.cpu().numpy(), steps.cpu().numpy()
+    assert np.all(np.abs(cum - rc) <= bar)
+    assert abs(tot[0] - rc[-1]) <= bar[-1] and tot2.item() == tot[0] and cum[-1] == tot[0]
+    # the per-step output of the same call path, summed on the host, gives the
+    # partial sums (positions reach 4e8 here, so the factors themselves carry
+    # the FP64 moments' rounding; their bar is checked at T = 2^20)
+    assert np.all(np.abs(np.cumsum(steps) - cum) <= 1e-12 * np.cumsum(np.abs(steps)))

@@ -158,10 +158,113 @@ def test_tv_numeric_flag(pks, nx):
     assert not torch.isnan(m[:bad]).any() and torch.isnan(m[bad:]).all()
 
 
-def test_tv_rejected_by_batched_calls(pks):
+def _packed_tv(nx, ny, lengths, rng, per_sequence_prior):
+    """Packed time-varying sequences: each sequence's rows from its own random
+    model, rows concatenated like y; one prior per sequence or a shared one."""
+    parts = [wl.random_tv_model(nx, ny, max(L, 1), rng) for L in lengths]
+    ys = [wl.simulate_tv(mo, rng)[0][:L] for mo, L in zip(parts, lengths)]
+    cat = lambda f: np.concatenate([getattr(mo, f)[:L] for mo, L in zip(parts, lengths)])
+    if per_sequence_prior:
+        m0 = np.stack([mo.m0 for mo in parts])
+        P0 = np.stack([mo.P0 for mo in parts])
+    else:
+        m0, P0 = parts[0].m0, parts[0].P0
+    model = wl.Model(cat("F"), cat("Q"), cat("H"), cat("R"), m0, P0, cat("u"), cat("d"))
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    return model, np.concatenate(ys), offsets
+
+
+def _ref_packed(model, y, offsets, per_sequence_prior, precision):
+    yy = y if precision == "fp64" else y.astype(np.float32).astype(np.float64)
+    total, nx = y.shape[0], model.nx
+    out = {"m": np.empty((total, nx)), "P": np.empty((total, nx, nx)), "ms": np.empty((total, nx)),
+           "Ps": np.empty((total, nx, nx)), "ll": np.empty(total)}
+    for b in range(offsets.shape[0] - 1):
+        s_ = slice(int(offsets[b]), int(offsets[b + 1]))
+        if s_.stop == s_.start:
+            continue
+        m0 = model.m0[b] if per_sequence_prior else model.m0
+        P0 = model.P0[b] if per_sequence_prior else model.P0
+        r = oracle.kf_rts_tv(model.F[s_], model.Q[s_], model.H[s_], model.R[s_], m0, P0, yy[s_],
+                             u=model.u[s_], d=model.d[s_], loglik=True)
+        for k in out:
+            out[k][s_] = r[k]
+    return out
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 2), (6, 2)])
+@pytest.mark.parametrize("per_sequence_prior", [True, False])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tv_batched(pks, nx, ny, per_sequence_prior, precision):
+    """Packed time-varying sequences (lengths 0, 1, 2 and several tiles): every
+    sequence starts from its prior; filter, smoother and log-likelihood against
+    the oracle run on each sequence's own rows."""
+    rng = np.random.default_rng(60 + nx + (7 if per_sequence_prior else 0))
+    lengths = [300, 0, 1, 2, 700, 64, 65] if nx <= 4 else [120, 0, 1, 2, 90]
+    model, y, offsets = _packed_tv(nx, ny, lengths, rng, per_sequence_prior)
+    ref = _ref_packed(model, y, offsets, per_sequence_prior, precision)
+    dm = pks.to_device(model, per_sequence=per_sequence_prior, time_varying=True)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    yd = torch.as_tensor(y).to("cuda", dt)
+    od = torch.as_tensor(offsets).cuda()
+    m, P = pks.filter_batched(dm, od, yd, precision)
+    ms, Ps = pks.smooth_batched(dm, od, m, P, precision)
+    cum, tot = pks.loglik_batched(dm, od, yd, m, P, precision, cumulative=True)
+    torch.cuda.synchronize()
+    floor = "rms" if precision == "mixed" else "none"
+    for k, g in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps)):
+        e = wl.max_rel_err(g.double().cpu().numpy(), ref[k], floor)
+        print("tv batched", nx, per_sequence_prior, precision, k, "%.2e" % e, flush=True)
+        assert e <= TOL[precision], k
+    if precision == "fp64":
+        rc, rt = oracle.loglik_prefix(ref["ll"], offsets)
+        cum, tot = cum.cpu().numpy(), tot.cpu().numpy()
+        assert np.max(np.abs(cum - rc) / np.maximum(1.0, np.abs(rc))) <= 1e-9
+        assert np.max(np.abs(tot - rt) / np.maximum(1.0, np.abs(rt))) <= 1e-9
+
+
+def test_tv_batched_numeric_flag(pks):
+    """A failing step in sequence 2 of packed time-varying sequences: the flag
+    names sequence 2, its outputs are NaN from that step on, the others finite."""
+    rng = np.random.default_rng(8)
+    lengths = [200, 150, 300, 100]
+    model, y, offsets = _packed_tv(3, 2, lengths, rng, True)
+    bad = int(offsets[2]) + 40
+    model.R[bad] = -10.0 * np.eye(2)
+    dm = pks.to_device(model, per_sequence=True, time_varying=True)
+    ws = pks.workspace(3, 2, int(offsets[-1]), 4, "fp64", time_varying=True)
+    od = torch.as_tensor(offsets).cuda()
+    m, P = pks.filter_batched(dm, od, torch.as_tensor(y).cuda(), "fp64", ws=ws)
+    ok, first = pks.read_numeric_status(ws)
+    assert not ok and first == 2
+    assert torch.isnan(m[bad:offsets[3]]).all() and not torch.isnan(m[offsets[2]:bad]).any()
+    assert not torch.isnan(m[:offsets[2]]).any() and not torch.isnan(m[offsets[3]:]).any()
+
+
+def test_tv_equal_rows_batched_equals_time_invariant_batched(pks):
+    """Packed sequences whose rows all repeat one model, with one prior per
+    sequence: bitwise the batched time-invariant result (same kernels and
+    constants)."""
+    w = wl.workload(4, B=9, T=900)
+    mo = w.model.select(0)
+    per_seq = wl.Model(*[np.stack([getattr(mo, f)] * w.B) for f in ("F", "Q", "H", "R")],
+                       w.model.m0, w.model.P0)
+    rep = lambda a: np.broadcast_to(a, (w.total,) + a.shape).copy()
+    tv = wl.Model(rep(mo.F), rep(mo.Q), rep(mo.H), rep(mo.R), w.model.m0, w.model.P0)
+    od = torch.as_tensor(w.offsets).cuda()
+    yd = torch.as_tensor(w.y).cuda()
+    a = pks.filter_batched(pks.to_device(per_seq, per_sequence=True), od, yd, "fp64")
+    b = pks.filter_batched(pks.to_device(tv, per_sequence=True, time_varying=True), od, yd, "fp64")
+    sa = pks.smooth_batched(pks.to_device(per_seq, per_sequence=True), od, *a, "fp64")
+    sb = pks.smooth_batched(pks.to_device(tv, per_sequence=True, time_varying=True), od, *b, "fp64")
+    torch.cuda.synchronize()
+    for x, z in zip(a + sa, b + sb):
+        assert torch.equal(x, z)
+
+
+def test_tv_rejected_by_plans(pks):
     model = wl.random_tv_model(2, 1, 10, np.random.default_rng(1))
     dm = pks.to_device(model, time_varying=True)
-    od = torch.tensor([0, 10], dtype=torch.int64, device="cuda")
     y = torch.zeros(10, 1, dtype=torch.float64, device="cuda")
     with pytest.raises(ValueError):
-        pks.filter_batched(dm, od, y, "fp64")
+        pks.Plan(dm, y)
