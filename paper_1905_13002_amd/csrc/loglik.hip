@@ -270,16 +270,17 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_small(LLArgs a, int64_t ntile
 // ---------------------------------------------------------------------------
 // any size: one wavefront per step
 // ---------------------------------------------------------------------------
-// Makes one wave's LDS writes visible to its other lanes.
+// Makes one wave's LDS writes visible to its other lanes (LDS only: the
+// lanes exchange nothing through global memory here).
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __host__ __device__ inline int ll_wave_words(int nx, int ny) {
-    // P [nx][nx], T = G P [ny][nx], S [ny][ny], m [nx], r [ny]
-    return nx * nx + ny * nx + ny * ny + nx + ny;
+    // P [nx][nx], T = G P [ny][nx], S [ny][ny], m [nx], r [ny], G [ny][nx]
+    return nx * nx + ny * nx + ny * ny + nx + ny + ny * nx;
 }
 
 template <typename R, bool SEG>
@@ -292,6 +293,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
     double* S = T + ny * nx;
     double* m = S + ny * ny;
     double* r = m + nx;
+    double* G = r + ny;          // the step's G = H F, staged once per step
     const R* gm = static_cast<const R*>(a.m);
     const R* gP = static_cast<const R*>(a.P);
     const R* gy = static_cast<const R*>(a.y);
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
         const int b = SEG ? seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k, start)
                           : seq_between<false>(a.offsets, 0, 0, k, start);
         const double* cst = a.consts64 + a.cstride * b + k * a.sstride;
-        const double* G = cst + a.cG;
+        for (int i = lane; i < ny * nx; i += 64) G[i] = cst[a.cG + i];
         if (k == start) {
             const int64_t ps = a.per_sequence ? b : 0;
             for (int i = lane; i < n2; i += 64) P[i] = a.P0[ps * n2 + i];
@@ -314,11 +316,13 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
         for (int idx = lane; idx < ny * nx; idx += 64) {          // T = G P
             const int i = idx / nx, j = idx - i * nx;
             double v = 0.0;
+#pragma unroll 4
             for (int l = 0; l < nx; ++l) v += G[i * nx + l] * P[l * nx + j];
             T[idx] = v;
         }
         for (int i = lane; i < ny; i += 64) {                      // r = y - G m - e
             double v = (double)gy[k * ny + i] - cst[a.ce + i];
+#pragma unroll 4
             for (int l = 0; l < nx; ++l) v -= G[i * nx + l] * m[l];
             r[i] = v;
         }
@@ -327,6 +331,7 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
             const int i = idx / ny, i2 = idx - i * ny;
             if (i2 > i) continue;
             double v = 0.0;
+#pragma unroll 4
             for (int j = 0; j < nx; ++j) v += T[i * nx + j] * G[i2 * nx + j];
             S[idx] = cst[a.cS + idx] + v;
         }

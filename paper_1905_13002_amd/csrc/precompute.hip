@@ -381,11 +381,12 @@ struct SmallPre {
     }
 };
 
-// Makes one wave's LDS writes visible to its other lanes.
+// Makes one wave's LDS writes visible to its other lanes.  The fences cover
+// LDS only, so the wave does not wait here for its global stores.
 __device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Writes the constants of the wave's 64 models field by field: every lane
@@ -405,6 +406,17 @@ struct WaveWriter {
     __device__ __forceinline__ void emit(int off, const double (&v)[N], bool ok) const {
         static_assert(N <= MAXN, "field larger than the stage");
         const int lane = threadIdx.x & 63;
+        if (nvalid <= 8) {        // few models (a shared or small set): each lane stores its own
+            if (lane < nvalid) {
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const double x = ok ? v[i] : __builtin_nan("");
+                    d[(size_t)lane * cw + off + i] = x;
+                    if (f) f[(size_t)lane * cw + off + i] = (float)x;
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) stg[lane * (MAXN + 1) + i] = ok ? v[i] : __builtin_nan("");
         wave_sync_lds();
