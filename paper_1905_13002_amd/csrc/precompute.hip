@@ -393,8 +393,10 @@ __device__ __forceinline__ void wave_sync_lds() {
 // puts the n words of one field of its own model into an LDS stage, then the
 // wave stores them with consecutive lanes on consecutive words (runs of n
 // words per model) instead of one store per word that touches 64 models'
-// lines; in the mixed mode a float copy goes out alongside.  A model whose
-// factorisation failed writes NaN.  Every lane of the wave must call emit.
+// lines.  In the mixed mode the scans read the float copy, and from the
+// double copy only S (the rank-ny solves run in double), so only that field
+// is written twice.  A model whose factorisation failed writes NaN.  Every
+// lane of the wave must call emit.
 template <int MAXN>
 struct WaveWriter {
     double* stg;          // LDS [64][MAXN + 1]
@@ -402,16 +404,18 @@ struct WaveWriter {
     float* f;             // their float copy (mixed mode) or nullptr
     int cw;               // words per model
     int nvalid;           // models of this wave that exist
+    int s_off;            // offset of S (kept in double in the mixed mode too)
     template <int N>
     __device__ __forceinline__ void emit(int off, const double (&v)[N], bool ok) const {
         static_assert(N <= MAXN, "field larger than the stage");
         const int lane = threadIdx.x & 63;
+        const bool dbl = !f || off == s_off;
         if (nvalid <= 8) {        // few models (a shared or small set): each lane stores its own
             if (lane < nvalid) {
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const double x = ok ? v[i] : __builtin_nan("");
-                    d[(size_t)lane * cw + off + i] = x;
+                    if (dbl) d[(size_t)lane * cw + off + i] = x;
                     if (f) f[(size_t)lane * cw + off + i] = (float)x;
                 }
             }
@@ -425,7 +429,7 @@ struct WaveWriter {
             const int e = r * 64 + lane, bl = e / N, i = e - bl * N;
             if (bl < nvalid) {
                 const double x = stg[bl * (MAXN + 1) + i];
-                d[(size_t)bl * cw + off + i] = x;
+                if (dbl) d[(size_t)bl * cw + off + i] = x;
                 if (f) f[(size_t)bl * cw + off + i] = (float)x;
             }
         }
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(64) void k_precompute_small(PrecomputeArgs a, int n
     const ConstLayout CL = const_layout(NX, NY);
     const int nvalid = nmodels - b0 < 64 ? nmodels - b0 : 64;
     const WaveWriter<MAXN> out{stg, a.consts64 + (size_t)b0 * a.cw,
-                               a.mixed ? a.consts32 + (size_t)b0 * a.cw : nullptr, a.cw, nvalid};
+                               a.mixed ? a.consts32 + (size_t)b0 * a.cw : nullptr, a.cw, nvalid, CL.S};
     bool ok = true;
     if (a.what == 4 && part == 0) {
         double T1[nm], S[m2], Lc[m2], G[nm], e[NY];
