@@ -317,3 +317,20 @@ def test_loglik_cv_T2pow23(pks):
     # partial sums (positions reach 4e8 here, so the factors themselves carry
     # the FP64 moments' rounding; their bar is checked at T = 2^20)
     assert np.all(np.abs(np.cumsum(steps) - cum) <= 1e-12 * np.cumsum(np.abs(steps)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_loglik_batched_per_sequence_large_state(pks, precision):
+    """Per-sequence models through the one-wave kernel (nx = 6, ny = 5): each
+    step's G, S, e and, at a sequence start, the prior come from its own model."""
+    rng = np.random.default_rng(17)
+    B = 7
+    models = [wl.random_stable_model(6, 5, rng, radius=0.9, with_offsets=True) for _ in range(B)]
+    lengths = [130, 0, 1, 257, 40, 2, 90]
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 5)) for mo, L in zip(models, lengths)]
+    stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+    model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), stack("u"),
+                     stack("d"))
+    check_ll(pks, model, np.concatenate(ys), precision, offsets=offsets, per_sequence=True,
+             what="per-sequence 6x5")
