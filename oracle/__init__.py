@@ -12,6 +12,10 @@ with the HIP library (``paper_1905_13002_amd``) and imports nothing from it.
 * ``loglik=True`` adds the per-step factors log p(y_k | y_1:k-1) of the
   marginal likelihood (Section III-C); :func:`loglik_prefix` turns them into
   log p(y_1:k) and the per-sequence totals log p(y_1:n).
+* :func:`loglik_factors` evaluates the same factors from GIVEN filtered
+  moments, in extended precision (numpy ``longdouble``, 64-bit significand):
+  the definition of each factor written out, so that it can serve as the
+  reference for a likelihood computed from someone else's moments.
 * :mod:`oracle.elements` restates the paper's linear/Gaussian elements and
   associative operators (Lemmas 1-4) in numpy FP64, for operator-level checks.
 """
@@ -195,6 +199,75 @@ def loglik_prefix(ll, offsets=None):
             cum[k] = acc
         tot[b] = acc
     return cum, tot
+
+
+_LOG_2PI_LD = np.log(np.longdouble(2) * np.longdouble("3.14159265358979323846264338327950288"))
+
+
+def _chol_logdet_quad(S, r):
+    """Cholesky factor of every S[k] (unrolled over columns, vectorised over
+    k), returning log det S[k] and r[k]^T S[k]^-1 r[k]; NaN where a pivot is
+    not positive."""
+    n = S.shape[-1]
+    L = np.zeros_like(S)
+    z = np.zeros_like(r)
+    logdet = np.zeros(S.shape[0], dtype=S.dtype)
+    ok = np.ones(S.shape[0], dtype=bool)
+    for j in range(n):
+        d = S[:, j, j] - np.sum(L[:, j, :j] * L[:, j, :j], axis=1)
+        ok &= d > 0
+        ljj = np.sqrt(np.where(d > 0, d, np.longdouble(1)))
+        L[:, j, j] = ljj
+        for i in range(j + 1, n):
+            L[:, i, j] = (S[:, i, j] - np.sum(L[:, i, :j] * L[:, j, :j], axis=1)) / ljj
+        z[:, j] = (r[:, j] - np.sum(L[:, j, :j] * z[:, :j], axis=1)) / ljj
+        logdet += 2 * np.log(ljj)
+    quad = np.sum(z * z, axis=1)
+    nan = np.longdouble("nan")
+    return np.where(ok, logdet, nan), np.where(ok, quad, nan)
+
+
+def loglik_factors(F, Q, H, R, m0, P0, y, m, P, offsets=None, u=None, d=None, per_sequence=False):
+    """log p(y_k | y_1:k-1) of every step, from GIVEN filtered moments m, P.
+
+    Section III-C: each factor is the Gaussian density of y_k under the
+    one-step prediction of the filtered moments of step k-1 (of the prior
+    x_0 ~ N(m0, P0) at a sequence's first step):
+        m^-_k = F m_{k-1} + u,   P^-_k = F P_{k-1} F^T + Q,
+        log N(y_k; H m^-_k + d, H P^-_k H^T + R).
+    Evaluated in extended precision (numpy longdouble) from the float64 values
+    of the inputs, so the result is the factor of exactly those inputs, to
+    about 1e-18 relative of its terms: where the residual y_k - H m^-_k - d is a
+    small difference of large numbers (positions of 1e7) a float64 evaluation
+    loses about seven digits of it.  Returns float64 [total].
+    Sequences as in kf_rts_batched (offsets [B+1], per-sequence models when
+    ``per_sequence``)."""
+    ld = np.longdouble
+    y = np.asarray(y)
+    total = y.shape[0]
+    if offsets is None:
+        offsets = np.array([0, total], dtype=np.int64)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    out = np.empty(total)
+    for b in range(offsets.shape[0] - 1):
+        s, e = int(offsets[b]), int(offsets[b + 1])
+        if e <= s:
+            continue
+        pick = (lambda a: a[b]) if per_sequence else (lambda a: a)
+        Fb, Qb, Hb, Rb = (np.asarray(pick(a), dtype=np.float64).astype(ld) for a in (F, Q, H, R))
+        m0b, P0b = (np.asarray(pick(a), dtype=np.float64).astype(ld) for a in (m0, P0))
+        nx, ny = Fb.shape[0], Hb.shape[0]
+        ub = np.zeros(nx, dtype=ld) if u is None else np.asarray(pick(u), dtype=np.float64).astype(ld)
+        db = np.zeros(ny, dtype=ld) if d is None else np.asarray(pick(d), dtype=np.float64).astype(ld)
+        mprev = np.concatenate([m0b[None], np.asarray(m[s:e - 1], dtype=np.float64).astype(ld)])
+        Pprev = np.concatenate([P0b[None], np.asarray(P[s:e - 1], dtype=np.float64).astype(ld)])
+        mp = mprev @ Fb.T + ub
+        Pp = Fb @ Pprev @ Fb.T + Qb
+        S = Hb @ Pp @ Hb.T + Rb
+        r = np.asarray(y[s:e], dtype=np.float64).astype(ld) - mp @ Hb.T - db
+        logdet, quad = _chol_logdet_quad(S, r)
+        out[s:e] = (-(ny * _LOG_2PI_LD + logdet + quad) / 2).astype(np.float64)
+    return out
 
 
 if __name__ == "__main__":  # pragma: no cover

@@ -497,6 +497,90 @@ def test_oracle_loglik_batched_restarts_per_sequence():
         assert tot[b] == cum[offsets[b + 1] - 1]
 
 
+
+def test_loglik_factors_from_oracle_moments_match_dense_joint_density():
+    """The extended-precision factors, fed the oracle's own filtered moments,
+    sum to the dense Gaussian log-density of y_1..y_k (chain rule), for models
+    with u, d, singular Q and several sequences with their own models."""
+    rng = np.random.default_rng(31)
+    for nx, ny, T, singQ in ((1, 1, 9, False), (3, 2, 17, True), (4, 4, 12, False), (2, 3, 20, False)):
+        model = wl.random_small_model(nx, ny, rng, singular_Q=singQ)
+        model = wl.Model(model.F, model.Q, model.H, model.R, model.m0, model.P0,
+                         rng.standard_normal(nx), rng.standard_normal(ny))
+        y, _ = wl.simulate(model, T, rng)
+        out = run(model, y)
+        f = oracle.loglik_factors(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, out["m"], out["P"],
+                                  u=model.u, d=model.d)
+        ref = joint_loglik(model.F, model.Q, model.H, model.R, model.m0, model.P0, y, model.u, model.d)
+        assert np.max(np.abs(np.cumsum(f) - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
+    # per-sequence models: each sequence restarts from its own prior
+    lens = [5, 0, 1, 9]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    models = [wl.random_small_model(3, 2, rng) for _ in lens]
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 2)) for mo, L in zip(models, lens)]
+    stack = lambda a: np.stack([getattr(mo, a) for mo in models])
+    y = np.concatenate(ys)
+    out = oracle.kf_rts_batched(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), y,
+                                offsets, per_sequence=True, smooth=False, threads=2)
+    f = oracle.loglik_factors(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), y,
+                              out["m"], out["P"], offsets=offsets, per_sequence=True)
+    for b, mo in enumerate(models):
+        if lens[b]:
+            sl = slice(offsets[b], offsets[b + 1])
+            ref = joint_loglik(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, ys[b])
+            assert np.max(np.abs(np.cumsum(f[sl]) - ref) / np.maximum(1.0, np.abs(ref))) < 1e-10
+
+
+def test_loglik_factors_scalar_closed_form_at_large_state():
+    """nx = ny = 1 with a filtered mean of 1e7 and a residual of order one: the
+    factor log N(y; h (f m + u) + d, h^2 (f^2 p + q) + r) evaluated in exact
+    rational arithmetic (fractions of the float64 inputs), then rounded.  A
+    float64 evaluation of the residual would lose about seven digits here."""
+    from fractions import Fraction as Fr
+    import math
+    f, q, h, r, u, d = 1.0, 1e-3, 1.0 + 2.0 ** -30, 0.25, 0.125, -0.375
+    m_prev = np.array([[12345678.123456789]])
+    p_prev = np.array([[[0.0625]]])
+    mu = h * (f * m_prev[0, 0] + u) + d
+    y = np.array([[mu + 0.731]])
+    one = lambda v: np.array([[v]])
+    # the first step uses the prior: make the prior the given moments
+    got = oracle.loglik_factors(one(f), one(q), one(h), one(r), m_prev[0], p_prev[0], y,
+                                np.zeros((1, 1)), np.zeros((1, 1, 1)), u=np.array([u]), d=np.array([d]))[0]
+    F_, H_, m_ = Fr(f), Fr(h), Fr(m_prev[0, 0])
+    res = Fr(y[0, 0]) - (H_ * (F_ * m_ + Fr(u)) + Fr(d))
+    var = H_ * H_ * (F_ * F_ * Fr(p_prev[0, 0, 0]) + Fr(q)) + Fr(r)
+    ref = -0.5 * (math.log(2 * math.pi) + math.log(float(var)) + float(res * res / var))
+    # bar: the extended format's rounding (2^-64) of terms of size |h f m|,
+    # through the gradient v = res / var, plus a float64 rounding of the result
+    ext = 16 * 2.0 ** -64 * abs(float(res / var)) * abs(h * f * m_prev[0, 0])
+    assert abs(got - ref) <= ext + 4e-16 * abs(ref)
+    # and a plain float64 residual really is off at this size (what the
+    # extended evaluation is for): its error is well above that bar
+    naive = y[0, 0] - (h * (f * m_prev[0, 0] + u) + d)
+    assert abs(naive - float(res)) * abs(float(1 / var)) > 10 * ext
+
+
+def test_loglik_factors_detect_a_planted_offset():
+    """A shift of one filtered mean by 1e-9 of its size changes exactly the
+    next factor, by the first-order amount (G^T v) . dm."""
+    w = wl.workload(1, T=200)
+    mo = w.model
+    out = run(mo, w.y)
+    f0 = oracle.loglik_factors(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y, out["m"], out["P"])
+    m1 = out["m"].copy()
+    dm = 1e-9 * np.abs(m1[120]) + 1e-12
+    m1[120] += dm
+    f1 = oracle.loglik_factors(mo.F, mo.Q, mo.H, mo.R, mo.m0, mo.P0, w.y, m1, out["P"])
+    changed = np.nonzero(f1 != f0)[0]
+    assert list(changed) == [121]
+    G = mo.H @ mo.F
+    S = G @ out["P"][120] @ G.T + mo.H @ mo.Q @ mo.H.T + mo.R
+    r = w.y[121] - G @ out["m"][120]
+    v = np.linalg.solve(S, r)
+    assert abs((f1[121] - f0[121]) - v @ (G @ dm)) <= 1e-6 * abs(v @ (G @ dm))
+
+
 # ---------------------------------------------------------------------------
 # time-varying models (Section IV's general model, one row per step)
 # ---------------------------------------------------------------------------
