@@ -94,7 +94,8 @@ def ll_kernel_model(nx, ny, rs):
     return {"k_ll_steps": k, "k_ll_block_scan": dict(bytes=16, flops=1), "k_ll_fixup": dict(bytes=16, flops=1)}
 
 
-KERNEL_SOURCES = ["paper_1905_13002_amd/csrc/small_ops.hpp", "paper_1905_13002_amd/csrc/scan_small_impl.hpp"]
+KERNEL_SOURCES = ["paper_1905_13002_amd/csrc/small_ops.hpp", "paper_1905_13002_amd/csrc/scan_small_impl.hpp",
+                  "paper_1905_13002_amd/csrc/precompute.hip"]
 
 
 def sources_sha():
@@ -121,6 +122,25 @@ def measured_traffic(workload_name, precision, kernel):
     if not ent:
         return None
     return ent.get("hbm_bytes_per_launch")
+
+
+def measured_pass_traffic(workload_name, precision):
+    """HBM bytes of one whole pass (every kernel's counter bytes per launch,
+    summed) from the committed counter summary, if it was taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload_name)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("sources_sha") != sources_sha():
+        return None
+    ks = [v for k, v in rec.get("kernels", {}).items() if k.startswith(precision + "/")]
+    if not ks:
+        return None
+    return int(sum(v.get("hbm_bytes_per_launch", 0) for v in ks))
 
 
 # rocprofv3 runs that the committed kernel profile of the default workload
@@ -422,8 +442,40 @@ def main():
                   algorithmic_bytes_per_launch=km["bytes"] * T, algorithmic_flops_per_launch=km["flops"] * T)
         return dom, per_launch, rl
 
-    dom64, kern64, rl64 = roofline("fp64")
-    domm, kernm, rlm = roofline("mixed")
+    def pass_roofline(prec, sec, dom_rl):
+        """The whole pass against its binding roofline: the method's own
+        traffic, ny + 3 (nx + nx^2) words per step (y in; filtered moments out;
+        filtered moments in; smoothed moments out; plus the per-step model rows
+        of a time-varying model), over the measured time per pass.  The
+        dominant kernel's own roofline is reported beside it."""
+        rs = 8 if prec == "fp64" else 4
+        f = op_flops(nx, ny)
+        bytes_step = (ny + 3 * (nx + nx * nx)) * rs
+        if tv:
+            bytes_step += (2 * nx * nx + nx + ny * nx + ny + ny * ny) * 8
+        flops_step = (f["f_full"] + f["f_carry"] + 2 * f["f_elem"] + 2 * f["s_elem"] + f["s_full"]
+                      + f["s_carry"])
+        peak_f = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+        t_mem = bytes_step * T / (HBM_PEAK_GBS * 1e9)
+        t_alu = flops_step * T / (peak_f * 1e12)
+        tr = measured_pass_traffic(w.name, prec)
+        if t_mem >= t_alu:
+            ach = bytes_step * T / sec / 1e9
+            rl = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(ach / HBM_PEAK_GBS, 4), traffic=tr)
+        else:
+            ach = flops_step * T / sec / 1e12
+            rl = dict(bound="alu", achieved=round(ach, 3), peak=peak_f, unit="TFLOP/s",
+                      frac=round(ach / peak_f, 4), traffic=tr)
+        rl.update(scope="whole pass (all kernels of one filter + smoother pass)",
+                  algorithmic_bytes_per_step=bytes_step, algorithmic_flops_per_step=round(flops_step, 1),
+                  dominant_kernel=dom_rl)
+        return rl
+
+    dom64, kern64, rl64k = roofline("fp64")
+    domm, kernm, rlmk = roofline("mixed")
+    rl64 = pass_roofline("fp64", results["fp64"]["sec"], rl64k)
+    rlm = pass_roofline("mixed", results["mixed"]["sec"], rlmk)
 
     # CPU baseline: the oracle as it stands, one host thread, on the same workload
     cpu = None

@@ -78,6 +78,34 @@ struct LLArgs {
     const int* tile_seq;           // [tiles + 1] sequence of each tile's first step (batched)
 };
 
+// Residual y_k - G m - e with a compensated sum: every product and every
+// addition keeps its rounding error (error-free transformations: the product's
+// error from an FMA, the sum's by Knuth's TwoSum), and the errors are added at
+// the end (the Dot2 scheme of Ogita, Rump and Oishi, "Accurate sum and dot
+// product", SIAM J. Sci. Comput. 2005).  The result is as accurate as if it
+// were computed in twice the working precision and then rounded.  Where the
+// state is large (positions of 1e7 in the constant-velocity workload) the
+// residual is a small difference of large numbers, and the plain sum would
+// lose about seven digits of it.
+struct Acc2 {
+    double s, c;
+};
+__device__ __forceinline__ void acc2_add(Acc2& a, double x) {
+#pragma clang fp contract(off)
+    const double t = a.s + x;
+    const double z = t - a.s;
+    a.c += (a.s - (t - z)) + (x - z);
+    a.s = t;
+}
+__device__ __forceinline__ void acc2_sub_prod(Acc2& a, double g, double x) {
+#pragma clang fp contract(off)
+    const double p = g * x;
+    const double e = fma(g, x, -p);     // g x = p + e exactly
+    acc2_add(a, -p);
+    a.c -= e;
+}
+__device__ __forceinline__ double acc2_value(const Acc2& a) { return a.s + a.c; }
+
 // sequence index and first step of step k (k < total)
 template <bool SEG>
 __device__ __forceinline__ int seq_of(const int64_t* off, int B, int64_t k, int64_t& start) {
@@ -152,10 +180,11 @@ __device__ __forceinline__ void ll_step_small(const LLArgs& a, int64_t k, int b,
     const R* yk = static_cast<const R*>(a.y) + k * NY;
 #pragma unroll
     for (int i = 0; i < NY; ++i) {
-        double v = (double)yk[i] - cst[a.ce + i];
+        Acc2 v{(double)yk[i], 0.0};
+        acc2_add(v, -cst[a.ce + i]);
 #pragma unroll
-        for (int l = 0; l < NX; ++l) v -= G[i * NX + l] * m[l];
-        r[i] = v;
+        for (int l = 0; l < NX; ++l) acc2_sub_prod(v, G[i * NX + l], m[l]);
+        r[i] = acc2_value(v);
     }
     // S += G P G^T (lower triangle; the Cholesky factorisation reads only it)
     double T[NY * NX];
@@ -321,10 +350,11 @@ __global__ __launch_bounds__(kLLThreads) void k_ll_wave(LLArgs a) {
             T[idx] = v;
         }
         for (int i = lane; i < ny; i += 64) {                      // r = y - G m - e
-            double v = (double)gy[k * ny + i] - cst[a.ce + i];
+            Acc2 v{(double)gy[k * ny + i], 0.0};
+            acc2_add(v, -cst[a.ce + i]);
 #pragma unroll 4
-            for (int l = 0; l < nx; ++l) v -= G[i * nx + l] * m[l];
-            r[i] = v;
+            for (int l = 0; l < nx; ++l) acc2_sub_prod(v, G[i * nx + l], m[l]);
+            r[i] = acc2_value(v);
         }
         wave_sync();
         for (int idx = lane; idx < ny * ny; idx += 64) {          // S = S0 + T G^T (lower)
@@ -463,8 +493,8 @@ __global__ __launch_bounds__(kScanThreads) void k_ll_block_scan(LLScanArgs a) {
         double v = 0.0;
         int h = 0;
         if (k < a.total) {
-            while (SEG && k >= end) {        // next non-empty sequence
-                ++b;
+            while (SEG && k >= end && b < a.B - 1) {   // next non-empty sequence (offsets
+                ++b;                                     // past total stay in the last one)
                 start = end;
                 end = a.offsets[b + 1];
             }
@@ -507,9 +537,10 @@ __global__ __launch_bounds__(kTopThreads) void k_ll_top(LLScanArgs a) {
     if (!a.tot) return;
     __syncthreads();                         // carries written by this workgroup
     for (int b = t; b < a.B; b += kTopThreads) {
-        const int64_t s = SEG ? a.offsets[b] : 0, e = SEG ? a.offsets[b + 1] : a.total;
+        const int64_t s = SEG ? a.offsets[b] : 0;
+        const int64_t e = SEG ? min(a.offsets[b + 1], a.total) : a.total;   // offsets past total: clamped
         double v = 0.0;
-        if (e > s) {
+        if (e > s && e > 0) {
             const int64_t k = e - 1, c = k / kLLBlock;
             v = a.cum[k];
             if (s < c * kLLBlock) v += a.carry[c];
