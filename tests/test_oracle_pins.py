@@ -635,3 +635,158 @@ def test_irregular_cv_model_constants():
         assert np.allclose(w.model.F[k], ref.F, rtol=0, atol=0)
         assert np.allclose(w.model.Q[k], ref.Q, rtol=1e-15, atol=0)
     assert np.all((dts >= 0.05) & (dts <= 0.15))
+
+
+# ---------------------------------------------------------------------------
+# discrete-state hidden Markov model (the framework with the counting measure)
+# ---------------------------------------------------------------------------
+from oracle import hmm_elements as hel  # noqa: E402
+
+
+def _random_hmm(K, T, rng, sparse=False):
+    Pi = rng.random((K, K)) + 0.05
+    if sparse:
+        Pi *= rng.random((K, K)) < 0.5
+        Pi[np.arange(K), np.arange(K)] += 0.1        # every row keeps a way out
+    Pi /= Pi.sum(axis=1, keepdims=True)
+    p0 = rng.random(K) + 0.1
+    p0 /= p0.sum()
+    L = rng.normal(0.0, 1.5, size=(T, K))
+    return Pi, p0, L
+
+
+def _hmm_brute_force(Pi, p0, L):
+    """Sum over every state path x_0..x_T of p0[x_0] prod Pi[x_{k-1}][x_k]
+    exp(L[k-1][x_k]): filtered and smoothed marginals and log p(y_1:k)."""
+    import itertools
+    K = Pi.shape[0]
+    T = L.shape[0]
+    alpha = np.zeros((T, K))
+    gamma = np.zeros((T, K))
+    logp = np.zeros(T)
+    for k in range(1, T + 1):                        # data y_1..y_k
+        acc = np.zeros(K)
+        tot = 0.0
+        for path in itertools.product(range(K), repeat=k + 1):
+            w = p0[path[0]]
+            for t in range(1, k + 1):
+                w *= Pi[path[t - 1], path[t]] * np.exp(L[t - 1, path[t]])
+            acc[path[k]] += w
+            tot += w
+            if k == T:
+                for t in range(1, T + 1):
+                    gamma[t - 1, path[t]] += w
+        alpha[k - 1] = acc / tot
+        logp[k - 1] = np.log(tot)
+        if k == T:
+            gamma /= tot
+    return alpha, gamma, logp
+
+
+@pytest.mark.parametrize("K,T,sparse", [(2, 1, False), (2, 4, False), (3, 5, False), (3, 4, True), (4, 3, False)])
+def test_hmm_oracle_matches_brute_force(K, T, sparse):
+    rng = np.random.default_rng(70 + 10 * K + T)
+    Pi, p0, L = _random_hmm(K, T, rng, sparse)
+    out = oracle.hmm_fb(Pi, p0, L)
+    a, g, lp = _hmm_brute_force(Pi, p0, L)
+    assert np.max(np.abs(out["alpha"] - a)) < 1e-13
+    assert np.max(np.abs(out["gamma"] - g)) < 1e-13
+    assert np.max(np.abs(np.cumsum(out["ll"]) - lp)) < 1e-12 * max(1.0, np.max(np.abs(lp)))
+
+
+def test_hmm_oracle_two_state_by_hand():
+    """Two states, two steps, numbers worked by hand:
+    pred_1 = p0 Pi = (0.55, 0.45); u_1 = pred_1 * (0.3, 0.6) = (0.165, 0.27),
+    p(y_1) = 0.435; pred_2 = alpha_1 Pi; gamma_1 from the backward equation."""
+    Pi = np.array([[0.9, 0.1], [0.2, 0.8]])
+    p0 = np.array([0.5, 0.5])
+    lik = np.array([[0.3, 0.6], [0.5, 0.1]])
+    out = oracle.hmm_fb(Pi, p0, np.log(lik))
+    a1 = np.array([0.165, 0.27]) / 0.435
+    assert np.allclose(out["alpha"][0], a1, rtol=0, atol=1e-15)
+    assert abs(out["ll"][0] - np.log(0.435)) < 1e-15
+    pred2 = np.array([a1[0] * 0.9 + a1[1] * 0.2, a1[0] * 0.1 + a1[1] * 0.8])
+    u2 = pred2 * lik[1]
+    a2 = u2 / u2.sum()
+    assert np.allclose(out["alpha"][1], a2, rtol=0, atol=1e-15)
+    assert abs(out["ll"][1] - np.log(u2.sum())) < 1e-15
+    g1 = a1 * np.array([0.9 * a2[0] / pred2[0] + 0.1 * a2[1] / pred2[1],
+                        0.2 * a2[0] / pred2[0] + 0.8 * a2[1] / pred2[1]])
+    assert np.allclose(out["gamma"][0], g1, rtol=0, atol=1e-15)
+    assert np.array_equal(out["gamma"][1], out["alpha"][1])
+
+
+def test_hmm_oracle_deterministic_cycle():
+    """A cyclic permutation Pi[i][(i+1) % K] = 1 with x_0 = 0 known: x_k = k mod K
+    whatever the measurements, so filtered = smoothed = that indicator and
+    log p(y_1:T) = sum_k L[k-1][k mod K].  A transposed Pi would run the cycle
+    backwards."""
+    K, T = 5, 23
+    Pi = np.roll(np.eye(K), 1, axis=1)
+    p0 = np.eye(K)[0]
+    L = np.random.default_rng(3).normal(size=(T, K))
+    out = oracle.hmm_fb(Pi, p0, L)
+    ind = np.eye(K)[np.arange(1, T + 1) % K]
+    assert np.array_equal(out["alpha"], ind) and np.array_equal(out["gamma"], ind)
+    assert abs(out["ll"].sum() - L[np.arange(T), np.arange(1, T + 1) % K].sum()) < 1e-12
+
+
+def test_hmm_oracle_invariants():
+    """Marginals sum to one, gamma_T = alpha_T bitwise, and a constant added to
+    one step's log-likelihoods moves only that step's factor, by the constant."""
+    rng = np.random.default_rng(12)
+    Pi, p0, L = _random_hmm(6, 300, rng, sparse=True)
+    out = oracle.hmm_fb(Pi, p0, L)
+    assert np.max(np.abs(out["alpha"].sum(axis=1) - 1)) < 1e-14
+    assert np.max(np.abs(out["gamma"].sum(axis=1) - 1)) < 1e-13
+    assert np.array_equal(out["gamma"][-1], out["alpha"][-1])
+    L2 = L.copy()
+    L2[100] += 7.25
+    out2 = oracle.hmm_fb(Pi, p0, L2)
+    d = out2["ll"] - out["ll"]
+    assert abs(d[100] - 7.25) < 1e-13 and np.max(np.abs(np.delete(d, 100))) < 1e-13
+    assert np.max(np.abs(out2["alpha"] - out["alpha"])) < 1e-14
+    assert np.max(np.abs(out2["gamma"] - out["gamma"])) < 1e-14
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_hmm_elements_fold_equals_forward_backward(sparse):
+    """Theorems 1-2 with sums: the left fold of the filtering elements under
+    Definition 1 gives the filtered marginals and log p(y_1:k); the right fold
+    of the smoothing elements under Definition 2 the smoothed marginals."""
+    rng = np.random.default_rng(5 if sparse else 6)
+    Pi, p0, L = _random_hmm(5, 40, rng, sparse)
+    out = oracle.hmm_fb(Pi, p0, L)
+    f, g = hel.filter_elements(Pi, p0, L)
+    alpha, logp = hel.filter_prefix_fold(f, g)
+    assert np.max(np.abs(alpha - out["alpha"])) < 1e-13
+    assert np.max(np.abs(logp - np.cumsum(out["ll"]))) < 1e-11
+    a = hel.smoother_elements(Pi, out["alpha"])
+    gamma = hel.smoother_suffix_fold(a)
+    assert np.max(np.abs(gamma - out["gamma"])) < 1e-13
+
+
+def test_hmm_operators_associative_with_identity_and_any_bracketing():
+    rng = np.random.default_rng(8)
+    Pi, p0, L = _random_hmm(4, 9, rng)
+    f, g = hel.filter_elements(Pi, p0, L)
+    e = hel.filter_identity(4)
+    for i in range(1, 7):
+        x, y, z = (f[i], g[i]), (f[i + 1], g[i + 1]), (f[i + 2], g[i + 2])
+        l = hel.filter_combine(*hel.filter_combine(*x, *y), *z)
+        r = hel.filter_combine(*x, *hel.filter_combine(*y, *z))
+        assert np.max(np.abs(l[0] - r[0])) < 1e-14 and np.max(np.abs(l[1] / r[1] - 1)) < 1e-14
+        for a_, b_ in (hel.filter_combine(*x, *e), hel.filter_combine(*e, *x)):
+            assert np.max(np.abs(a_ - x[0])) < 1e-15 and np.max(np.abs(b_ / x[1] - 1)) < 1e-15
+    # a balanced tree gives the sequential result
+    pairs = [(f[k], g[k]) for k in range(8)]
+    while len(pairs) > 1:
+        pairs = [hel.filter_combine(*pairs[2 * i], *pairs[2 * i + 1]) for i in range(len(pairs) // 2)]
+    out = oracle.hmm_fb(Pi, p0, L[:8])
+    assert np.max(np.abs(pairs[0][0][0] - out["alpha"][7])) < 1e-14
+    assert abs(np.log(pairs[0][1][0]) - out["ll"].sum()) < 1e-12
+    a = hel.smoother_elements(Pi, oracle.hmm_fb(Pi, p0, L)["alpha"])
+    for i in range(6):
+        l = hel.smoother_combine(hel.smoother_combine(a[i], a[i + 1]), a[i + 2])
+        r = hel.smoother_combine(a[i], hel.smoother_combine(a[i + 1], a[i + 2]))
+        assert np.max(np.abs(l - r)) < 1e-15
