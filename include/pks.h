@@ -262,6 +262,43 @@ pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_pr
 pks_status pks_read_numeric_status(void *ws, int32_t *first_bad_sequence, void *stream);
 
 /*
+ * Discrete-state hidden Markov model: the same parallel filter and smoother
+ * with a finite state space, where the integrals of Definitions 1 and 2
+ * become sums over the states (the paper's concluding section notes that the
+ * framework holds with the counting measure).  Model:
+ *     x_0 ~ p0,  p(x_k = j | x_{k-1} = i) = Pi[i][j],  p(y_k | x_k = j) = exp(L[k-1][j]),
+ * with the emission log-likelihoods L [T][K] supplied by the caller (any
+ * emission model).  Theorem 1: the prefix a_1 (x) ... (x) a_k carries the
+ * filtered marginal alpha_k = p(x_k | y_1:k) and p(y_1:k); Theorem 2: the
+ * suffix a_k (x) ... (x) a_T carries the smoothed marginal gamma_k =
+ * p(x_k | y_1:T).  FP64 throughout.
+ *   K      number of states, 1..64
+ *   Pi     DEVICE double [K][K], rows summing to one
+ *   p0     DEVICE double [K], the distribution of x_0 (the first data are y_1)
+ *   L      DEVICE double [T][K]; rows may hold -inf (impossible states); a
+ *          step whose data are impossible under the model gives NaN
+ *   alpha  DEVICE double [T][K] out (filter) / in (smoother)
+ *   logp   DEVICE double [T] out or NULL: log p(y_1:k), the g-part of the prefix
+ *   gamma  DEVICE double [T][K] out
+ * Workspace: pks_hmm_workspace_bytes(K, T) bytes (0 for invalid sizes).
+ * Outputs must not overlap the inputs or each other.  A row of Pi with no
+ * way into a state that the filter reaches is fine; a smoothed marginal puts
+ * no weight on states the filter cannot reach.
+ */
+typedef struct {
+    int32_t K;
+    const double *Pi;
+    const double *p0;
+} pks_hmm;
+size_t pks_hmm_workspace_bytes(int32_t K, int64_t T);
+pks_status pks_hmm_filter(const pks_hmm *model, int64_t T, const double *L, double *alpha, double *logp,
+                          void *ws, size_t ws_bytes, void *stream);
+pks_status pks_hmm_smooth(const pks_hmm *model, int64_t T, const double *alpha, double *gamma, void *ws,
+                          size_t ws_bytes, void *stream);
+pks_status pks_hmm_filter_smooth(const pks_hmm *model, int64_t T, const double *L, double *alpha,
+                                 double *logp, double *gamma, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Diagnostics: per-kernel timing.  After pks_profile_start(), every call made
  * by this thread brackets each kernel it launches with HIP events recorded on
  * the launch stream.  pks_profile_stop() synchronises the device, stops the

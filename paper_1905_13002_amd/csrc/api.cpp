@@ -503,6 +503,57 @@ pks_status pks_loglik_tv(const pks_model_tv* model, int64_t T, const void* y, co
                        (hipStream_t)stream, true);
 }
 
+// ---- discrete-state hidden Markov model --------------------------------------
+namespace {
+pks_status hmm_impl(const pks_hmm* model, int64_t T, const double* L, double* alpha, double* logp,
+                    double* gamma, void* ws, size_t ws_bytes, int passes, hipStream_t s) {
+    if (!model) return fail(PKS_E_ARG, "model is NULL");
+    if (model->K < 1 || model->K > 64) return fail(PKS_E_ARG, "K = %d outside [1, 64]", model->K);
+    if (!model->Pi || !model->p0) return fail(PKS_E_ARG, "Pi and p0 are required");
+    if (T < 0) return fail(PKS_E_ARG, "negative number of steps");
+    if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
+    const size_t need = hmm_ws_bytes(model->K, T);
+    if (ws_bytes < need)
+        return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes, need);
+    if (T == 0) return PKS_OK;
+    const size_t bK = (size_t)T * model->K * sizeof(double), bT = (size_t)T * sizeof(double);
+    if ((passes & 1) && (!L || !alpha)) return fail(PKS_E_ARG, "L and alpha must not be NULL");
+    if ((passes & 2) && (!alpha || !gamma)) return fail(PKS_E_ARG, "alpha and gamma must not be NULL");
+    if ((passes & 1) && (overlaps(L, bK, alpha, bK) || overlaps(L, bK, logp, bT) || overlaps(alpha, bK, logp, bT)))
+        return fail(PKS_E_ARG, "filter outputs overlap the input or each other");
+    if ((passes & 2) && (overlaps(gamma, bK, alpha, bK) || overlaps(gamma, bK, logp, bT) ||
+                         ((passes & 1) && overlaps(gamma, bK, L, bK))))
+        return fail(PKS_E_ARG, "smoother output overlaps the inputs or the other outputs");
+    const hipError_t e = launch_hmm(model->K, T, model->Pi, model->p0, L, alpha, logp, gamma, ws, passes, s);
+    if (e != hipSuccess) return hip_fail(e, "HMM kernels");
+    return PKS_OK;
+}
+}  // namespace
+
+size_t pks_hmm_workspace_bytes(int32_t K, int64_t T) {
+    if (K < 1 || K > 64 || T < 0) return 0;
+    return hmm_ws_bytes(K, T);
+}
+
+pks_status pks_hmm_filter(const pks_hmm* model, int64_t T, const double* L, double* alpha, double* logp, void* ws,
+                          size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return hmm_impl(model, T, L, alpha, logp, nullptr, ws, ws_bytes, 1, (hipStream_t)stream);
+}
+
+pks_status pks_hmm_smooth(const pks_hmm* model, int64_t T, const double* alpha, double* gamma, void* ws,
+                          size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return hmm_impl(model, T, nullptr, const_cast<double*>(alpha), nullptr, gamma, ws, ws_bytes, 2,
+                    (hipStream_t)stream);
+}
+
+pks_status pks_hmm_filter_smooth(const pks_hmm* model, int64_t T, const double* L, double* alpha, double* logp,
+                                 double* gamma, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    return hmm_impl(model, T, L, alpha, logp, gamma, ws, ws_bytes, 3, (hipStream_t)stream);
+}
+
 pks_status pks_read_numeric_status(void* ws, int32_t* first_bad_sequence, void* stream) {
     g_last_error.clear();
     if (!ws) return fail(PKS_E_ARG, "workspace is NULL");

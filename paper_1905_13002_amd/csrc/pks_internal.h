@@ -169,6 +169,14 @@ hipError_t launch_loglik(const pks_model& model, int32_t B, const int64_t* offse
                          bool cumulative, bool mixed, void* ws, const WsLayout& L, hipStream_t s,
                          bool tv = false);
 
+// discrete-state hidden Markov model (hmm.hip), 1 <= K <= 64 states
+int hmm_padded_states(int K);
+int64_t hmm_block_len(int K, int64_t T);
+size_t hmm_ws_bytes(int K, int64_t T);
+// passes: 1 = filter (alpha, logp), 2 = smoother (gamma from alpha), 3 = both
+hipError_t launch_hmm(int K, int64_t T, const double* Pi, const double* p0, const double* L, double* alpha,
+                      double* logp, double* gamma, void* ws, int passes, hipStream_t st);
+
 // large-state path (scan_large.hip), 5 <= nx <= 64
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);

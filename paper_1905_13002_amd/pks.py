@@ -28,7 +28,8 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_plan_destroy", "pks_autotune", "pks_read_numeric_status", "pks_last_error",
             "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched",
             "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv",
-            "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched"]
+            "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched",
+            "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth"]
 
 
 class PksError(RuntimeError):
@@ -43,6 +44,10 @@ class pks_model(ctypes.Structure):
                 ("H", ctypes.c_void_p), ("d", ctypes.c_void_p), ("R", ctypes.c_void_p),
                 ("m0", ctypes.c_void_p), ("P0", ctypes.c_void_p),
                 ("per_sequence", ctypes.c_int32)]
+
+
+class pks_hmm(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Pi", ctypes.c_void_p), ("p0", ctypes.c_void_p)]
 
 
 class pks_model_tv(ctypes.Structure):
@@ -60,7 +65,12 @@ def _load():
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     mp = ctypes.POINTER(pks_model)
     mt = ctypes.POINTER(pks_model_tv)
+    hp = ctypes.POINTER(pks_hmm)
     sig = {
+        "pks_hmm_workspace_bytes": (sz, [i32, i64]),
+        "pks_hmm_filter": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, sz, vp]),
+        "pks_hmm_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, sz, vp]),
+        "pks_hmm_filter_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, vp, sz, vp]),
         "pks_workspace_bytes_tv": (sz, [i32, i32, i64, ctypes.c_int]),
         "pks_filter_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_smooth_tv": (ctypes.c_int, [mt, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
@@ -380,6 +390,73 @@ def profile_stop(max_kernels: int = 64):
         nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (float(tot[i]), int(cnt[i]))
     return out
+
+
+# ---------------------------------------------------------------------------
+# discrete-state hidden Markov model
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceHmm:
+    """Transition matrix Pi [K,K] and prior p0 [K] as float64 device tensors."""
+    Pi: torch.Tensor
+    p0: torch.Tensor
+
+    @property
+    def K(self):
+        return self.Pi.shape[-1]
+
+    def struct(self):
+        s = pks_hmm()
+        s.K = self.K
+        s.Pi = self.Pi.data_ptr()
+        s.p0 = self.p0.data_ptr()
+        return s
+
+
+def hmm_to_device(Pi, p0, device="cuda") -> DeviceHmm:
+    cv = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+    return DeviceHmm(cv(Pi), cv(p0))
+
+
+def hmm_workspace(K: int, T: int, device="cuda") -> torch.Tensor:
+    n = lib.pks_hmm_workspace_bytes(K, int(T))
+    if n == 0:
+        raise PksError(PKS_E_ARG, "invalid HMM workspace request (K=%d, T=%d)" % (K, T))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def hmm_filter_smooth(model: DeviceHmm, L: torch.Tensor, ws=None, out=None, smooth=True, stream=None):
+    """Filtered marginals alpha [T,K], log p(y_1:k) [T] and (``smooth``) the
+    smoothed marginals gamma [T,K] from the emission log-likelihoods L [T,K]."""
+    T, K = L.shape[0], model.K
+    if L.dtype != torch.float64 or L.ndim != 2 or L.shape[1] != K:
+        raise ValueError("L must be float64 [T, K]")
+    ws = ws if ws is not None else hmm_workspace(K, T, L.device)
+    if out is None:
+        alpha = torch.empty((T, K), dtype=torch.float64, device=L.device)
+        logp = torch.empty(T, dtype=torch.float64, device=L.device)
+        gamma = torch.empty((T, K), dtype=torch.float64, device=L.device) if smooth else None
+    else:
+        alpha, logp, gamma = out
+    st = model.struct()
+    if smooth:
+        _check(lib.pks_hmm_filter_smooth(ctypes.byref(st), T, _ptr(L), _ptr(alpha), _ptr(logp), _ptr(gamma),
+                                         _ptr(ws), ws.numel(), _stream(stream)))
+    else:
+        _check(lib.pks_hmm_filter(ctypes.byref(st), T, _ptr(L), _ptr(alpha), _ptr(logp), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return alpha, logp, gamma
+
+
+def hmm_smooth(model: DeviceHmm, alpha: torch.Tensor, ws=None, out=None, stream=None):
+    """Smoothed marginals gamma [T,K] from filtered marginals alpha [T,K]."""
+    T, K = alpha.shape[0], model.K
+    ws = ws if ws is not None else hmm_workspace(K, T, alpha.device)
+    gamma = out if out is not None else torch.empty((T, K), dtype=torch.float64, device=alpha.device)
+    st = model.struct()
+    _check(lib.pks_hmm_smooth(ctypes.byref(st), T, _ptr(alpha), _ptr(gamma), _ptr(ws), ws.numel(),
+                              _stream(stream)))
+    return gamma
 
 
 def version() -> str:

@@ -19,6 +19,11 @@ Workloads (ids 1..5):
      times (dt_k ~ U(0.05, 0.15), so F_{k-1} and Q_{k-1} change every step),
      q = 1, sigma^2 = 0.25, T = 2**20
 
+Discrete-state hidden Markov model inputs (:func:`hmm_workload`): a sticky
+transition matrix, a uniform prior and Gaussian emissions y_k ~ N(mu_{x_k}, 1)
+with mu_j = j / 2; the inputs of the method are the emission log-likelihoods
+L[k-1][j] = log N(y_k; mu_j, 1).  Workload 7: K = 64 states, T = 2**16.
+
 A time-varying model is a Model whose F, Q, H, R (and u, d) carry a leading
 [T] axis: row k-1 holds the transition into step k (F_{k-1}, Q_{k-1}, u_{k-1})
 and the measurement model of step k (H_k, R_k, d_k).
@@ -311,6 +316,7 @@ WORKLOAD_NAMES = {
     4: "cv_batched_B4096_uneven",
     5: "random_nx64_ny32_B64_T8192",
     6: "cv_irregular_T1048576",
+    7: "hmm_K64_T65536",
 }
 
 
@@ -427,3 +433,61 @@ def max_rel_err(X: np.ndarray, Xref: np.ndarray, floor: str = "none") -> float:
     if np.any(np.isnan(r)):
         return float("nan")
     return float(np.max(r))
+
+
+# ---------------------------------------------------------------------------
+# discrete-state hidden Markov model
+# ---------------------------------------------------------------------------
+@dataclass
+class HmmWorkload:
+    name: str
+    Pi: np.ndarray          # [K, K] row-stochastic
+    p0: np.ndarray          # [K]
+    L: np.ndarray           # [T, K] emission log-likelihoods
+    x: Optional[np.ndarray] = None   # [T] simulated states
+
+    @property
+    def K(self) -> int:
+        return self.Pi.shape[0]
+
+    @property
+    def T(self) -> int:
+        return self.L.shape[0]
+
+
+def hmm_model(K: int, rng: np.random.Generator, stay: float = 0.9, sparse: bool = False):
+    """Sticky transitions: Pi = stay I + (1 - stay) D with D's rows drawn from
+    a flat Dirichlet (with ``sparse``, about half of D's entries are zero);
+    uniform prior."""
+    D = rng.dirichlet(np.ones(K), size=K)
+    if sparse:
+        D *= rng.random((K, K)) < 0.5
+        D[np.arange(K), (np.arange(K) + 1) % K] += 1e-3
+        D /= D.sum(axis=1, keepdims=True)
+    Pi = stay * np.eye(K) + (1.0 - stay) * D
+    Pi /= Pi.sum(axis=1, keepdims=True)
+    return Pi, np.full(K, 1.0 / K)
+
+
+def hmm_simulate(Pi: np.ndarray, p0: np.ndarray, T: int, rng: np.random.Generator, sigma: float = 1.0):
+    """States x_1..x_T of the chain and the Gaussian emission log-likelihoods
+    of y_k ~ N(x_k / 2, sigma^2) under every state."""
+    K = Pi.shape[0]
+    cum = np.cumsum(Pi, axis=1)
+    x = np.empty(T, dtype=np.int64)
+    s = rng.choice(K, p=p0)
+    u = rng.random(T)
+    for k in range(T):
+        s = min(int(np.searchsorted(cum[s], u[k], side="right")), K - 1)
+        x[k] = s
+    mu = 0.5 * np.arange(K)
+    y = mu[x] + sigma * rng.standard_normal(T)
+    L = -0.5 * ((y[:, None] - mu[None, :]) / sigma) ** 2 - np.log(sigma * np.sqrt(2.0 * np.pi))
+    return np.ascontiguousarray(L), x
+
+
+def hmm_workload(K: int = 64, T: int = 1 << 16, seed: int = 7, sparse: bool = False) -> HmmWorkload:
+    rng = rng_for(seed, K)
+    Pi, p0 = hmm_model(K, rng, sparse=sparse)
+    L, x = hmm_simulate(Pi, p0, T, rng)
+    return HmmWorkload("hmm_K%d_T%d" % (K, T), Pi, p0, L, x)

@@ -207,3 +207,31 @@ def test_time_varying_batched_argument_errors():
                                      None) == pks.PKS_E_ARG
     assert lib.pks_loglik_tv_batched(ctypes.byref(t), 3, FAKE, 100, y, m, P, None, None, 0, 0, ws, wsb,
                                      None) == pks.PKS_E_ARG
+
+
+def test_hmm_workspace_and_argument_errors():
+    """Discrete-state HMM entry points: workspace sizing and validation."""
+    assert lib.pks_hmm_workspace_bytes(0, 10) == 0 and lib.pks_hmm_workspace_bytes(65, 10) == 0
+    assert lib.pks_hmm_workspace_bytes(4, -1) == 0
+    assert 0 < lib.pks_hmm_workspace_bytes(4, 100) < lib.pks_hmm_workspace_bytes(64, 100)
+    assert 0 < lib.pks_hmm_workspace_bytes(64, 1 << 16) <= lib.pks_hmm_workspace_bytes(64, 1 << 20)
+    m = pks.pks_hmm()
+    m.K, m.Pi, m.p0 = 4, FAKE, FAKE + 0x1000
+    need = lib.pks_hmm_workspace_bytes(4, 16)
+    L, a, lp, g, ws = FAKE + 0x100000, FAKE + 0x200000, FAKE + 0x300000, FAKE + 0x400000, FAKE + 0x800000
+    f = lambda mp, T=16, L=L, a=a, lp=lp, ws=ws, n=need: lib.pks_hmm_filter(mp, T, L, a, lp, ws, n, None)
+    assert f(None) == pks.PKS_E_ARG
+    assert f(ctypes.byref(m), T=-1) == pks.PKS_E_ARG
+    assert f(ctypes.byref(m), L=None) == pks.PKS_E_ARG
+    assert f(ctypes.byref(m), ws=None) == pks.PKS_E_ARG
+    assert f(ctypes.byref(m), n=need - 1) == pks.PKS_E_WORKSPACE
+    assert f(ctypes.byref(m), a=L + 8) == pks.PKS_E_ARG                  # output overlaps input
+    assert f(ctypes.byref(m), T=0) == pks.PKS_OK                        # empty: nothing enqueued
+    bad = pks.pks_hmm()
+    bad.K, bad.Pi, bad.p0 = 65, FAKE, FAKE
+    assert f(ctypes.byref(bad)) == pks.PKS_E_ARG
+    bad.K, bad.Pi = 4, None
+    assert f(ctypes.byref(bad)) == pks.PKS_E_ARG
+    assert lib.pks_hmm_smooth(ctypes.byref(m), 16, a, None, ws, need, None) == pks.PKS_E_ARG
+    assert lib.pks_hmm_smooth(ctypes.byref(m), 16, a, a + 8, ws, need, None) == pks.PKS_E_ARG
+    assert lib.pks_hmm_filter_smooth(ctypes.byref(m), 16, L, a, lp, L, ws, need, None) == pks.PKS_E_ARG
