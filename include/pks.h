@@ -58,14 +58,17 @@ typedef enum {
     PKS_E_UNSUPPORTED = 2,  /* valid request this library does not handle   */
     PKS_E_WORKSPACE = 3,    /* ws_bytes smaller than pks_workspace_bytes()   */
     PKS_E_HIP = 4,          /* a HIP runtime call or kernel launch failed    */
-    PKS_E_NUMERIC = 5       /* reported by pks_read_numeric_status only      */
+    PKS_E_NUMERIC = 5,      /* reported by pks_read_numeric_status only      */
+    PKS_STATUS_RANGE_ = 0x7fffffff  /* not a status: makes every int a valid value */
 } pks_status;
 
 typedef enum {
     PKS_FP64 = 0,        /* all arithmetic, inputs and outputs in double              */
-    PKS_MIXED_FP32 = 1   /* float storage and products; the (I + C_i J_j) solves of
+    PKS_MIXED_FP32 = 1,  /* float storage and products; the (I + C_i J_j) solves of
                             Lemma 2, the Cholesky solves of Lemmas 1 and 3 and the
                             covariance symmetrisation run in double                  */
+    PKS_PRECISION_RANGE_ = 0x7fffffff  /* not a precision: any int passed here is a valid
+                                          value of the type, and is rejected with PKS_E_ARG */
 } pks_precision;
 
 /*

@@ -133,6 +133,7 @@ ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offset
     a.agg = base + L.agg;
     a.carry = base + L.carry;
     a.ept = cfg.ept;
+    a.large_blocks = cfg.blocks;
     a.nwaves = round_up(std::max<int64_t>(1, ceil_div(total, 64 * cfg.ept)), 4);
     a.nthr = a.nwaves * 64;
     a.ept1 = cfg.ept1;
@@ -164,6 +165,7 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     const bool mixed = prec == PKS_MIXED_FP32;
     TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
     if (cfg.ept < kMinEpt) cfg.ept = kMinEpt;
+    if (!small_supported(model.nx)) cfg.ept1 = 0;   // the large-state path reads only cfg.blocks
     hipError_t e = launch_precompute(model.nx, model.ny, nmodels, model, ws, L, mixed, passes,
                                      (passes & 1) != 0, s, tv, tv ? offsets : nullptr, B);
     if (e != hipSuccess) return hip_fail(e, "precompute kernel");

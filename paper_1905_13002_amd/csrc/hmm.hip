@@ -109,7 +109,7 @@ __device__ __forceinline__ double scaled_lik(const double* __restrict__ Lk, int 
 // ---------------------------------------------------------------------------
 // Strip products on the matrix cores.  A 16 x KP strip X (rows of the wave)
 // times a KP x KP matrix Y: lane l supplies X(l % 16, 4 s + l / 16) and
-// Y(4 s + l / 16, 16 t + l % 16) and receives D(4 (l / 16) + v, 16 t + l % 16)
+// Y(4 s + l / 16, 16 t + l % 16) and receives D(4 v + l / 16, 16 t + l % 16)
 // in register v of tile t.  X comes from the wave's LDS stage (row stride KP
 // + 1 doubles), Y from registers (Yf[s][t]).
 // ---------------------------------------------------------------------------
@@ -127,13 +127,13 @@ __device__ __forceinline__ void strip_times(const double* __restrict__ Xs, const
     }
 }
 
-// write the strip held in D layout into the stage (rows 4 lk + v, columns 16 t + li)
+// write the strip held in D layout into the stage (rows 4 v + lk, columns 16 t + li)
 template <int KP>
 __device__ __forceinline__ void stage_strip(double* __restrict__ Xs, const f64x4 (&D)[KP / 16], int li, int lk) {
 #pragma unroll
     for (int t = 0; t < KP / 16; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Xs[(4 * lk + v) * (KP + 1) + 16 * t + li] = D[t][v];
+        for (int v = 0; v < 4; ++v) Xs[(4 * v + lk) * (KP + 1) + 16 * t + li] = D[t][v];
 }
 
 // Y fragments of Pi (trans = false) or Pi^T (trans = true), zero outside K x K
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_filter_reduce(HmmArgs a) {
     for (int v = 0; v < 4; ++v) {
         c[v] = 0.0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) D[t][v] = (16 * w + 4 * lk + v == 16 * t + li) ? 1.0 : 0.0;
+        for (int t = 0; t < NT; ++t) D[t][v] = (16 * w + 4 * v + lk == 16 * t + li) ? 1.0 : 0.0;
     }
     for (int64_t k = s; k < e; ++k) {
         if (k == 0) {
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_filter_reduce(HmmArgs a) {
             for (int t = 0; t < NT; ++t) {
                 const double pv = (16 * t + li < K) ? p0[16 * t + li] : 0.0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) D[t][v] = (16 * w + 4 * lk + v < K) ? pv : 0.0;
+                for (int v = 0; v < 4; ++v) D[t][v] = (16 * w + 4 * v + lk < K) ? pv : 0.0;
             }
         }
         stage_strip<KP>(Xs, D, li, lk);
@@ -215,10 +215,10 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_filter_reduce(HmmArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) A[(16 * w + 4 * lk + v) * KP + 16 * t + li] = D[t][v];
+        for (int v = 0; v < 4; ++v) A[(16 * w + 4 * v + lk) * KP + 16 * t + li] = D[t][v];
     if (li == 0)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) C[16 * w + 4 * lk + v] = c[v];
+        for (int v = 0; v < 4; ++v) C[16 * w + 4 * v + lk] = c[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_smoother_reduce(HmmArgs a)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) D[t][v] = (16 * w + 4 * lk + v == 16 * t + li) ? 1.0 : 0.0;
+        for (int t = 0; t < NT; ++t) D[t][v] = (16 * w + 4 * v + lk == 16 * t + li) ? 1.0 : 0.0;
     for (int64_t k = e - 1; k >= s; --k) {
         const double ak = lane < K ? a.alpha[k * K + lane] : 0.0;
         if (k == a.T - 1) {
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_smoother_reduce(HmmArgs a)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) V[(16 * w + 4 * lk + v) * KP + 16 * t + li] = D[t][v];
+        for (int v = 0; v < 4; ++v) V[(16 * w + 4 * v + lk) * KP + 16 * t + li] = D[t][v];
 }
 
 // ---------------------------------------------------------------------------
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_scan_level(const double* _
 #pragma unroll
             for (int t = 0; t < NT; ++t) D[t][v] *= inv;
             if (li == 0) {
-                const int row = 16 * w + 4 * lk + v;
+                const int row = 16 * w + 4 * v + lk;
                 outC[b * KP + row] = inC[partner * KP + row] + cmax + log(r);
             }
         }
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(KP / 16 * 64) void k_hmm_scan_level(const double* _
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) oA[(size_t)(16 * w + 4 * lk + v) * KP + 16 * t + li] = D[t][v];
+        for (int v = 0; v < 4; ++v) oA[(size_t)(16 * w + 4 * v + lk) * KP + 16 * t + li] = D[t][v];
 }
 
 // ---------------------------------------------------------------------------

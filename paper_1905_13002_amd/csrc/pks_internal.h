@@ -114,6 +114,7 @@ struct ScanArgs {
     void* carry1;
     int64_t nthr1, nwaves1;
     int ept, ept1;               // elements per thread at level 0 / 1
+    int64_t large_blocks;        // large states: requested number of time blocks (0 = default)
     int* status;
     const int* model_fail;       // [nmodels] 1 = the model's precompute failed
     int nmodels;
@@ -131,8 +132,10 @@ __host__ __device__ __forceinline__ int64_t const_offset(const ScanArgs& a, int 
 
 // Tile configuration chosen for a launch.
 struct TileConfig {
-    int ept;      // elements per thread, level 0 (4, 8, 16)
-    int ept1;     // elements per thread, level 1 (aggregates); 0 = no level 1
+    int ept = 16;    // elements per thread, level 0 (4, 8, 16)
+    int ept1 = 0;    // elements per thread, level 1 (aggregates); 0 = no level 1
+    int blocks = 0;  // large states (nx >= 5): blocks of the time axis (Section III-C's
+                  // block elements); 0 = the default count
 };
 
 // Per-kernel timing (diagnostics).  While enabled on the calling thread,
@@ -179,6 +182,8 @@ hipError_t launch_hmm(int K, int64_t T, const double* Pi, const double* p0, cons
 
 // large-state path (scan_large.hip), 5 <= nx <= 64
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);
+// the default (and largest) number of time blocks of the large-state scans
+int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed);
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
 
 }  // namespace pks

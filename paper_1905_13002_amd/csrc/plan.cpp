@@ -47,7 +47,9 @@ const char* cache_path_or_env(const char* path) {
     return (env && *env) ? env : nullptr;
 }
 
-// The cache is a flat JSON object {"key": [ept, ept1], ...}, one entry a line.
+// The cache is a flat JSON object {"key": [ept, ept1, blocks], ...}, one entry
+// a line (entries of two numbers, from before the large-state tuning, read
+// with blocks = 0).
 std::map<std::string, TileConfig> read_cache(const char* path) {
     std::map<std::string, TileConfig> out;
     if (!path) return out;
@@ -60,11 +62,13 @@ std::map<std::string, TileConfig> read_cache(const char* path) {
         const size_t q1 = line.find('"', q0 + 1);
         const size_t b0 = line.find('[', q1);
         if (q1 == std::string::npos || b0 == std::string::npos) continue;
-        int e0 = 0, e1 = 0;
-        if (sscanf(line.c_str() + b0, "[%d , %d]", &e0, &e1) == 2 || sscanf(line.c_str() + b0, "[%d,%d]", &e0, &e1) == 2) {
+        int e0 = 0, e1 = 0, e2 = 0;
+        const int n = sscanf(line.c_str() + b0, "[ %d , %d , %d ]", &e0, &e1, &e2);
+        if (n >= 2) {
             TileConfig c;
             c.ept = e0;
             c.ept1 = e1;
+            c.blocks = n == 3 ? e2 : 0;
             out[line.substr(q0 + 1, q1 - q0 - 1)] = c;
         }
     }
@@ -79,7 +83,8 @@ bool write_cache(const char* path, const std::map<std::string, TileConfig>& m) {
         f << "{\n";
         size_t i = 0;
         for (const auto& kv : m) {
-            f << "  \"" << kv.first << "\": [" << kv.second.ept << ", " << kv.second.ept1 << "]"
+            f << "  \"" << kv.first << "\": [" << kv.second.ept << ", " << kv.second.ept1 << ", "
+              << kv.second.blocks << "]"
               << (++i < m.size() ? "," : "") << "\n";
         }
         f << "}\n";
@@ -87,7 +92,8 @@ bool write_cache(const char* path, const std::map<std::string, TileConfig>& m) {
     return std::rename(tmp.c_str(), path) == 0;
 }
 
-bool valid_config(const TileConfig& c) {
+bool valid_config(const TileConfig& c, int nx) {
+    if (!small_supported(nx)) return c.blocks >= 1;
     return (c.ept == 4 || c.ept == 8 || c.ept == 16) && (c.ept1 == 0 || c.ept1 == 1 || c.ept1 == 2 || c.ept1 == 4 || c.ept1 == 8);
 }
 
@@ -104,7 +110,7 @@ TileConfig tuned_config(int nx, int ny, int32_t B, int64_t total, pks_precision 
     if (p) {
         auto m = read_cache(p);
         auto it = m.find(cache_key(nx, ny, B, total, prec));
-        if (it != m.end() && valid_config(it->second)) return it->second;
+        if (it != m.end() && valid_config(it->second, nx)) return it->second;
     }
     return small_default_config(nx, total, prec == PKS_MIXED_FP32);
 }
@@ -203,10 +209,6 @@ pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_pr
         set_last_error("unknown precision");
         return PKS_E_ARG;
     }
-    if (!small_supported(nx)) {
-        set_last_error("autotuning covers the register (nx <= 4) path only");
-        return PKS_E_UNSUPPORTED;
-    }
     hipStream_t s = (hipStream_t)stream;
     const size_t rs = prec == PKS_FP64 ? 8 : 4;
     const int64_t T = total;
@@ -271,16 +273,36 @@ pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_pr
     hipEventCreate(&e1);
     TileConfig best = small_default_config(nx, total, prec == PKS_MIXED_FP32);
     float best_ms = 1e30f;
-    const int epts[3] = {4, 8, 16};
-    const int ept1s[5] = {0, 1, 2, 4, 8};
-    for (int ei = 0; ei < 3; ++ei) {
-        for (int li = 0; li < 5; ++li) {
+    // the candidates: register path (nx <= 4): elements per thread at both
+    // levels; large states: the number of time blocks (Section III-C's block
+    // length l = T / blocks), from the count the workspace is sized for down
+    // to an eighth of it (fewer, longer blocks: less scan work across blocks,
+    // fewer workgroups in flight)
+    std::vector<TileConfig> cands;
+    if (small_supported(nx)) {
+        const int epts[3] = {4, 8, 16};
+        const int ept1s[5] = {0, 1, 2, 4, 8};
+        for (int ei = 0; ei < 3; ++ei)
+            for (int li = 0; li < 5; ++li) {
+                TileConfig c;
+                c.ept = epts[ei];
+                c.ept1 = ept1s[li];
+                const int64_t waves = (T + 64 * c.ept - 1) / (64 * c.ept);
+                if (c.ept1 == 0 && waves > (int64_t)64 * 256) continue;    // top level would be too long
+                if (c.ept1 != 0 && waves < 128) continue;                  // second level not useful
+                cands.push_back(c);
+            }
+    } else {
+        const int64_t cap = large_default_blocks(nx, ny, T, prec == PKS_MIXED_FP32);
+        for (int64_t nb = cap; nb >= 1 && cands.size() < 4; nb /= 2) {
             TileConfig c;
-            c.ept = epts[ei];
-            c.ept1 = ept1s[li];
-            const int64_t waves = (T + 64 * c.ept - 1) / (64 * c.ept);
-            if (c.ept1 == 0 && waves > (int64_t)64 * 256) continue;        // top level would be too long
-            if (c.ept1 != 0 && waves < 128) continue;                      // second level not useful
+            c.blocks = (int)nb;
+            cands.push_back(c);
+        }
+        best = cands.front();
+    }
+    for (const TileConfig& c : cands) {
+        {
             float tot = 0.f;
             int reps = 0;
             pks_status st = PKS_OK;

@@ -47,6 +47,10 @@ int64_t large_blocks(int64_t total, int nx, int ny, bool mixed) {
 }  // namespace
 }  // namespace lg
 
+int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed) {
+    return lg::large_blocks(total, nx, ny, mixed);
+}
+
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec) {
     using namespace lg;
     const bool mixed = prec != PKS_FP64;
@@ -63,7 +67,8 @@ hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hip
     LargeArgs la;
     la.s = a;
     const int64_t nb_max = large_blocks(a.total, a.nx, a.ny, mixed);
-    la.nblocks = nb_max;
+    // a tuned block count is honoured up to the count the workspace is sized for
+    la.nblocks = (a.large_blocks > 0 && a.large_blocks < nb_max) ? a.large_blocks : nb_max;
     la.blen = (a.total + la.nblocks - 1) / la.nblocks;
     la.nblocks = (a.total + la.blen - 1) / la.blen;
     const size_t rs = mixed ? 4 : 8;

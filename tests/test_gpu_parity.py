@@ -218,13 +218,46 @@ def test_autotune_writes_cache_and_is_used(pks, tmp_path, monkeypatch, precision
     entries = json.loads(cache.read_text())
     key = "nx4_ny2_%s_T17_B0" % precision
     assert key in entries, entries
-    ept, ept1 = entries[key]
+    ept, ept1 = entries[key][:2]
     assert ept in (4, 8, 16) and ept1 in (0, 1, 2, 4, 8)
     monkeypatch.setenv("PKS_TUNE_CACHE", str(cache))
     w = wl.workload(1, T=T)
     check(pks, w.model, w.y, precision, "autotuned ept=%d ept1=%d" % (ept, ept1))
-    with pytest.raises(pks.PksError):
-        pks.autotune(16, 8, 1, 4096, precision, str(cache))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny,B,T", [(16, 8, 1, 4096), (64, 32, 4, 1024)])
+def test_autotune_large_states(pks, tmp_path, monkeypatch, precision, nx, ny, B, T):
+    """Large states: pks_autotune times the block counts of the time axis
+    (Section III-C's block length), records the fastest as the entry's third
+    number, and the scan (a plan, for the batched shape) runs with it,
+    checked against the oracle."""
+    cache = tmp_path / "tune.json"
+    pks.autotune(nx, ny, B, T, precision, str(cache))
+    entries = json.loads(cache.read_text())
+    key = "nx%d_ny%d_%s_T%d_B%d" % (nx, ny, precision, T.bit_length() - 1, B.bit_length() - 1)
+    assert key in entries, entries
+    blocks = entries[key][2]
+    assert blocks >= 1
+    monkeypatch.setenv("PKS_TUNE_CACHE", str(cache))
+    rng = np.random.default_rng(nx + ny)
+    model = wl.random_stable_model(nx, ny, rng, radius=0.97)
+    floor = "rms" if precision == "mixed" else "none"
+    if B == 1:
+        w = wl.single_sequence(model, T, seed=nx)
+        check(pks, model, w.y, precision, "autotuned nx=%d blocks=%d" % (nx, blocks), floor=floor)
+        return
+    offsets = np.arange(B + 1, dtype=np.int64) * (T // B)
+    y, _ = wl.simulate(model, T, rng)
+    dm = pks.to_device(model)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    plan = pks.Plan(dm, torch.as_tensor(y).to("cuda", dt), torch.as_tensor(offsets).cuda(), precision)
+    plan.launch()
+    torch.cuda.synchronize()
+    out = {k: getattr(plan, k).double().cpu().numpy() for k in ("m", "P", "ms", "Ps")}
+    plan.close()
+    ref = oracle_run(model, ref_input(y, precision), offsets)
+    assert_parity(out, ref, precision, "autotuned plan nx=%d blocks=%d" % (nx, blocks), floor)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
