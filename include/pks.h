@@ -265,6 +265,24 @@ pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_pr
 pks_status pks_read_numeric_status(void *ws, int32_t *first_bad_sequence, void *stream);
 
 /*
+ * pks_filter_smooth without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid hipMalloc).  Same arguments, outputs and errors as
+ * pks_filter_smooth minus ws / ws_bytes: the workspace is a static device
+ * array of pks_noalloc_scratch_bytes() bytes (32 MiB) that every GPU the
+ * library runs on holds until the process ends.  The call allocates nothing.
+ * A problem whose pks_workspace_bytes(nx, ny, T, 1, prec) exceeds that size
+ * returns PKS_E_UNSUPPORTED (about 3.1e5 steps at nx = 4, ny = 2 in FP64,
+ * 5.4e5 in PKS_MIXED_FP32).  All calls on one GPU share that GPU's array:
+ * calls that overlap on one GPU race (serialise them on one stream), and
+ * pks_read_numeric_status is not available for this entry point (its flag
+ * lives in the shared array; a failed factorisation still yields NaN).
+ */
+pks_status pks_filter_smooth_noalloc(const pks_model *model, int64_t T, const void *y, void *m, void *P,
+                                     void *ms, void *Ps, pks_precision prec, void *stream);
+size_t pks_noalloc_scratch_bytes(void);
+
+/*
  * Discrete-state hidden Markov model: the same parallel filter and smoother
  * with a finite state space, where the integrals of Definitions 1 and 2
  * become sums over the states (the paper's concluding section notes that the

@@ -21,7 +21,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = (["scan_large_f64.hip", "scan_large_f32.hip", "scan_large_f64_seg.hip", "scan_large_f32_seg.hip",
             "api.cpp", "plan.cpp", "precompute.hip", "scan_small.hip", "scan_large.hip", "loglik.hip",
-            "hmm.hip"]
+            "hmm.hip", "noalloc.hip"]
            + ["scan_small_n%d_%s.hip" % (n, t) for n in (4, 3, 2, 1) for t in ("f64", "f32")])
 
 ARCH = os.environ.get("PKS_OFFLOAD_ARCH", "gfx950")

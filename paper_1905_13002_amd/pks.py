@@ -29,7 +29,8 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_version", "pks_profile_start", "pks_profile_stop", "pks_loglik", "pks_loglik_batched",
             "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv",
             "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched",
-            "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth"]
+            "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth",
+            "pks_filter_smooth_noalloc", "pks_noalloc_scratch_bytes"]
 
 
 class PksError(RuntimeError):
@@ -68,6 +69,8 @@ def _load():
     hp = ctypes.POINTER(pks_hmm)
     sig = {
         "pks_hmm_workspace_bytes": (sz, [i32, i64]),
+        "pks_filter_smooth_noalloc": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
+        "pks_noalloc_scratch_bytes": (sz, []),
         "pks_hmm_filter": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, sz, vp]),
         "pks_hmm_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, sz, vp]),
         "pks_hmm_filter_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, vp, sz, vp]),

@@ -125,6 +125,10 @@ int main() {
     EXPECT(pks_autotune(4, 2, 1, 1000, PKS_FP64, nullptr, nullptr) == PKS_E_ARG);
     EXPECT(pks_autotune(0, 2, 1, 1000, PKS_FP64, "/tmp/unused.json", nullptr) == PKS_E_ARG);
     EXPECT(pks_read_numeric_status(nullptr, nullptr, nullptr) == PKS_E_ARG);
+    EXPECT(pks_filter_smooth_noalloc(nullptr, 16, y, mm, P, ms, Ps, PKS_FP64, nullptr) == PKS_E_ARG);
+    EXPECT(pks_filter_smooth_noalloc(&m, int64_t(1) << 24, y, mm, P, ms, Ps, PKS_FP64, nullptr) ==
+           PKS_E_UNSUPPORTED);
+    EXPECT(pks_noalloc_scratch_bytes() > 0);
     EXPECT(std::string(pks_version()).find("pks") != std::string::npos);
 
     // a request that passes validation reads the tuning cache (malformed lines

@@ -55,7 +55,7 @@ def test_host_abi_under_asan_ubsan(tmp_path):
     hipcc = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not found")
-    srcs = [s for s in _host_sources() if os.path.basename(s) != "noalloc.hip"]
+    srcs = _host_sources()
     driver = os.path.join(ROOT, "tests", "sanitize", "abi_driver.cpp")
     headers = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".h", ".hpp"))]
     tag = _digest(srcs + headers + [driver, os.path.join(ROOT, "include", "pks.h")])
