@@ -248,7 +248,10 @@ def summarize_trace(base, wid, op="filter_smooth"):
     from paper_1905_13002_amd import workloads as wl
     name = wl.WORKLOAD_NAMES[wid]
     ll = op == "loglik"
-    opt = " --op loglik" if ll else ""
+    hmm = op == "hmm"
+    if hmm:
+        name, wid = wl.WORKLOAD_NAMES[7], 7
+    opt = " --op loglik" if ll else (" --op hmm" if hmm else "")
     db = [f for f in sorted(os.listdir(base)) if f.endswith("_results.db")]
     if not db:
         raise FileNotFoundError("no *_results.db under %s" % base)
@@ -262,13 +265,15 @@ def summarize_trace(base, wid, op="filter_smooth"):
             rows.append((n, int(calls), float(avg), float(tot)))
     cmd = ("rocprofv3 --kernel-trace --stats -d %s -o trace -- python bench.py --workload %d%s --steps 2 "
            "--warmup 1 --no-cpu-baseline" % (base.rstrip("/"), wid, opt))
-    what = "marginal likelihood (filter, then factors + partial sums + totals)" if ll else "filter + smoother"
+    what = ("marginal likelihood (filter, then factors + partial sums + totals)" if ll else
+            ("discrete-state filter + smoother (FP64)" if hmm else "filter + smoother"))
     lines = ["# Kernel profile: %s, %s" % (name, what), "",
              "`rocprofv3` kernel trace on one MI355X, library built from this tree.  Commands (repository root):", "",
              "```", cmd, "python bench.py --summarize-trace %s --workload %d%s" % (base.rstrip("/"), wid, opt),
              "```", "",
-             "The bench runs the FP64 path and then the mixed path (warm-up, timed passes and one pass with HIP "
-             "events each); `avg_us` is the mean kernel duration over all dispatches, `total_ms` the sum.", "",
+             ("The bench runs the FP64 pass (warm-up, timed passes and passes with HIP events); " if hmm else
+              "The bench runs the FP64 path and then the mixed path (warm-up, timed passes and one pass with HIP "
+              "events each); ") + "`avg_us` is the mean kernel duration over all dispatches, `total_ms` the sum.", "",
              "| kernel | calls | avg_us | total_ms |", "|---|---:|---:|---:|"]
     for n, calls, avg, tot in rows:
         lines.append("| `%s` | %d | %.1f | %.2f |" % (n, calls, avg, tot / 1e3))
@@ -294,8 +299,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
-    ap.add_argument("--op", default="filter_smooth", choices=["filter_smooth", "loglik"],
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5, 6, 7])
+    ap.add_argument("--op", default="filter_smooth", choices=["filter_smooth", "loglik", "hmm"],
                     help="what a timed step runs (default: the filter + smoother pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
@@ -334,6 +339,9 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.op == "hmm":
+        bench_hmm(args, np, torch, oracle, pks, wl)
+        return
     w = wl.workload(args.workload)
     progress("workload %s generated (%d steps, %d sequences)" % (w.name, w.total, w.B))
     if args.op == "loglik":
@@ -544,6 +552,62 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_hmm(args, np, torch, oracle, pks, wl):
+    """Discrete-state HMM (workload 7: K = 64 states, T = 2^16): one step is
+    the filter (filtered marginals and log p(y_1:k)) plus the smoother.
+    Roofline: FP64 matrix products, 2 K^3 flops per step for each pass's
+    block elements (the GEMM of one step of the running product), against
+    the FP64 peak (matrix = vector on MI355X)."""
+    w = wl.hmm_workload()
+    T, K = w.T, w.K
+    progress("workload %s generated" % w.name)
+    dm = pks.hmm_to_device(w.Pi, w.p0)
+    L = torch.as_tensor(w.L).cuda()
+    ws = pks.hmm_workspace(K, T)
+    alpha = torch.empty((T, K), dtype=torch.float64, device="cuda")
+    logp = torch.empty(T, dtype=torch.float64, device="cuda")
+    gamma = torch.empty_like(alpha)
+    step = lambda: pks.hmm_filter_smooth(dm, L, ws=ws, out=(alpha, logp, gamma))
+    sec = time_steps(step, args.steps, args.warmup, torch)
+    pks.profile_start()
+    for _ in range(args.steps):
+        step()
+    prof = pks.profile_stop()
+    torch.cuda.synchronize()
+    kern = {k: tot / max(1, n) for k, (tot, n) in prof.items()}
+    ref = oracle.hmm_fb(w.Pi, w.p0, w.L)
+    a, g, lp = alpha.cpu().numpy(), gamma.cpu().numpy(), logp.cpu().numpy()
+    errs = {"alpha_abs": float(np.max(np.abs(a - ref["alpha"]))), "gamma_abs": float(np.max(np.abs(g - ref["gamma"]))),
+            "logp_rel": float(np.max(np.abs(lp - np.cumsum(ref["ll"])) / np.maximum(1.0, np.cumsum(np.abs(ref["ll"])))))}
+    flops_step = 2 * 2.0 * K ** 3
+    ach = flops_step * T / sec / 1e12
+    dom = max(kern, key=kern.get)
+    rl = dict(bound="mfma", achieved=round(ach, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+              frac=round(ach / FP64_PEAK_TFLOPS, 4), traffic=None, scope="whole pass",
+              algorithmic_flops_per_step=flops_step, dominant_kernel=dom, dominant_kernel_ms=round(kern[dom], 4))
+    cpu = None
+    if not args.no_cpu_baseline:
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            oracle.hmm_fb(w.Pi, w.p0, w.L)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 20:
+                break
+        cpu = dict(value=T / statistics.median(times), unit="smoothed time steps/s", cores=1, kind="oracle",
+                   sample="full workload (T=%d, K=%d), %d runs, median; sequential C forward-backward, 1 thread"
+                   % (T, K, len(times)))
+    line = {"metric": "HMM smoothed time steps/sec (filter+smoother), K=%d states" % K, "value": T / sec,
+            "unit": "smoothed time steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic (seeded sticky chain, Gaussian emissions)",
+            "config": {"workload": w.name, "T": T, "K": K, "path": "pks_hmm_filter_smooth"},
+            "max_err": errs, "roofline": rl, "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+            "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 
