@@ -32,7 +32,17 @@ bool small_supported(int nx) { return nx >= 1 && nx <= 4; }
 TileConfig small_default_config(int nx, int64_t total, bool mixed) {
     (void)nx;
     TileConfig c;
-    c.ept = mixed ? 8 : 16;
+    // the longest per-thread fold that still gives every SIMD (1024 on the
+    // chip) a wave; shorter sequences take the shortest fold (more threads,
+    // a shorter dependent chain per thread)
+    const int64_t simds = 1024;
+    const int emax = mixed ? 8 : 16;
+    c.ept = 4;
+    for (int e = emax; e > 4; e >>= 1)
+        if (total >= (int64_t)64 * e * simds) {
+            c.ept = e;
+            break;
+        }
     const int64_t waves = (total + 64 * c.ept - 1) / (64 * c.ept);
     if (mixed) c.ept1 = waves > 256 ? 1 : 0;
     else c.ept1 = waves > 2048 ? (waves > 64 * 1024 ? 2 : 1) : 0;

@@ -398,10 +398,12 @@ __device__ __forceinline__ void wave_load_moments(const R* __restrict__ m, const
 // wave-level scans (Kogge-Stone over shuffles).  Lanes without a partner take
 // the identity as the shuffled operand, so every lane runs the same combine.
 // ---------------------------------------------------------------------------
+// `lim`: a power of two >= the number of lanes that hold a real element (the
+// others hold the identity), so fewer levels suffice when few lanes are used.
 template <int N, typename R, bool G>
-__device__ __forceinline__ void wave_inclusive_f(FElem<N, R>& incl, int lane) {
+__device__ __forceinline__ void wave_inclusive_f(FElem<N, R>& incl, int lane, int lim = 64) {
 #pragma unroll 1
-    for (int d = 1; d < 64; d <<= 1) {
+    for (int d = 1; d < lim; d <<= 1) {
         FElem<N, R> o = incl;
         shfl_up_words<Words<N>::F>(reinterpret_cast<R*>(&o), d);
         if (lane >= d) fcombine<N, R, G>(o, incl, incl);
@@ -414,9 +416,9 @@ __device__ __forceinline__ void wave_exclusive_from_inclusive_f(const FElem<N, R
     if (lane == 0) set_identity(ex);
 }
 template <int N, typename R, bool G>
-__device__ __forceinline__ void wave_inclusive_suffix_s(SElem<N, R>& incl, int lane) {
+__device__ __forceinline__ void wave_inclusive_suffix_s(SElem<N, R>& incl, int lane, int lim = 64) {
 #pragma unroll 1
-    for (int d = 1; d < 64; d <<= 1) {
+    for (int d = 1; d < lim; d <<= 1) {
         SElem<N, R> o = incl;
         shfl_down_words<Words<N>::S>(reinterpret_cast<R*>(&o), d);
         if (lane + d < 64) scombine<N, R, G>(incl, o, incl);
@@ -507,6 +509,17 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce_items(ScanArgs a) {
     if (lane == 63) store_f(a.agg1, a.nwaves1, gt >> 6, acc);
 }
 
+// Kogge-Stone distance limit of a top-level wave: the threads of wave w that
+// hold items (chunk items each) number min(64, ceil(n / chunk) - 64 w); the
+// other lanes hold the identity, so levels beyond the next power of two of
+// that count change nothing.  Uniform across the wave.
+__device__ __forceinline__ int top_levels_lim(int64_t n, int64_t chunk, int wave) {
+    const int64_t used = (n + chunk - 1) / chunk - 64 * (int64_t)wave;
+    int lim = 1;
+    while (lim < 64 && lim < used) lim <<= 1;
+    return lim;
+}
+
 // top: one workgroup scans n items, writes carry[i] = moments of items 0..i-1
 // NT threads (64 or 256).  Also reports models whose precompute failed
 // (model_fail[b] != 0) to the numeric flag; this runs after the precompute
@@ -529,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_filter_top(const void* items, int64_t n,
         if (i == i0) acc = x;
         else fcombine<N, R, G>(acc, x, acc);
     }
-    wave_inclusive_f<N, R, G>(acc, lane);
+    wave_inclusive_f<N, R, G>(acc, lane, top_levels_lim(n, chunk, wave));
     FElem<N, R> ex;
     wave_exclusive_from_inclusive_f(acc, ex, lane);
     if (lane == 63) {
@@ -781,7 +794,7 @@ __global__ __launch_bounds__(NT) void k_smoother_top(const void* items, int64_t 
         load_s(items, n, i, x);
         scombine<N, R, G>(x, acc, acc);
     }
-    wave_inclusive_suffix_s<N, R, G>(acc, lane);
+    wave_inclusive_suffix_s<N, R, G>(acc, lane, top_levels_lim(n, chunk, wave));
     SElem<N, R> ex;
     wave_exclusive_suffix_s(acc, ex, lane);
     if (lane == 0) {
