@@ -234,6 +234,67 @@ def summarize_profiles(base, workload_name):
     print("wrote profiles/%s_kernels.md and profiles/traffic_%s.json" % (workload_name, workload_name))
 
 
+COUNTER_PASSES = [
+    "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAIT_INST_ANY SQ_INSTS_LDS "
+    "SQ_INSTS_VALU_FMA_F64 GRBM_GUI_ACTIVE",
+    "SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_INSTS_VMEM SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_MUL_F64 "
+    "SQ_INSTS_VALU_ADD_F64 SQ_WAIT_ANY SQ_THREAD_CYCLES_VALU",
+]
+
+
+def summarize_counters(base, workload_name):
+    """Write profiles/<workload>_counters.md from two rocprofv3 --pmc
+    databases under base/pmc_a and base/pmc_b (median over dispatches):
+    instruction mix and how busy the vector unit is, per kernel."""
+    import collections
+    import re
+    import sqlite3
+
+    def short(n):
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "")
+        m = re.match(r"void (\w+<[^>]*>)", n)
+        return m.group(1) if m else n
+
+    vals = collections.defaultdict(dict)
+    for sub in ("pmc_a", "pmc_b"):
+        d = os.path.join(base, sub)
+        dbs = [f for f in sorted(os.listdir(d)) if f.endswith("_results.db")]
+        cur = sqlite3.connect(os.path.join(d, dbs[0])).cursor()
+        acc = collections.defaultdict(list)
+        for kn, cn, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
+            acc[(short(kn), cn)].append(float(v))
+        for (kn, cn), v in acc.items():
+            vals[kn][cn] = statistics.median(v)
+    lines = ["# Counter profile: %s" % workload_name, "",
+             "`rocprofv3 --pmc` on one MI355X, library built from this tree; two passes (repository root):", "",
+             "```"]
+    for i, cnt in enumerate(COUNTER_PASSES):
+        lines.append("rocprofv3 --pmc %s -d gpurun_out/pmc_%s -o pmc -- python bench.py --steps 2 --warmup 1 "
+                     "--no-cpu-baseline" % (cnt, "ab"[i]))
+    lines += ["python bench.py --summarize-counters gpurun_out", "```", "",
+              "Per kernel (median over dispatches): `VALU/wave` = SQ_INSTS_VALU / SQ_WAVES; `VALU busy` = "
+              "SQ_ACTIVE_INST_VALU x 4 / (SQ_WAVE_CYCLES x 4): the share of a wave's lifetime spent issuing "
+              "vector instructions (both counters in quad-cycles); `FMA64 share` = SQ_INSTS_VALU_FMA_F64 / "
+              "SQ_INSTS_VALU; `wait` = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.  Register counts and waves per SIMD "
+              "are the compiler's (`hipcc -Rpass-analysis=kernel-resource-usage`).", "",
+              "| kernel | waves | VALU/wave | VALU busy | FMA64 share | LDS/wave | VMEM/wave | wait | LDS bank conflicts |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for kn in sorted(vals):
+        if not kn.startswith("k_"):
+            continue
+        v = vals[kn]
+        w = max(1.0, v.get("SQ_WAVES", 1.0))
+        wc = max(1.0, v.get("SQ_WAVE_CYCLES", 1.0))
+        lines.append("| `%s` | %d | %.0f | %.2f | %.2f | %.0f | %.0f | %.2f | %.0f |" % (
+            kn, w, v.get("SQ_INSTS_VALU", 0) / w, v.get("SQ_ACTIVE_INST_VALU", 0) / wc,
+            v.get("SQ_INSTS_VALU_FMA_F64", 0) / max(1.0, v.get("SQ_INSTS_VALU", 1.0)),
+            v.get("SQ_INSTS_LDS", 0) / w, v.get("SQ_INSTS_VMEM", 0) / w, v.get("SQ_WAIT_INST_ANY", 0) / wc,
+            v.get("SQ_LDS_BANK_CONFLICT", 0)))
+    with open(os.path.join(ROOT, "profiles", "%s_counters.md" % workload_name), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote profiles/%s_counters.md" % workload_name)
+
+
 def progress(msg):
     """One line per finished phase on stderr (the JSON result alone goes to stdout)."""
     print("bench: " + msg, file=sys.stderr, flush=True)
@@ -308,11 +369,16 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters under rocprofv3)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise the rocprofv3 databases under DIR into profiles/ and exit")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="summarise the two rocprofv3 --pmc counter passes under DIR into profiles/ and exit")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="summarise a rocprofv3 kernel trace of --workload under DIR into profiles/ and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, "cv_T1048576")
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, "cv_T1048576")
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.workload, args.op)

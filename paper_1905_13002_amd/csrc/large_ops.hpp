@@ -109,20 +109,72 @@ __device__ __forceinline__ void gemm_mfma_f32(float* C, int ldc, const float* A,
     }
 }
 
-// Products of the storage type.  FP32 products with both output dimensions
-// at least 32 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// FP64 product on the matrix cores (v_mfma_f64_16x16x4f64), one wave per
+// 16 x 16 tile of C, K in steps of 4.  Operands as for the FP32 instruction
+// (lane l supplies A(i0 + l % 16, k + l / 16) and B(k + l / 16, j0 + l % 16)),
+// but the FP64 result rows are interleaved: accumulator register r of lane l
+// holds C(i0 + 4 r + l / 16, j0 + l % 16).  Four k steps are loaded before
+// their products issue, so several operand loads are in flight.  Kept out of
+// line: inlined, its registers count against every caller, including the
+// kernels of small states that never take this path.
+__device__ __noinline__ void gemm_mfma_f64(double* C, int ldc, const double* A, int lda, bool ta, const double* B,
+                                              int ldb, bool tb, int m, int n, int k, double alpha, const double* D,
+                                              int ldd) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int tm = (m + 15) >> 4, tn = (n + 15) >> 4;
+    for (int t = wave; t < tm * tn; t += nwaves) {
+        const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+        const int ia = i0 + li, jb = j0 + li;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        int l0 = 0;
+        for (; l0 + 16 <= k; l0 += 16) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int l = l0 + 4 * q + lk;
+                av[q] = ia < m ? (ta ? A[l * lda + ia] : A[ia * lda + l]) : 0.0;
+                bv[q] = jb < n ? (tb ? B[jb * ldb + l] : B[l * ldb + jb]) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+        }
+        for (; l0 < k; l0 += 4) {
+            const int l = l0 + lk;
+            const double av = (ia < m && l < k) ? (ta ? A[l * lda + ia] : A[ia * lda + l]) : 0.0;
+            const double bv = (jb < n && l < k) ? (tb ? B[jb * ldb + l] : B[l * ldb + jb]) : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        const int j = j0 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 4 * r + lk;
+            if (i < m && j < n) {
+                double v = alpha * acc[r];
+                if (D) v += D[i * ldd + j];
+                C[i * ldc + j] = v;
+            }
+        }
+    }
+}
+
+// Products of the storage type.  Products with both output dimensions at
+// least 32 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
 // everything else on the vector units, with the largest register block that
 // still gives every thread of the workgroup a block of C.
 template <typename R>
 __device__ __forceinline__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
                       R alpha = R(1), const R* D = nullptr, int ldd = 0) {
     const int threads = blockDim.x;
-    if constexpr (sizeof(R) == 4) {
-        if (m >= 32 && n >= 32) {
+    if (m >= 32 && n >= 32) {
+        if constexpr (sizeof(R) == 4)
             gemm_mfma_f32(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
-            __syncthreads();
-            return;
-        }
+        else
+            gemm_mfma_f64(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
+        __syncthreads();
+        return;
     }
     if (((m + 3) >> 2) * ((n + 3) >> 2) >= threads)
         gemm_blocks<4, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
