@@ -229,6 +229,49 @@ __device__ __forceinline__ void make_selem(const R* __restrict__ cst, const Cons
 }
 
 
+// Lemma 3 element from explicit F, Q, u pointers (constants staged in LDS)
+template <int N, typename R>
+__device__ __forceinline__ void make_selem_p(const R* F, const R* Q, const R* u, const Moments<N, R>& x, bool last,
+                                             SElem<N, R>& e, int* status, int b) {
+    if (last) {
+#pragma unroll
+        for (int i = 0; i < N * N; ++i) e.E[i] = R(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) e.g[i] = x.m[i];
+#pragma unroll
+        for (int i = 0; i < tri(N); ++i) e.L[i] = x.P[i];
+    } else {
+        const bool ok = build_selem<N, R>(F, Q, u, x, e);
+        if (!ok) atomicMin(status, b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One shared model (a single time-invariant sequence): every step has the
+// same constants.  The step loops of the down-sweeps also store outputs, so
+// the compiler cannot prove constants read from global memory invariant and
+// re-reads them with vector memory instructions at every step; instead they
+// are copied to LDS once per workgroup and read from there.  The filter
+// stages its constants [0, F) when the rank-ny form applies (ny < nx <= 4,
+// at most 156 words), the smoother the copies of F, Q, u (2 nx^2 + nx words).
+// ---------------------------------------------------------------------------
+constexpr int kStageF = 160;
+template <int N>
+struct StageS {
+    static constexpr int words = 2 * N * N + N;
+};
+template <int N, typename R>
+__device__ __forceinline__ void stage_filter_consts(const ScanArgs& a, const ConstLayout& CL, R* csh, double* ssh) {
+    const R* g = static_cast<const R*>(a.consts);
+    for (int i = threadIdx.x; i < CL.F; i += blockDim.x) csh[i] = g[i];
+    for (int i = threadIdx.x; i < a.ny * a.ny; i += blockDim.x) ssh[i] = a.consts64[CL.S + i];
+}
+template <int N, typename R>
+__device__ __forceinline__ void stage_smoother_consts(const ScanArgs& a, const ConstLayout& CL, R* fsh) {
+    const R* g = static_cast<const R*>(a.consts);
+    for (int i = threadIdx.x; i < StageS<N>::words; i += blockDim.x) fsh[i] = g[CL.F + i];
+}
+
 // ---------------------------------------------------------------------------
 // Wave-cooperative moment transfers.  Lane l of a wave handles step
 // kbase + l * stride; a direct per-lane access of its moments would touch a
@@ -614,14 +657,21 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_items(ScanArgs a) {
 // level-0 down: outputs m_k, P_k
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
+    constexpr bool STG = !SEG && M > 0;
     __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
+    __shared__ R csh[STG ? kStageF : 1];
+    __shared__ double ssh[STG ? 16 : 1];
+    const ConstLayout CL = const_layout(N, a.ny);
+    if constexpr (STG) {
+        stage_filter_consts<N, R>(a, CL, csh, ssh);
+        __syncthreads();
+    }
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
     const int64_t kw = (gt - lane) * EPT;          // first step of the wave
     if (kw >= a.total) return;                     // whole wave beyond the end
     R* st = stage[threadIdx.x >> 6];
-    const ConstLayout CL = const_layout(N, a.ny);
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
     R* Po = static_cast<R*>(a.P);
@@ -639,7 +689,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         if (k < a.total) {
             seq_forward<SEG>(a, s, k);
             const int64_t moff = const_offset<SEG>(a, s.b, k);
-            const R* cst = static_cast<const R*>(a.consts) + moff;
+            const R* cst;
+            const double* Sp;
+            if constexpr (STG) {
+                cst = csh;
+                Sp = ssh;
+            } else {
+                cst = static_cast<const R*>(a.consts) + moff;
+                Sp = a.consts64 + moff + CL.S;
+            }
             const bool first = k == s.start;
             FElem<N, R> x;
             build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
@@ -649,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
                 constexpr int MM = M > 0 ? M : 1;
                 R Gz[MM * N];
                 load_gz<N, MM, R>(cst, CL, first, Gz);
-                fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
+                fcarry_fresh<N, MM, R, SEG>(X, x, Gz, Sp);
             }
         }
         wave_store_moments<N, R>(mo, Po, kw, e, EPT - 1, EPT, a.total, st, lane, X);
@@ -663,14 +721,23 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
 // arrays: each thread reads its filter prefix before writing its smoother one).
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a) {
+    constexpr bool STG = !SEG && M > 0;
     __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
+    __shared__ R csh[STG ? kStageF : 1];
+    __shared__ double ssh[STG ? 16 : 1];
+    __shared__ R fsh[STG ? StageS<N>::words : 1];
+    const ConstLayout CL = const_layout(N, a.ny);
+    if constexpr (STG) {
+        stage_filter_consts<N, R>(a, CL, csh, ssh);
+        stage_smoother_consts<N, R>(a, CL, fsh);
+        __syncthreads();
+    }
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
     const int64_t kw = (gt - lane) * EPT;
     if (kw >= a.total) return;
     R* st = stage[threadIdx.x >> 6];
-    const ConstLayout CL = const_layout(N, a.ny);
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
     R* Po = static_cast<R*>(a.P);
@@ -690,7 +757,18 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
         if (k < a.total) {
             seq_forward<SEG>(a, s, k);
             const int64_t moff = const_offset<SEG>(a, s.b, k);
-            const R* cst = static_cast<const R*>(a.consts) + moff;
+            const R* cst;
+            const double* Sp;
+            const R* Fp;
+            if constexpr (STG) {
+                cst = csh;
+                Sp = ssh;
+                Fp = fsh;
+            } else {
+                cst = static_cast<const R*>(a.consts) + moff;
+                Sp = a.consts64 + moff + CL.S;
+                Fp = cst + CL.F;
+            }
             const bool first = k == s.start;
             {
                 FElem<N, R> x;
@@ -701,11 +779,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
                     constexpr int MM = M > 0 ? M : 1;
                     R Gz[MM * N];
                     load_gz<N, MM, R>(cst, CL, first, Gz);
-                    fcarry_fresh<N, MM, R, SEG>(X, x, Gz, a.consts64 + moff + CL.S);
+                    fcarry_fresh<N, MM, R, SEG>(X, x, Gz, Sp);
                 }
             }
             SElem<N, R> el;
-            make_selem<N, R>(cst, CL, X, k == s.end - 1, el, a.status, s.b);
+            make_selem_p<N, R>(Fp, Fp + N * N, Fp + 2 * N * N, X, k == s.end - 1, el, a.status, s.b);
             if (e == 0) sacc = el;
             else scombine<N, R, SEG>(sacc, el, sacc);
         }
@@ -723,10 +801,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
 // ===========================================================================
 template <int N, typename R, int EPT, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
+    __shared__ R fsh[SEG ? 1 : StageS<N>::words];
+    const ConstLayout CL = const_layout(N, a.ny);
+    if constexpr (!SEG) {
+        stage_smoother_consts<N, R>(a, CL, fsh);
+        __syncthreads();
+    }
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
-    const ConstLayout CL = const_layout(N, a.ny);
     const R* m = static_cast<const R*>(a.m);
     const R* P = static_cast<const R*>(a.P);
     SElem<N, R> acc;
@@ -742,9 +825,11 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
             const Moments<N, R> x = xn;
             if (k > k0) load_moments_step(m, P, k - 1, xn);
             seq_backward<SEG>(a, s, k);
-            const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
+            const R* Fp;
+            if constexpr (SEG) Fp = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k) + CL.F;
+            else Fp = fsh;
             SElem<N, R> el;
-            make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
+            make_selem_p<N, R>(Fp, Fp + N * N, Fp + 2 * N * N, x, k == s.end - 1, el, a.status, s.b);
             if (k == klast) acc = el;
             else scombine<N, R, SEG>(el, acc, acc);
         }
@@ -866,13 +951,18 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down_items(ScanArgs a) {
 template <int N, typename R, int EPT, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
     __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
+    __shared__ R fsh[SEG ? 1 : StageS<N>::words];
+    const ConstLayout CL = const_layout(N, a.ny);
+    if constexpr (!SEG) {
+        stage_smoother_consts<N, R>(a, CL, fsh);
+        __syncthreads();
+    }
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
     const int64_t kw = (gt - lane) * EPT;
     if (kw >= a.total) return;
     R* st = stage[threadIdx.x >> 6];
-    const ConstLayout CL = const_layout(N, a.ny);
     const R* m = static_cast<const R*>(a.m);
     const R* P = static_cast<const R*>(a.P);
     R* mso = static_cast<R*>(a.ms);
@@ -915,9 +1005,11 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
         }
         if (k <= klast) {
             seq_backward<SEG>(a, s, k);
-            const R* cst = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k);
+            const R* Fp;
+            if constexpr (SEG) Fp = static_cast<const R*>(a.consts) + const_offset<SEG>(a, s.b, k) + CL.F;
+            else Fp = fsh;
             SElem<N, R> el;
-            make_selem<N, R>(cst, CL, x, k == s.end - 1, el, a.status, s.b);
+            make_selem_p<N, R>(Fp, Fp + N * N, Fp + 2 * N * N, x, k == s.end - 1, el, a.status, s.b);
             scarry<N, R, SEG>(el, Y);
         }
         wave_store_moments_rev<N, R>(mso, Pso, kw, e, EPT, EPT, a.total, st, lane, Y);
