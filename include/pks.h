@@ -265,6 +265,23 @@ pks_status pks_autotune(int32_t nx, int32_t ny, int32_t B, int64_t total, pks_pr
 pks_status pks_read_numeric_status(void *ws, int32_t *first_bad_sequence, void *stream);
 
 /*
+ * Debug mode: NaN-filled workspaces.  While on, every call that takes a
+ * workspace (the noalloc entry point's static one included) first fills its
+ * floating-point regions with a pattern that reads as NaN in double and in
+ * float, on the call's stream; a kernel that read workspace memory the call
+ * has not written would then give NaN outputs.  The numeric flag and the
+ * integer tables are not filled, so pks_read_numeric_status keeps working.
+ * Results are otherwise unchanged (bitwise); the fill costs one pass over the
+ * workspace.  A plan captured while the mode is on fills its workspace at
+ * every launch.  Off by default; also switched on when the environment
+ * variable PKS_DEBUG_POISON is set to anything but "0" when first queried.
+ * pks_set_debug_poison(on): on != 0 switches it on, 0 off (process-wide;
+ * always PKS_OK).  pks_debug_poison(): 1 if on, else 0.
+ */
+pks_status pks_set_debug_poison(int32_t on);
+int32_t pks_debug_poison(void);
+
+/*
  * pks_filter_smooth without a caller workspace, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * hosts that forbid hipMalloc).  Same arguments, outputs and errors as

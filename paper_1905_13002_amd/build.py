@@ -24,6 +24,15 @@ SOURCES = (["scan_large_f64.hip", "scan_large_f32.hip", "scan_large_f64_seg.hip"
             "hmm.hip", "noalloc.hip"]
            + ["scan_small_n%d_%s.hip" % (n, t) for n in (4, 3, 2, 1) for t in ("f64", "f32")])
 
+# The small-state scan units hold the top-level kernels, whose 4 x 4 products
+# run on v_mfma_f64_4x4x4f64.  They are built with MFMA results kept in
+# ordinary VGPRs: when a workgroup size left the compiler room for the
+# accumulation registers (AGPR form), the same top-level kernel returned wrong
+# carries for every item after the first, while the VGPR form (forced here,
+# or chosen by the compiler under a tighter register budget) is exact.
+PER_FILE = {"scan_small_n%d_%s.hip" % (n, t): ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+            for n in (4, 3, 2, 1) for t in ("f64", "f32")}
+
 ARCH = os.environ.get("PKS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
@@ -37,7 +46,7 @@ def _compile(src: str, extra) -> str:
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + COMMON + list(extra) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + PER_FILE.get(src, []) + list(extra) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stdout))

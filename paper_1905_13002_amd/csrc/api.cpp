@@ -3,8 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -80,6 +82,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.consts32 = o; o = align256(o + sizeof(float) * (size_t)CL.words * nmodels);
     L.scratch = o; o = align256(o + sizeof(double) * (size_t)precompute_scratch_words(nx, ny) * nmodels);
     L.model_fail = o; o = align256(o + sizeof(int32_t) * (size_t)nmodels);
+    L.top_flags = o; o = align256(o + sizeof(int32_t) * (size_t)(1 + kTopMaxWorkgroups));
     // small-state scan: level 0 over steps, level 1 over level-0 wave aggregates
     const int64_t waves0 = round_up(std::max<int64_t>(1, ceil_div(total, 64 * kMinEpt)), 4);
     const int64_t thr0 = waves0 * 64;
@@ -97,6 +100,7 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.thr1 = o; o = align256(o + rs * fw * (size_t)thr1);
     L.agg1 = o; o = align256(o + rs * fw * (size_t)waves1);
     L.carry1 = o; o = align256(o + rs * mw * (size_t)waves1);
+    L.top_agg = o; o = align256(o + sizeof(double) * (size_t)kTopMaxWorkgroups * kTopAggWords);
     L.large = o;
     if (!small) o = align256(o + large_ws_bytes(nx, ny, total, prec));
     const int64_t nblk = ll_blocks(total);
@@ -110,6 +114,38 @@ WsLayout ws_layout(int nx, int ny, int64_t total, int32_t nmodels, pks_precision
     L.tv_offsets = o; o = align256(o + 2 * sizeof(int64_t));
     L.total = o;
     return L;
+}
+
+// ---------------------------------------------------------------------------
+// debug: NaN-filled workspace
+// ---------------------------------------------------------------------------
+namespace {
+std::atomic<int> g_poison{-1};   // -1: not yet read from the environment
+}
+
+bool debug_poison() {
+    int v = g_poison.load(std::memory_order_relaxed);
+    if (v < 0) {
+        const char* e = std::getenv("PKS_DEBUG_POISON");
+        v = (e && *e && std::strcmp(e, "0") != 0) ? 1 : 0;
+        int expected = -1;
+        if (!g_poison.compare_exchange_strong(expected, v)) v = expected;
+    }
+    return v > 0;
+}
+
+hipError_t poison_workspace(void* ws, const WsLayout& L, hipStream_t s) {
+    char* b = static_cast<char*>(ws);
+    const size_t span[4][2] = {{L.consts64, L.model_fail},      // constants, precompute scratch
+                               // (then the integer flags: model failures, top-level tickets)
+                               {L.thr, L.ll_blk_h},             // scan state, large-state region, ll arrays
+                               {L.ll_blk_v, L.ll_blk_first},
+                               {L.ll_carry, L.ll_tile_seq}};
+    for (const auto& r : span) {
+        const hipError_t e = launch_poison(b + r[0], r[1] - r[0], s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -146,6 +182,8 @@ ScanArgs make_scan_args(const pks_model& model, int32_t B, const int64_t* offset
     }
     a.status = reinterpret_cast<int*>(base + L.status);
     a.model_fail = reinterpret_cast<const int*>(base + L.model_fail);
+    a.top_flags = reinterpret_cast<int*>(base + L.top_flags);
+    a.top_agg = reinterpret_cast<double*>(base + L.top_agg);
     // a time-varying precompute flags failing steps itself: nothing to collect
     a.nmodels = tv ? 0 : (model.per_sequence ? B : 1);
     return a;
@@ -161,6 +199,10 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
         return fail(PKS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required",
                     ws_bytes, L.total);
     if (total == 0) return PKS_OK;
+    if (debug_poison()) {
+        const hipError_t pe = poison_workspace(ws, L, s);
+        if (pe != hipSuccess) return hip_fail(pe, "workspace fill");
+    }
     const bool small = small_supported(model.nx);
     const bool mixed = prec == PKS_MIXED_FP32;
     TileConfig cfg = forced ? *forced : tuned_config(model.nx, model.ny, B, total, prec);
@@ -274,6 +316,10 @@ pks_status loglik_impl(const pks_model* model, int32_t B, const int64_t* offsets
         }
         return PKS_OK;
     }
+    if (debug_poison()) {
+        const hipError_t pe = poison_workspace(ws, L, s);
+        if (pe != hipSuccess) return hip_fail(pe, "workspace fill");
+    }
     const int nmodels = tv ? (int)total : (model->per_sequence ? B : 1);
     // only G, S, e of every model (or step) are read: precompute mode 4
     hipError_t e = launch_precompute(model->nx, model->ny, nmodels, *model, ws, L, false, 4, false, s, tv,
@@ -333,6 +379,13 @@ void prof_end(hipStream_t s) {
 using namespace pks;
 
 extern "C" {
+
+pks_status pks_set_debug_poison(int32_t on) {
+    pks::g_poison.store(on ? 1 : 0);
+    return PKS_OK;
+}
+
+int32_t pks_debug_poison(void) { return pks::debug_poison() ? 1 : 0; }
 
 size_t pks_workspace_bytes(int32_t nx, int32_t ny, int64_t total_steps, int32_t B, pks_precision prec) {
     if (nx < 1 || nx > 64 || ny < 1 || ny > 64 || total_steps < 0 || B < 1) return 0;
@@ -526,6 +579,10 @@ pks_status hmm_impl(const pks_hmm* model, int64_t T, const double* L, double* al
     if ((passes & 2) && (overlaps(gamma, bK, alpha, bK) || overlaps(gamma, bK, logp, bT) ||
                          ((passes & 1) && overlaps(gamma, bK, L, bK))))
         return fail(PKS_E_ARG, "smoother output overlaps the inputs or the other outputs");
+    if (debug_poison()) {
+        const hipError_t pe = launch_poison(ws, need, s);
+        if (pe != hipSuccess) return hip_fail(pe, "workspace fill");
+    }
     const hipError_t e = launch_hmm(model->K, T, model->Pi, model->p0, L, alpha, logp, gamma, ws, passes, s);
     if (e != hipSuccess) return hip_fail(e, "HMM kernels");
     return PKS_OK;

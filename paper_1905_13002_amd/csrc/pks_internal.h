@@ -57,6 +57,11 @@ __host__ __device__ inline int precompute_scratch_words(int nx, int ny) {
     return (6 * n2 + 8 * nm + 4 * m2 + 4 * nx + 4 * ny + 15) & ~15;
 }
 
+// Device-wide top level of the small-state scans: at most this many
+// workgroups, each publishing one aggregate of kTopAggWords doubles.
+constexpr int kTopMaxWorkgroups = 64;
+constexpr int kTopAggWords = 6 * 16;
+
 constexpr int kStatusOk = 0x7fffffff;     // "no failure" value of the numeric flag
 constexpr int kStatusMagic = 0x504b5331;  // marks a prepared status word
 
@@ -79,6 +84,8 @@ struct WsLayout {
     size_t ll_blk_h, ll_blk_v, ll_blk_first, ll_carry;   // [blocks] int32 / double
     size_t ll_tile_seq;   // [total / 256 + 2] int32: sequence of each 256-step tile's first step
     size_t tv_offsets;    // int64 {0, T}: a time-varying model's one sequence, for the SEG kernels
+    size_t top_flags;     // int32 [1 + kTopMaxWorkgroups]: ticket counter and publish flags of the top level
+    size_t top_agg;       // double [kTopMaxWorkgroups][kTopAggWords]: workgroup aggregates of the top level
     size_t total;
     // sizes used for capacity checks
     int64_t cap_thr, cap_waves, cap_thr1, cap_waves1;
@@ -115,6 +122,8 @@ struct ScanArgs {
     int64_t nthr1, nwaves1;
     int ept, ept1;               // elements per thread at level 0 / 1
     int64_t large_blocks;        // large states: requested number of time blocks (0 = default)
+    int* top_flags;              // top level: ticket counter + publish flags (cleared by the kernel before it)
+    double* top_agg;             // top level: published workgroup aggregates
     int* status;
     const int* model_fail;       // [nmodels] 1 = the model's precompute failed
     int nmodels;
@@ -159,6 +168,17 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
 // passes: 1 = filter, 2 = smoother, 3 = both (fused where possible)
 hipError_t launch_small(ScanArgs a, bool mixed, int passes, hipStream_t s);
 TileConfig small_default_config(int nx, int64_t total, bool mixed);
+
+// Debug mode (pks_set_debug_poison, or the environment variable
+// PKS_DEBUG_POISON set to anything but 0): every call first fills the
+// floating-point regions of its workspace with NaN (launch_poison writes
+// [p, p + bytes), 8-byte words), so a kernel that reads workspace memory this
+// call has not written turns its outputs into NaN.
+bool debug_poison();
+hipError_t launch_poison(void* p, size_t bytes, hipStream_t s);
+// the floating-point regions of a workspace with layout L (the numeric flag,
+// the per-model failure flags and the integer tables are left alone)
+hipError_t poison_workspace(void* ws, const WsLayout& L, hipStream_t s);
 
 // marginal likelihood (loglik.hip)
 constexpr int kLLBlock = 4096;      // steps per block of the prefix sums

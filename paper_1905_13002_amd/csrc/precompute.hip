@@ -15,6 +15,8 @@
 // its constants with NaN.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pks_internal.h"
 
 namespace pks {
@@ -90,6 +92,13 @@ __global__ void k_status_prepare(int* status, int reset, int64_t* offsets, int64
     }
     offsets[0] = 0;
     offsets[1] = T;
+}
+
+// Debug fill of workspace memory: every 8-byte word becomes a pattern that is
+// a NaN whether it is read as one double or as either of its two floats.
+__global__ void k_poison(unsigned long long* p, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0xFFF80000FFF80000ull;
 }
 
 // out[m x n] = op(A) op(B); A is [m x k] (or [k x m] if ta), B is [k x n] (or [n x k] if tb)
@@ -681,6 +690,14 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
         hipLaunchKernelGGL(k_precompute, dim3(nmodels), dim3(threads), a.use_lds ? lds_bytes : 0, s, a);
     }
     prof_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_poison(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 8;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_poison, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<unsigned long long*>(p), n);
     return hipGetLastError();
 }
 

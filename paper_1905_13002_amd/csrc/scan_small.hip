@@ -25,10 +25,11 @@ hipError_t dispatch_n(ScanArgs a, int passes, hipStream_t s) {
 bool small_supported(int nx) { return nx >= 1 && nx <= 4; }
 
 // Defaults measured on MI355X (constant-velocity model, T = 2^20): FP64 is
-// fastest with 16 steps per thread and one scan level, the mixed mode with 8
-// steps per thread and a second level of one aggregate per thread.  Very long
-// inputs always get the second level so the single-workgroup top scan stays
-// short.  pks_autotune overrides these per problem shape.
+// fastest with 16 steps per thread, the mixed mode with 8, both with a single
+// scan level under the device-wide top level (which folds ceil(waves / 1024)
+// aggregates per element).  Beyond 16384 waves (E > 16 sequential folds at the
+// top) a second level of one aggregate per thread is inserted.
+// pks_autotune overrides these per problem shape.
 TileConfig small_default_config(int nx, int64_t total, bool mixed) {
     (void)nx;
     TileConfig c;
@@ -44,8 +45,7 @@ TileConfig small_default_config(int nx, int64_t total, bool mixed) {
             break;
         }
     const int64_t waves = (total + 64 * c.ept - 1) / (64 * c.ept);
-    if (mixed) c.ept1 = waves > 256 ? 1 : 0;
-    else c.ept1 = waves > 2048 ? (waves > 64 * 1024 ? 2 : 1) : 0;
+    c.ept1 = waves > 16 * 1024 ? 1 : 0;
     return c;
 }
 

@@ -10,9 +10,10 @@
 //            Kogge-Stone pattern over cross-lane shuffles (six combines); each
 //            thread stores its in-wave exclusive prefix and lane 63 the wave
 //            aggregate (struct-of-arrays in the workspace).
-//   top    : one workgroup scans the wave aggregates (sequential chunk fold,
-//            wave Kogge-Stone, cross-wave through LDS) and stores, per wave,
-//            the moments of everything before it.  Optionally one more level
+//   top    : a device-wide scan of the wave aggregates (top_epl.hpp: up to
+//            64 workgroups with one element per 16 lanes, a look-back over
+//            the published workgroup aggregates) stores, per wave, the
+//            moments of everything before it.  Optionally one more level
 //            (the same reduce over the wave aggregates) is inserted when the
 //            number of waves is large.
 //   down   : thread t applies the wave's incoming moments to its exclusive
@@ -28,6 +29,7 @@
 #pragma once
 #include "pks_internal.h"
 #include "small_ops.hpp"
+#include "top_epl.hpp"
 
 namespace pks {
 
@@ -474,6 +476,13 @@ __device__ __forceinline__ void wave_exclusive_suffix_s(const SElem<N, R>& incl,
     if (lane == 63) set_identity(ex);
 }
 
+// The top level's workgroups draw tickets and publish flags that must start
+// at zero: the kernel that runs just before each top level (a reduce kernel)
+// clears them.
+__device__ __forceinline__ void clear_top_flags(const ScanArgs& a) {
+    if (blockIdx.x == 0 && threadIdx.x <= kTopMaxWg) a.top_flags[threadIdx.x] = 0;
+}
+
 // ===========================================================================
 // FILTER
 // ===========================================================================
@@ -488,6 +497,7 @@ __device__ __forceinline__ void load_gz(const R* __restrict__ cst, const ConstLa
 // single-step elements are folded with the rank-ny form of Lemma 2.
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
+    clear_top_flags(a);
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
@@ -530,6 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
 // reduce over explicit items (level 1: the level-0 wave aggregates)
 template <int N, typename R, int EPT, bool G>
 __global__ __launch_bounds__(kBlock) void k_filter_reduce_items(ScanArgs a) {
+    clear_top_flags(a);
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t i0 = gt * EPT;
@@ -550,85 +561,6 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce_items(ScanArgs a) {
     wave_exclusive_from_inclusive_f(acc, ex, lane);
     store_f(a.thr1, a.nthr1, gt, ex);
     if (lane == 63) store_f(a.agg1, a.nwaves1, gt >> 6, acc);
-}
-
-// Kogge-Stone distance limit of a top-level wave: the threads of wave w that
-// hold items (chunk items each) number min(64, ceil(n / chunk) - 64 w); the
-// other lanes hold the identity, so levels beyond the next power of two of
-// that count change nothing.  Uniform across the wave.
-__device__ __forceinline__ int top_levels_lim(int64_t n, int64_t chunk, int wave) {
-    const int64_t used = (n + chunk - 1) / chunk - 64 * (int64_t)wave;
-    int lim = 1;
-    while (lim < 64 && lim < used) lim <<= 1;
-    return lim;
-}
-
-// top: one workgroup scans n items, writes carry[i] = moments of items 0..i-1
-// NT threads (64 or 256).  Also reports models whose precompute failed
-// (model_fail[b] != 0) to the numeric flag; this runs after the precompute
-// kernel has finished, so the flag was already prepared.
-template <int N, typename R, bool G, int NT>
-__global__ __launch_bounds__(NT) void k_filter_top(const void* items, int64_t n, void* carry,
-                                                   const int* model_fail, int nmodels, int* status) {
-    __shared__ R sh[NT / 64][Words<N>::F];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int b = tid; b < nmodels; b += NT)
-        if (model_fail[b]) atomicMin(status, b);
-    const int64_t chunk = (n + NT - 1) / NT;
-    const int64_t i0 = tid * chunk;
-    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
-    FElem<N, R> acc;
-    set_identity(acc);
-    for (int64_t i = i0; i < i1; ++i) {
-        FElem<N, R> x;
-        load_f(items, n, i, x);
-        if (i == i0) acc = x;
-        else fcombine<N, R, G>(acc, x, acc);
-    }
-    wave_inclusive_f<N, R, G>(acc, lane, top_levels_lim(n, chunk, wave));
-    FElem<N, R> ex;
-    wave_exclusive_from_inclusive_f(acc, ex, lane);
-    if (lane == 63) {
-        const R* w = reinterpret_cast<const R*>(&acc);
-#pragma unroll
-        for (int k = 0; k < Words<N>::F; ++k) sh[wave][k] = w[k];
-    }
-    __syncthreads();
-    // incoming moments of this thread's first item.  Every prefix that starts
-    // at the first item has A = 0 (it contains step 1), so the waves before
-    // this one and the in-wave prefix are applied in moments form.
-    Moments<N, R> X;
-    if (wave > 0) {
-        {
-            FElem<N, R> x0;
-            R* xw = reinterpret_cast<R*>(&x0);
-#pragma unroll
-            for (int k = 0; k < Words<N>::F; ++k) xw[k] = sh[0][k];
-#pragma unroll
-            for (int r = 0; r < N; ++r) X.m[r] = x0.b[r];
-#pragma unroll
-            for (int r = 0; r < tri(N); ++r) X.P[r] = x0.C[r];
-        }
-        for (int w = 1; w < wave; ++w) {
-            FElem<N, R> x;
-            R* xw = reinterpret_cast<R*>(&x);
-#pragma unroll
-            for (int k = 0; k < Words<N>::F; ++k) xw[k] = sh[w][k];
-            fcarry<N, R, G>(X, x);
-        }
-        fcarry<N, R, G>(X, ex);
-    } else {
-#pragma unroll
-        for (int r = 0; r < N; ++r) X.m[r] = ex.b[r];
-#pragma unroll
-        for (int r = 0; r < tri(N); ++r) X.P[r] = ex.C[r];
-    }
-    for (int64_t i = i0; i < i1; ++i) {
-        store_m(carry, n, i, X);
-        FElem<N, R> x;
-        load_f(items, n, i, x);
-        fcarry<N, R, G>(X, x);
-    }
 }
 
 // level-1 down: carries of the level-0 waves
@@ -721,6 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
 // arrays: each thread reads its filter prefix before writing its smoother one).
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a) {
+    clear_top_flags(a);
     constexpr bool STG = !SEG && M > 0;
     __shared__ R stage[kBlock / 64][MomStage<N, R>::WORDS];
     __shared__ R csh[STG ? kStageF : 1];
@@ -801,6 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
 // ===========================================================================
 template <int N, typename R, int EPT, bool SEG>
 __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
+    clear_top_flags(a);
     __shared__ R fsh[SEG ? 1 : StageS<N>::words];
     const ConstLayout CL = const_layout(N, a.ny);
     if constexpr (!SEG) {
@@ -843,6 +777,7 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce(ScanArgs a) {
 
 template <int N, typename R, int EPT, bool G>
 __global__ __launch_bounds__(kBlock) void k_smoother_reduce_items(ScanArgs a) {
+    clear_top_flags(a);
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t i0 = gt * EPT;
@@ -862,68 +797,6 @@ __global__ __launch_bounds__(kBlock) void k_smoother_reduce_items(ScanArgs a) {
     wave_exclusive_suffix_s(acc, ex, lane);
     store_s(a.thr1, a.nthr1, gt, ex);
     if (lane == 0) store_s(a.agg1, a.nwaves1, gt >> 6, acc);
-}
-
-// top: carry[i] = moments of items i+1..n-1 (suffix; E of the product is 0)
-template <int N, typename R, bool G, int NT>
-__global__ __launch_bounds__(NT) void k_smoother_top(const void* items, int64_t n, void* carry) {
-    __shared__ R sh[NT / 64][Words<N>::S];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t chunk = (n + NT - 1) / NT;
-    const int64_t i0 = tid * chunk;
-    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
-    SElem<N, R> acc;
-    set_identity(acc);
-    for (int64_t i = i1 - 1; i >= i0; --i) {
-        SElem<N, R> x;
-        load_s(items, n, i, x);
-        scombine<N, R, G>(x, acc, acc);
-    }
-    wave_inclusive_suffix_s<N, R, G>(acc, lane, top_levels_lim(n, chunk, wave));
-    SElem<N, R> ex;
-    wave_exclusive_suffix_s(acc, ex, lane);
-    if (lane == 0) {
-        const R* w = reinterpret_cast<const R*>(&acc);
-#pragma unroll
-        for (int k = 0; k < Words<N>::S; ++k) sh[wave][k] = w[k];
-    }
-    __syncthreads();
-    // incoming moments of this thread's last item.  Every suffix that ends at
-    // the last item has E = 0 (it contains step T), so the waves after this
-    // one and the in-wave suffix are applied in moments form.
-    constexpr int NW = NT / 64;
-    Moments<N, R> Y;
-    if (wave < NW - 1) {
-        {
-            SElem<N, R> xl;
-            R* xw = reinterpret_cast<R*>(&xl);
-#pragma unroll
-            for (int k = 0; k < Words<N>::S; ++k) xw[k] = sh[NW - 1][k];
-#pragma unroll
-            for (int r = 0; r < N; ++r) Y.m[r] = xl.g[r];
-#pragma unroll
-            for (int r = 0; r < tri(N); ++r) Y.P[r] = xl.L[r];
-        }
-        for (int w = NW - 2; w > wave; --w) {
-            SElem<N, R> x;
-            R* xw = reinterpret_cast<R*>(&x);
-#pragma unroll
-            for (int k = 0; k < Words<N>::S; ++k) xw[k] = sh[w][k];
-            scarry<N, R, G>(x, Y);
-        }
-        scarry<N, R, G>(ex, Y);
-    } else {
-#pragma unroll
-        for (int r = 0; r < N; ++r) Y.m[r] = ex.g[r];
-#pragma unroll
-        for (int r = 0; r < tri(N); ++r) Y.P[r] = ex.L[r];
-    }
-    for (int64_t i = i1 - 1; i >= i0; --i) {
-        store_m(carry, n, i, Y);
-        SElem<N, R> x;
-        load_s(items, n, i, x);
-        scarry<N, R, G>(x, Y);
-    }
 }
 
 template <int N, typename R, int EPT, bool G>
@@ -1021,25 +894,37 @@ __global__ __launch_bounds__(kBlock) void k_smoother_down(ScanArgs a) {
 // ===========================================================================
 inline int64_t blocks_for_threads(int64_t nthr) { return (nthr + kBlock - 1) / kBlock; }
 
-template <int N, typename R, bool G>
-void launch_filter_top(const void* items, int64_t n, void* carry, const ScanArgs& a, hipStream_t s) {
-    if (n <= 64) {
-        prof_begin("k_filter_top", s);
-        hipLaunchKernelGGL((k_filter_top<N, R, G, 64>), dim3(1), dim3(64), 0, s, items, n, carry, a.model_fail,
-                           a.nmodels, a.status);
-        prof_end(s);
-    } else {
-        prof_begin("k_filter_top", s);
-        hipLaunchKernelGGL((k_filter_top<N, R, G, kBlock>), dim3(1), dim3(kBlock), 0, s, items, n, carry,
-                           a.model_fail, a.nmodels, a.status);
-        prof_end(s);
-    }
+// the device-wide top level over n items (top_epl.hpp)
+inline TopArgs top_args(const void* items, int64_t n, void* carry, const ScanArgs& a) {
+    TopArgs t;
+    t.items = items;
+    t.n = n;
+    t.carry = carry;
+    const int64_t per_wg_max = (int64_t)kTopGroups * kTopMaxWg;
+    t.E = (int)((n + per_wg_max - 1) / per_wg_max);
+    if (t.E < 1) t.E = 1;
+    const int64_t per_wg = (int64_t)kTopGroups * t.E;
+    t.nwg = (int)((n + per_wg - 1) / per_wg);
+    if (t.nwg < 1) t.nwg = 1;
+    t.wg_agg = a.top_agg;
+    t.flags = a.top_flags;
+    t.model_fail = a.model_fail;
+    t.nmodels = a.nmodels;
+    t.status = a.status;
+    return t;
 }
 template <int N, typename R, bool G>
-void launch_smoother_top(const void* items, int64_t n, void* carry, hipStream_t s) {
+void launch_filter_top(const void* items, int64_t n, void* carry, const ScanArgs& a, hipStream_t s) {
+    const TopArgs t = top_args(items, n, carry, a);
+    prof_begin("k_filter_top", s);
+    hipLaunchKernelGGL((k_filter_top<N, R, G>), dim3(t.nwg), dim3(kTopThreads), 0, s, t);
+    prof_end(s);
+}
+template <int N, typename R, bool G>
+void launch_smoother_top(const void* items, int64_t n, void* carry, const ScanArgs& a, hipStream_t s) {
+    const TopArgs t = top_args(items, n, carry, a);
     prof_begin("k_smoother_top", s);
-    if (n <= 64) hipLaunchKernelGGL((k_smoother_top<N, R, G, 64>), dim3(1), dim3(64), 0, s, items, n, carry);
-    else hipLaunchKernelGGL((k_smoother_top<N, R, G, kBlock>), dim3(1), dim3(kBlock), 0, s, items, n, carry);
+    hipLaunchKernelGGL((k_smoother_top<N, R, G>), dim3(t.nwg), dim3(kTopThreads), 0, s, t);
     prof_end(s);
 }
 
@@ -1083,13 +968,13 @@ hipError_t run_smoother(ScanArgs a, hipStream_t s) {
     hipLaunchKernelGGL((k_smoother_reduce<N, R, EPT, SEG>), dim3(nb0), dim3(kBlock), 0, s, a);
     prof_end(s);
     if (a.nwaves1 == 0) {
-        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, s);
+        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, a, s);
     } else {
         const int64_t nb1 = a.nthr1 / kBlock;
         prof_begin("k_smoother_reduce_items", s);
         PKS_EPT1_SWITCH(k_smoother_reduce_items)
         prof_end(s);
-        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, s);
+        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, a, s);
         prof_begin("k_smoother_down_items", s);
         PKS_EPT1_SWITCH(k_smoother_down_items)
         prof_end(s);
@@ -1122,13 +1007,13 @@ hipError_t run_filter_smoother(ScanArgs a, hipStream_t s) {
     hipLaunchKernelGGL((k_filter_down_smooth_reduce<N, R, EPT, SEG, M>), dim3(nb0), dim3(kBlock), 0, s, a);
     prof_end(s);
     if (a.nwaves1 == 0) {
-        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, s);
+        launch_smoother_top<N, R, SEG>(a.agg, a.nwaves, a.carry, a, s);
     } else {
         const int64_t nb1 = a.nthr1 / kBlock;
         prof_begin("k_smoother_reduce_items", s);
         PKS_EPT1_SWITCH(k_smoother_reduce_items)
         prof_end(s);
-        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, s);
+        launch_smoother_top<N, R, SEG>(a.agg1, a.nwaves1, a.carry1, a, s);
         prof_begin("k_smoother_down_items", s);
         PKS_EPT1_SWITCH(k_smoother_down_items)
         prof_end(s);

@@ -30,7 +30,8 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_workspace_bytes_tv", "pks_filter_tv", "pks_smooth_tv", "pks_filter_smooth_tv", "pks_loglik_tv",
             "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched",
             "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth",
-            "pks_filter_smooth_noalloc", "pks_noalloc_scratch_bytes"]
+            "pks_filter_smooth_noalloc", "pks_noalloc_scratch_bytes", "pks_set_debug_poison",
+            "pks_debug_poison"]
 
 
 class PksError(RuntimeError):
@@ -71,6 +72,8 @@ def _load():
         "pks_hmm_workspace_bytes": (sz, [i32, i64]),
         "pks_filter_smooth_noalloc": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
         "pks_noalloc_scratch_bytes": (sz, []),
+        "pks_set_debug_poison": (ctypes.c_int, [i32]),
+        "pks_debug_poison": (i32, []),
         "pks_hmm_filter": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, sz, vp]),
         "pks_hmm_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, sz, vp]),
         "pks_hmm_filter_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, vp, sz, vp]),
@@ -365,6 +368,16 @@ class Plan:
 def autotune(nx, ny, B, total, precision="fp64", cache_path: Optional[str] = None, stream=None):
     _check(lib.pks_autotune(nx, ny, B, int(total), _prec(precision),
                             cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def set_debug_poison(on: bool):
+    """Debug mode: every call first fills its workspace's floating-point
+    regions with NaN (see pks_set_debug_poison)."""
+    _check(lib.pks_set_debug_poison(1 if on else 0))
+
+
+def debug_poison() -> bool:
+    return bool(lib.pks_debug_poison())
 
 
 def read_numeric_status(ws: torch.Tensor, stream=None):
