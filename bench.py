@@ -239,57 +239,77 @@ COUNTER_PASSES = [
     "SQ_INSTS_VALU_FMA_F64 GRBM_GUI_ACTIVE",
     "SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_INSTS_VMEM SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU_MUL_F64 "
     "SQ_INSTS_VALU_ADD_F64 SQ_WAIT_ANY SQ_THREAD_CYCLES_VALU",
+    "SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAVES",
 ]
 
 
-def summarize_counters(base, workload_name):
-    """Write profiles/<workload>_counters.md from two rocprofv3 --pmc
-    databases under base/pmc_a and base/pmc_b (median over dispatches):
-    instruction mix and how busy the vector unit is, per kernel."""
+def counter_commands(wid, base="gpurun_out"):
+    """The rocprofv3 passes behind profiles/<workload>_counters.md (one timed
+    step each; the large-state workloads without the oracle check)."""
+    extra = " --steps 2 --warmup 1" if wid == 2 else " --workload %d --steps 1 --warmup 0 --no-check" % wid
+    return ["rocprofv3 --pmc %s -d %s/pmc_%s -o pmc -- python bench.py%s --no-cpu-baseline"
+            % (cnt, base, "abc"[i], extra) for i, cnt in enumerate(COUNTER_PASSES)]
+
+
+def summarize_counters(base, wid):
+    """Write profiles/<workload>_counters.md from the rocprofv3 --pmc
+    databases under base/pmc_a, pmc_b and pmc_c (median over dispatches):
+    instruction mix, how busy the vector unit and the matrix cores are, LDS
+    bank conflicts, per kernel."""
+    from paper_1905_13002_amd import workloads as wl
+    workload_name = wl.WORKLOAD_NAMES[wid]
     import collections
     import re
     import sqlite3
 
     def short(n):
-        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "")
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "").replace("lg::", "")
         m = re.match(r"void (\w+<[^>]*>)", n)
         return m.group(1) if m else n
 
     vals = collections.defaultdict(dict)
-    for sub in ("pmc_a", "pmc_b"):
+    for sub in ("pmc_a", "pmc_b", "pmc_c"):
         d = os.path.join(base, sub)
+        if not os.path.isdir(d):
+            continue
         dbs = [f for f in sorted(os.listdir(d)) if f.endswith("_results.db")]
         cur = sqlite3.connect(os.path.join(d, dbs[0])).cursor()
         acc = collections.defaultdict(list)
         for kn, cn, v in cur.execute("select kernel_name, counter_name, value from counters_collection"):
             acc[(short(kn), cn)].append(float(v))
         for (kn, cn), v in acc.items():
-            vals[kn][cn] = statistics.median(v)
+            vals[kn][cn + ("_C" if sub == "pmc_c" and cn in ("SQ_WAVE_CYCLES", "SQ_WAVES") else "")] = \
+                statistics.median(v)
     lines = ["# Counter profile: %s" % workload_name, "",
              "`rocprofv3 --pmc` on one MI355X, library built from this tree; two passes (repository root):", "",
              "```"]
-    for i, cnt in enumerate(COUNTER_PASSES):
-        lines.append("rocprofv3 --pmc %s -d gpurun_out/pmc_%s -o pmc -- python bench.py --steps 2 --warmup 1 "
-                     "--no-cpu-baseline" % (cnt, "ab"[i]))
-    lines += ["python bench.py --summarize-counters gpurun_out", "```", "",
+    lines += counter_commands(wid, base)
+    lines += ["python bench.py --summarize-counters %s%s" % (base, "" if wid == 2 else " --workload %d" % wid),
+              "```", "",
               "Per kernel (median over dispatches): `VALU/wave` = SQ_INSTS_VALU / SQ_WAVES; `VALU busy` = "
               "SQ_ACTIVE_INST_VALU x 4 / (SQ_WAVE_CYCLES x 4): the share of a wave's lifetime spent issuing "
               "vector instructions (both counters in quad-cycles); `FMA64 share` = SQ_INSTS_VALU_FMA_F64 / "
-              "SQ_INSTS_VALU; `wait` = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES.  Register counts and waves per SIMD "
-              "are the compiler's (`hipcc -Rpass-analysis=kernel-resource-usage`).", "",
-              "| kernel | waves | VALU/wave | VALU busy | FMA64 share | LDS/wave | VMEM/wave | wait | LDS bank conflicts |",
-              "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+              "SQ_INSTS_VALU; `wait` = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; `MFMA/wave` = SQ_INSTS_MFMA / "
+              "SQ_WAVES; `MFMA busy` = SQ_VALU_MFMA_BUSY_CYCLES / SQ_WAVE_CYCLES (third pass: matrix-core busy "
+              "cycles per wave cycle); `bank conflicts/LDS` = "
+              "SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS instruction).  Register counts "
+              "and waves per SIMD are the compiler's (`hipcc -Rpass-analysis=kernel-resource-usage`).", "",
+              "| kernel | waves | VALU/wave | VALU busy | FMA64 share | LDS/wave | VMEM/wave | wait | "
+              "bank conflicts/LDS | MFMA/wave | MFMA busy |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for kn in sorted(vals):
         if not kn.startswith("k_"):
             continue
         v = vals[kn]
         w = max(1.0, v.get("SQ_WAVES", 1.0))
         wc = max(1.0, v.get("SQ_WAVE_CYCLES", 1.0))
-        lines.append("| `%s` | %d | %.0f | %.2f | %.2f | %.0f | %.0f | %.2f | %.0f |" % (
+        lines.append("| `%s` | %d | %.0f | %.2f | %.2f | %.0f | %.0f | %.2f | %.2f | %.0f | %.2f |" % (
             kn, w, v.get("SQ_INSTS_VALU", 0) / w, v.get("SQ_ACTIVE_INST_VALU", 0) / wc,
             v.get("SQ_INSTS_VALU_FMA_F64", 0) / max(1.0, v.get("SQ_INSTS_VALU", 1.0)),
             v.get("SQ_INSTS_LDS", 0) / w, v.get("SQ_INSTS_VMEM", 0) / w, v.get("SQ_WAIT_INST_ANY", 0) / wc,
-            v.get("SQ_LDS_BANK_CONFLICT", 0)))
+            v.get("SQ_LDS_BANK_CONFLICT", 0) / max(1.0, v.get("SQ_INSTS_LDS", 1.0)),
+            v.get("SQ_INSTS_MFMA", 0) / w,
+            v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) / max(1.0, v.get("SQ_WAVE_CYCLES_C", v.get("SQ_WAVE_CYCLES", 1.0)))))
     with open(os.path.join(ROOT, "profiles", "%s_counters.md" % workload_name), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("wrote profiles/%s_counters.md" % workload_name)
@@ -364,6 +384,8 @@ def main():
     ap.add_argument("--op", default="filter_smooth", choices=["filter_smooth", "loglik", "hmm"],
                     help="what a timed step runs (default: the filter + smoother pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the comparison with the oracle (profiling runs; the line then has no max_rel_err)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters under rocprofv3)")
@@ -378,7 +400,7 @@ def main():
         summarize_profiles(args.summarize_profiles, "cv_T1048576")
         return
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters, "cv_T1048576")
+        summarize_counters(args.summarize_counters, args.workload)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.workload, args.op)
@@ -474,6 +496,9 @@ def main():
     errs = {}
     for prec in ("fp64", "mixed"):
         out = results[prec]["out"]
+        if args.no_check:
+            errs[prec] = {k: float("nan") for k in ("m", "P", "ms", "Ps")}
+            continue
         if not batched:
             ref = ref_for(prec)
             errs[prec] = {k: wl.max_rel_err(out[k], ref[k]) for k in ("m", "P", "ms", "Ps")}

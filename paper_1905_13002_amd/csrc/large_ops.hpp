@@ -168,7 +168,7 @@ template <typename R>
 __device__ __forceinline__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
                       R alpha = R(1), const R* D = nullptr, int ldd = 0) {
     const int threads = blockDim.x;
-    if (m >= 32 && n >= 32) {
+    if (m >= 16 && n >= 16) {
         if constexpr (sizeof(R) == 4)
             gemm_mfma_f32(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
         else
