@@ -161,7 +161,7 @@ __device__ __noinline__ void gemm_mfma_f64(double* C, int ldc, const double* A, 
 }
 
 // Products of the storage type.  Products with both output dimensions at
-// least 32 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
+// least 16 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
 // everything else on the vector units, with the largest register block that
 // still gives every thread of the workgroup a block of C.
 template <typename R>

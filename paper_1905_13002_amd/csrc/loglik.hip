@@ -25,9 +25,14 @@
 //                            steps are loaded coalesced and staged through LDS
 //                            (odd row stride), the next tile's loads in flight
 //                            while the current one is evaluated.
-//   k_ll_wave<R,SEG>         any size: one wavefront per step; P_{k-1}, G P_{k-1}
-//                            and S in LDS, the Cholesky factorisation and the
-//                            forward substitution row-parallel across lanes.
+//   k_ll_wave<R,SEG>         nx, ny < 32 beyond the above: one wavefront per
+//                            step; P_{k-1}, G P_{k-1} and S in LDS, the Cholesky
+//                            factorisation and the forward substitution
+//                            row-parallel across lanes.
+//   k_ll_large<R,SEG>        nx or ny >= 32: one workgroup per step (persistent);
+//                            G P_{k-1} and S0 + (G P_{k-1}) G^T on the matrix
+//                            cores, S factorised and r^T S^-1 r solved with the
+//                            register / blocked Cholesky of the large-state scans.
 //   k_ll_tile_seq            batched: the sequence of every tile's first step
 //                            (one search each), so that a lane only searches
 //                            between two neighbouring entries.
@@ -46,6 +51,7 @@
 
 #include <algorithm>
 
+#include "large_ops.hpp"
 #include "pks_internal.h"
 
 namespace pks {
@@ -584,6 +590,79 @@ void launch_small_kernel(const LLArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_ll_small<NX, NY, R, SEG>), dim3((unsigned)grid), dim3(kLLThreads), 0, s, a, ntiles);
 }
 
+// ---------------------------------------------------------------------------
+// nx or ny >= 32: one workgroup per step
+// ---------------------------------------------------------------------------
+// LDS: P_{k-1} [nx][nx] (widened to double), T = G P [ny][nx], S [ny][ny],
+// G [ny][nx] (staged when the step's model differs from the previous step's),
+// m [nx], r [ny], x [ny].  S0 and e are read from the constants.
+__host__ __device__ inline int ll_large_words(int nx, int ny) {
+    return nx * nx + 2 * ny * nx + ny * ny + nx + 2 * ny;
+}
+
+template <typename R, bool SEG>
+__global__ __launch_bounds__(256) void k_ll_large(LLArgs a) {
+    extern __shared__ __align__(16) double lds_ll[];
+    __shared__ int flag_sh;
+    const int nx = a.nx, ny = a.ny, n2 = nx * nx, tid = threadIdx.x, nt = blockDim.x;
+    double* P = lds_ll;
+    double* T = P + n2;
+    double* S = T + ny * nx;
+    double* G = S + ny * ny;
+    double* m = G + ny * nx;
+    double* r = m + nx;
+    double* x = r + ny;
+    const R* gm = static_cast<const R*>(a.m);
+    const R* gP = static_cast<const R*>(a.P);
+    const R* gy = static_cast<const R*>(a.y);
+    const double* staged = nullptr;   // constants whose G is in LDS
+    for (int64_t k = blockIdx.x; k < a.total; k += gridDim.x) {
+        int64_t start;
+        const int64_t tile = k / kLLThreads;
+        const int b = SEG ? seq_between<true>(a.offsets, a.tile_seq[tile], a.tile_seq[tile + 1], k, start)
+                          : seq_between<false>(a.offsets, 0, 0, k, start);
+        const double* cst = a.consts64 + a.cstride * b + k * a.sstride;
+        if (cst != staged) {
+            for (int i = tid; i < ny * nx; i += nt) G[i] = cst[a.cG + i];
+            staged = cst;
+        }
+        if (k == start) {
+            const int64_t ps = a.per_sequence ? b : 0;
+            for (int i = tid; i < n2; i += nt) P[i] = a.P0[ps * n2 + i];
+            for (int i = tid; i < nx; i += nt) m[i] = a.m0[ps * nx + i];
+        } else {
+            for (int i = tid; i < n2; i += nt) P[i] = (double)gP[(k - 1) * n2 + i];
+            for (int i = tid; i < nx; i += nt) m[i] = (double)gm[(k - 1) * nx + i];
+        }
+        __syncthreads();
+        large::gemmR<double>(T, nx, G, nx, false, P, nx, false, ny, nx, nx);    // T = G P (ends with a barrier)
+        for (int i = tid; i < ny; i += nt) {                                     // r = y - G m - e
+            Acc2 v{(double)gy[k * ny + i], 0.0};
+            acc2_add(v, -cst[a.ce + i]);
+            for (int l = 0; l < nx; ++l) acc2_sub_prod(v, G[i * nx + l], m[l]);
+            r[i] = x[i] = acc2_value(v);
+        }
+        large::gemmR<double>(S, ny, T, nx, false, G, nx, true, ny, ny, nx, 1.0, cst + a.cS, ny);   // S = S0 + T G^T
+        const bool ok = large::cholesky(S, ny, ny, &flag_sh);                  // L below, L^T above the diagonal
+        large::chol_solve(S, ny, ny, x, 1, 1);                                   // x = S^-1 r
+        __syncthreads();
+        if (tid == 0) {
+            double quad = 0.0, logdet = 0.0;
+            for (int i = 0; i < ny; ++i) {
+                quad = fma(r[i], x[i], quad);
+                logdet += log(S[i * ny + i]);
+            }
+            double ll = -0.5 * (ny * kLog2Pi + quad) - logdet;
+            if (!ok) {
+                ll = __builtin_nan("");
+                atomicMin(a.status, b);
+            }
+            a.step[k] = ll;
+        }
+        __syncthreads();                                                          // LDS reuse by the next step
+    }
+}
+
 template <int NX, typename R, bool SEG>
 bool launch_small_ny(int ny, const LLArgs& a, hipStream_t s) {
     switch (ny) {
@@ -609,7 +688,12 @@ bool launch_small_ll(const LLArgs& a, hipStream_t s) {
 template <typename R, bool SEG>
 void launch_steps(const LLArgs& a, hipStream_t s) {
     prof_begin("k_ll_steps", s);
-    if (!(a.nx <= 4 && a.ny <= 4 && launch_small_ll<R, SEG>(a, s))) {
+    if (a.nx >= 32 || a.ny >= 32) {
+        const size_t lds = sizeof(double) * (size_t)ll_large_words(a.nx, a.ny);
+        const int threads = 256;
+        const unsigned grid = (unsigned)std::min<int64_t>(a.total, 4096);
+        hipLaunchKernelGGL((k_ll_large<R, SEG>), dim3(grid), dim3(threads), lds, s, a);
+    } else if (!(a.nx <= 4 && a.ny <= 4 && launch_small_ll<R, SEG>(a, s))) {
         const size_t per_wave = sizeof(double) * (size_t)ll_wave_words(a.nx, a.ny);
         int waves = (int)std::min<size_t>(4, std::max<size_t>(1, (64 * 1024) / per_wave));
         const int64_t want = (a.total + waves - 1) / waves;

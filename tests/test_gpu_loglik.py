@@ -201,7 +201,8 @@ def test_loglik_random_small_models(pks, nx, ny, precision):
                                      (33, 17, 150), (64, 32, 120), (64, 64, 40)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_loglik_one_wave_per_step(pks, nx, ny, T, precision):
-    """Sizes outside nx, ny <= 4 take the one-wavefront-per-step kernel."""
+    """Sizes outside nx, ny <= 4: the one-wavefront-per-step kernel, and from
+    nx or ny = 32 on the one-workgroup-per-step kernel with matrix-core products."""
     rng = np.random.default_rng(400 + nx + 3 * ny)
     model = wl.random_stable_model(nx, ny, rng, radius=0.95)
     y, _ = wl.simulate(model, T, rng)
@@ -416,6 +417,43 @@ def test_loglik_cv_T2pow23(pks):
     # partial sums (positions reach 4e8 here, so the factors themselves carry
     # the FP64 moments' rounding; their bar is checked at T = 2^20)
     assert np.all(np.abs(np.cumsum(steps) - cum) <= 1e-12 * np.cumsum(np.abs(steps)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_loglik_batched_per_sequence_matrix_core_sizes(pks, precision):
+    """Per-sequence models through the one-workgroup-per-step kernel (nx = 40,
+    ny = 33: products on the matrix cores with ragged 16 x 16 tiles), empty and
+    one-step sequences, u and d; a sequence whose innovation covariance is not
+    positive definite gives NaN and is named by the flag, the others are
+    unaffected."""
+    rng = np.random.default_rng(23)
+    B = 6
+    models = [wl.random_stable_model(40, 33, rng, radius=0.9, with_offsets=True) for _ in range(B)]
+    lengths = [60, 0, 1, 33, 47, 20]
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 33)) for mo, L in zip(models, lengths)]
+    stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+    model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), stack("u"),
+                     stack("d"))
+    y = np.concatenate(ys)
+    check_ll(pks, model, y, precision, offsets=offsets, per_sequence=True, what="per-sequence 40x33")
+    if precision != "fp64":
+        return
+    R = model.R.copy()
+    R[4] = -100.0 * np.eye(33)
+    bad = wl.Model(model.F, model.Q, model.H, R, model.m0, model.P0, model.u, model.d)
+    dm = pks.to_device(bad, per_sequence=True)
+    od = torch.as_tensor(offsets).cuda()
+    yd = torch.as_tensor(y).cuda()
+    good = wl.Model(model.F, model.Q, model.H, model.R, model.m0, model.P0, model.u, model.d)
+    m, P = pks.filter_batched(pks.to_device(good, per_sequence=True), od, yd, "fp64")
+    ws = pks.workspace(40, 33, int(offsets[-1]), B)
+    ll, tot = pks.loglik_batched(dm, od, yd, m, P, "fp64", ws=ws)
+    ok, first = pks.read_numeric_status(ws)
+    assert not ok and first == 4
+    s4 = slice(int(offsets[4]), int(offsets[5]))
+    assert torch.isnan(ll[s4]).all() and torch.isnan(tot[4])
+    assert not torch.isnan(tot[[0, 1, 2, 3, 5]]).any()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

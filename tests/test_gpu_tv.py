@@ -120,7 +120,7 @@ def test_tv_separate_calls(pks, precision):
         assert wl.max_rel_err(out[k], ref[k], floor) <= TOL[precision], k
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 2), (6, 3)])
+@pytest.mark.parametrize("nx,ny", [(4, 2), (6, 3), (17, 16), (33, 32)])
 def test_tv_loglik(pks, nx, ny):
     """The per-step factors and partial sums of a time-varying model (FP64),
     each step's prediction from its own F_{k-1}, Q_{k-1}, u_{k-1}, H_k, R_k, d_k."""
