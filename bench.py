@@ -345,7 +345,7 @@ def summarize_trace(base, wid, op="filter_smooth"):
         if n.startswith("k_"):
             rows.append((n, int(calls), float(avg), float(tot)))
     cmd = ("rocprofv3 --kernel-trace --stats -d %s -o trace -- python bench.py --workload %d%s --steps 2 "
-           "--warmup 1 --no-cpu-baseline" % (base.rstrip("/"), wid, opt))
+           "--warmup 1 --no-cpu-baseline --no-check" % (base.rstrip("/"), wid, opt))
     what = ("marginal likelihood (filter, then factors + partial sums + totals)" if ll else
             ("discrete-state filter + smoother (FP64)" if hmm else "filter + smoother"))
     lines = ["# Kernel profile: %s, %s" % (name, what), "",
@@ -427,7 +427,7 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    if args.op == "hmm":
+    if args.op == "hmm" or args.workload == 7:   # workload 7 is the discrete-state model
         bench_hmm(args, np, torch, oracle, pks, wl)
         return
     w = wl.workload(args.workload)
@@ -669,10 +669,15 @@ def bench_hmm(args, np, torch, oracle, pks, wl):
     prof = pks.profile_stop()
     torch.cuda.synchronize()
     kern = {k: tot / max(1, n) for k, (tot, n) in prof.items()}
-    ref = oracle.hmm_fb(w.Pi, w.p0, w.L)
-    a, g, lp = alpha.cpu().numpy(), gamma.cpu().numpy(), logp.cpu().numpy()
-    errs = {"alpha_abs": float(np.max(np.abs(a - ref["alpha"]))), "gamma_abs": float(np.max(np.abs(g - ref["gamma"]))),
-            "logp_rel": float(np.max(np.abs(lp - np.cumsum(ref["ll"])) / np.maximum(1.0, np.cumsum(np.abs(ref["ll"])))))}
+    if args.no_check:
+        errs = {"alpha_abs": float("nan"), "gamma_abs": float("nan"), "logp_rel": float("nan")}
+    else:
+        ref = oracle.hmm_fb(w.Pi, w.p0, w.L)
+        a, g, lp = alpha.cpu().numpy(), gamma.cpu().numpy(), logp.cpu().numpy()
+        errs = {"alpha_abs": float(np.max(np.abs(a - ref["alpha"]))),
+                "gamma_abs": float(np.max(np.abs(g - ref["gamma"]))),
+                "logp_rel": float(np.max(np.abs(lp - np.cumsum(ref["ll"])) /
+                                         np.maximum(1.0, np.cumsum(np.abs(ref["ll"])))))}
     flops_step = 2 * 2.0 * K ** 3
     ach = flops_step * T / sec / 1e12
     dom = max(kern, key=kern.get)
@@ -732,6 +737,8 @@ def bench_loglik(args, w, np, torch, oracle, pks, wl, dev):
 
     # accuracy: the oracle's factors summed per sequence (sampled sequences when batched)
     sample = list(range(B)) if not batched else sorted(set([0, B - 1] + list(range(0, B, max(1, B // 64)))))
+    if args.no_check:
+        sample = []
     errs = {}
     for prec in ("fp64", "mixed"):
         yy = w.y if prec == "fp64" else w.y.astype(np.float32).astype(np.float64)
