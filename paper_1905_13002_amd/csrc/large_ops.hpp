@@ -162,18 +162,20 @@ __device__ __noinline__ void gemm_mfma_f64(double* C, int ldc, const double* A, 
 
 // Products of the storage type.  Products with both output dimensions at
 // least 16 (dense enough to fill 16 x 16 tiles) run on the matrix cores;
+// `sync` = false leaves out the closing workgroup barrier, for a product
+// followed by others that neither read its output nor write its operands.
 // everything else on the vector units, with the largest register block that
 // still gives every thread of the workgroup a block of C.
 template <typename R>
 __device__ __forceinline__ void gemmR(R* C, int ldc, const R* A, int lda, bool ta, const R* B, int ldb, bool tb, int m, int n, int k,
-                      R alpha = R(1), const R* D = nullptr, int ldd = 0) {
+                      R alpha = R(1), const R* D = nullptr, int ldd = 0, bool sync = true) {
     const int threads = blockDim.x;
     if (m >= 16 && n >= 16) {
         if constexpr (sizeof(R) == 4)
             gemm_mfma_f32(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
         else
             gemm_mfma_f64(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
-        __syncthreads();
+        if (sync) __syncthreads();
         return;
     }
     if (((m + 3) >> 2) * ((n + 3) >> 2) >= threads)
@@ -182,7 +184,7 @@ __device__ __forceinline__ void gemmR(R* C, int ldc, const R* A, int lda, bool t
         gemm_blocks<2, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
     else
         gemm_blocks<1, R>(C, ldc, A, lda, ta, B, ldb, tb, m, n, k, alpha, D, ldd);
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 // Walks the row-major (row, col) pairs of a range with `cols` columns that
@@ -251,7 +253,7 @@ __device__ __forceinline__ void gemm_blocks_acc64(TC* C, int ldc, const TA* A, i
 
 template <typename TA, typename TB, typename TC>
 __device__ __forceinline__ void gemm_acc64(TC* C, int ldc, const TA* A, int lda, const TB* B, int ldb, int m, int n, int k,
-                           double alpha, const TC* D = nullptr, int ldd = 0) {
+                           double alpha, const TC* D = nullptr, int ldd = 0, bool sync = true) {
     const int threads = blockDim.x;
     if (((m + 3) >> 2) * ((n + 3) >> 2) >= threads)
         gemm_blocks_acc64<4>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
@@ -259,7 +261,7 @@ __device__ __forceinline__ void gemm_acc64(TC* C, int ldc, const TA* A, int lda,
         gemm_blocks_acc64<2>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
     else
         gemm_blocks_acc64<1>(C, ldc, A, lda, B, ldb, m, n, k, alpha, D, ldd);
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 // The next (up to) four pairs of a walk over `rows` rows; returns how many.
@@ -304,13 +306,13 @@ __device__ __forceinline__ void wave_axpy_rows(const double* Lc, int sl, double 
 
 // out = (X + X^T)/2 + D (symmetrisation in double); out may alias D, not X
 template <typename R>
-__device__ __forceinline__ void sym_add(R* out, const R* X, const R* D, int n) {
+__device__ __forceinline__ void sym_add(R* out, const R* X, const R* D, int n, bool sync = true) {
     for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
         const int i = it.r, j = it.c;
         const int idx = it.r * it.cols + it.c;
         out[idx] = R(0.5 * (double(X[i * n + j]) + double(X[j * n + i])) + (D ? double(D[idx]) : 0.0));
     }
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 template <typename T, typename U>
@@ -328,14 +330,14 @@ __device__ __forceinline__ void fill(T* dst, T v, int count) {
 // y[m] = op(A) x (+ d), A [m x k] (or [k x m] if ta)
 template <typename R>
 __device__ __forceinline__ void gemv(R* y, const R* A, int lda, bool ta, const R* x, int m, int k, const R* d = nullptr,
-                     R alpha = R(1)) {
+                     R alpha = R(1), bool sync = true) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
         R s = R(0);
 #pragma unroll 8
         for (int l = 0; l < k; ++l) s = fma(ta ? A[l * lda + i] : A[i * lda + l], x[l], s);
         y[i] = alpha * s + (d ? d[i] : R(0));
     }
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 // Makes the LDS and global writes of one wave visible to its other lanes (a

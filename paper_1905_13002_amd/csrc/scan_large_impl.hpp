@@ -226,14 +226,18 @@ __device__ __forceinline__ void fcombine_tail(const Ctx& c, const R* ei, const R
     R* X3 = c.r<R>(c.ar.X3);
     R* w = c.r<R>(c.ar.w);
     R* JA = c.r<R>(c.ar.JA);
-    gemv<R>(out + c.fl.eta, X1, n, true, w, n, n, ei + c.fl.eta);
-    gemmR<R>(Z, n, X1, n, true, JA, n, false, n, n, n);
-    sym_add<R>(out + c.fl.J, Z, ei + c.fl.J, n);
-    gemmR<R>(out + c.fl.A, n, Aj, n, false, X1, n, false, n, n, n);
-    gemv<R>(out + c.fl.b, Aj, n, false, x2, n, n, bj);
+    // five independent pieces, one barrier: each reads only scratch and the
+    // constants and writes a buffer none of the others touches (eta, A, b of
+    // `out` are written in place element by element where out is ei)
+    gemv<R>(out + c.fl.eta, X1, n, true, w, n, n, ei + c.fl.eta, R(1), false);
+    gemmR<R>(Z, n, X1, n, true, JA, n, false, n, n, n, R(1), nullptr, 0, false);
+    gemmR<R>(out + c.fl.A, n, Aj, n, false, X1, n, false, n, n, n, R(1), nullptr, 0, false);
+    gemv<R>(out + c.fl.b, Aj, n, false, x2, n, n, bj, R(1), false);
     gemmR<R>(T, n, Aj, n, false, X3, n, false, n, n, n);
-    gemmR<R>(Z, n, T, n, false, Aj, n, true, n, n, n);
-    sym_add<R>(out + c.fl.C, Z, Cj, n);
+    // J from Z while (A_j X3) A_j^T goes to X3, which the last product consumed
+    sym_add<R>(out + c.fl.J, Z, ei + c.fl.J, n, false);
+    gemmR<R>(X3, n, T, n, false, Aj, n, true, n, n, n);
+    sym_add<R>(out + c.fl.C, X3, Cj, n);
 }
 
 // full Lemma 2: out = ei (x) ej; ej given by its parts (matrices may live in
@@ -246,7 +250,7 @@ __device__ __forceinline__ void fcombine_wg(const Ctx& c, const R* ei, const R* 
     R* Z = c.r<R>(c.ar.Z);
     R* v = c.r<R>(c.ar.x2);
     // M = I + C_i J_j (products in R)
-    gemmR<R>(Z, n, ei + c.fl.C, n, false, Jj, n, false, n, n, n);
+    gemmR<R>(Z, n, ei + c.fl.C, n, false, Jj, n, false, n, n, n, R(1), nullptr, 0, false);
     gemv<R>(v, ei + c.fl.C, n, false, etaj, n, n, ei + c.fl.b);          // b_i + C_i eta_j
     for (Walk2 it(threadIdx.x, blockDim.x, n); it.r < n; it.next()) {
         const int r = it.r, q = it.c;
@@ -270,7 +274,7 @@ __device__ __forceinline__ void fcombine_wg(const Ctx& c, const R* ei, const R* 
     for (int r = threadIdx.x; r < n; r += blockDim.x) x2[r] = R(aug[r * lda + 2 * n]);
     __syncthreads();
     // w = eta_j - J_j b_i ; JA = J_j A_i
-    gemv<R>(c.r<R>(c.ar.w), Jj, n, false, ei + c.fl.b, n, n, etaj, R(-1));
+    gemv<R>(c.r<R>(c.ar.w), Jj, n, false, ei + c.fl.b, n, n, etaj, R(-1), false);
     gemmR<R>(c.r<R>(c.ar.JA), n, Jj, n, false, ei + c.fl.A, n, false, n, n, n);
     fcombine_tail<R>(c, ei, Aj, bj, Cj, out, Z, c.r<R>(c.ar.T));
 }
@@ -286,10 +290,10 @@ __device__ __forceinline__ void fcombine_fresh_wg(const Ctx& c, const R* ei, con
     R* v = c.r<R>(c.ar.x2);
     double* sg = c.d<R>(c.ar.sig);      // Sigma [m x m]
     double* rh = sg + m * m;            // [m x (2n+1)] = [GA | Gv | Y^T]
-    gemmR<R>(Y, m, ei + c.fl.C, n, false, Gm, n, true, n, m, n);             // C_i G^T
-    gemv<R>(v, ei + c.fl.C, n, false, etaj, n, n, ei + c.fl.b);             // b_i + C_i eta_j
-    gemmR<R>(GA, n, Gm, n, false, ei + c.fl.A, n, false, m, n, n);          // G A_i
-    gemv<R>(Gv, Gm, n, false, v, m, n);                                     // G v
+    gemmR<R>(Y, m, ei + c.fl.C, n, false, Gm, n, true, n, m, n, R(1), nullptr, 0, false);   // C_i G^T
+    gemv<R>(v, ei + c.fl.C, n, false, etaj, n, n, ei + c.fl.b, R(1), false);                   // b_i + C_i eta_j
+    gemmR<R>(GA, n, Gm, n, false, ei + c.fl.A, n, false, m, n, n);                              // G A_i
+    gemv<R>(Gv, Gm, n, false, v, m, n, nullptr, R(1), false);                                   // G v
     // G C_i G^T into the X1 buffer (free until X1 is formed)
     gemmR<R>(c.r<R>(c.ar.X1), m, Gm, n, false, Y, m, false, m, m, n);
     {
@@ -314,13 +318,14 @@ __device__ __forceinline__ void fcombine_fresh_wg(const Ctx& c, const R* ei, con
     // X1 = A_i - Y T1 ; x2 = v - Y t2 ; X3 = C_i - sym(Y Zt)   (T1, t2, Zt in rh),
     // products of Y with the FP64 solution summed in double.  Y Zt goes to the
     // JA buffer, free until JA is formed.
-    gemm_acc64<R, double, R>(X1, n, Y, m, rh, rhs, n, n, m, -1.0, ei + c.fl.A, n);
-    gemm_acc64<R, double, R>(x2, 1, Y, m, rh + n, rhs, n, 1, m, -1.0, v, 1);
+    // four independent pieces, one barrier (Gv was consumed by the right-hand side)
+    gemm_acc64<R, double, R>(X1, n, Y, m, rh, rhs, n, n, m, -1.0, ei + c.fl.A, n, false);
+    gemm_acc64<R, double, R>(x2, 1, Y, m, rh + n, rhs, n, 1, m, -1.0, v, 1, false);
     R* YZ = c.r<R>(c.ar.JA);
-    gemm_acc64<R, double, R>(YZ, n, Y, m, rh + n + 1, rhs, n, n, m, -1.0);
-    sym_add<R>(X3, YZ, ei + c.fl.C, n);
-    // w = eta_j - W (G b_i) ; JA = W (G A_i)
+    gemm_acc64<R, double, R>(YZ, n, Y, m, rh + n + 1, rhs, n, n, m, -1.0, nullptr, 0, false);
     gemv<R>(Gv, Gm, n, false, ei + c.fl.b, m, n);                           // G b_i (reuses Gv)
+    // X3 = C_i - sym(Y Zt) ; w = eta_j - W (G b_i) ; then JA = W (G A_i) over YZ
+    sym_add<R>(X3, YZ, ei + c.fl.C, n, false);
     gemv<R>(c.r<R>(c.ar.w), Wm, m, false, Gv, n, m, etaj, R(-1));
     gemmR<R>(c.r<R>(c.ar.JA), n, Wm, m, false, GA, n, false, n, n, m);
     // the tail's scratch reuses the Sigma / right-hand-side region and the
