@@ -72,5 +72,57 @@ def build(extra=(), jobs=None, verbose=True) -> str:
     return OUT
 
 
+def resource_usage(out_md: str) -> None:
+    """Compile every unit with the compiler's kernel-resource remarks and
+    write a table (registers, scratch, LDS, waves per SIMD per kernel) to
+    `out_md`."""
+    import re
+    rows = {}
+    for src in SOURCES:
+        if not src.endswith(".hip"):
+            continue
+        cmd = ([HIPCC] + COMMON + PER_FILE.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o",
+               os.devnull, "-Rpass-analysis=kernel-resource-usage"])
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        cur = None
+        for line in r.stdout.splitlines():
+            m = re.search(r"remark:\s+Function Name: (\S+)", line)
+            if m:
+                cur = m.group(1)
+                rows.setdefault(cur, {})
+                continue
+            m = re.search(r"remark:\s+(VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
+                          r"LDS Size \[bytes/block\]): (\d+)", line)
+            if m and cur:
+                rows[cur][m.group(1).split(" ")[0]] = int(m.group(2))
+    demangle = shutil.which("llvm-cxxfilt") or shutil.which("c++filt") or "c++filt"
+    names = list(rows)
+    try:
+        dem = subprocess.run([demangle], input="\n".join(names), stdout=subprocess.PIPE, text=True).stdout.split("\n")
+    except OSError:
+        dem = names
+    lines = ["# Kernel resources (compiler: hipcc -Rpass-analysis=kernel-resource-usage, gfx950)", "",
+             "Command: `python -m paper_1905_13002_amd.build --resource-usage profiles/kernel_resources.md`.", "",
+             "| kernel | VGPRs | AGPRs | scratch B/lane | LDS B/block | waves/SIMD |", "|---|---:|---:|---:|---:|---:|"]
+    for raw, d in sorted(zip(names, dem), key=lambda x: x[1]):
+        v = rows[raw]
+        if not v:
+            continue
+        short = re.sub(r"pks::(\(anonymous namespace\)::|lg::)?", "", d.strip() or raw)
+        short = re.sub(r"\(.*\)$", "", short).replace("void ", "")
+        # small-state scans: the nx = 4 instantiations only (nx = 1..3 are alike)
+        if re.match(r"k_(filter|smoother)_\w+<[123],", short):
+            continue
+        lines.append("| `%s` | %s | %s | %s | %s | %s |" % (short, v.get("VGPRs", ""), v.get("AGPRs", ""),
+                                                           v.get("ScratchSize", ""), v.get("LDS", ""),
+                                                           v.get("Occupancy", "")))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", out_md, file=sys.stderr)
+
+
 if __name__ == "__main__":
-    build(extra=sys.argv[1:])
+    if len(sys.argv) == 3 and sys.argv[1] == "--resource-usage":
+        resource_usage(sys.argv[2])
+    else:
+        build(extra=sys.argv[1:])
