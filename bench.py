@@ -95,7 +95,7 @@ def ll_kernel_model(nx, ny, rs):
 
 
 KERNEL_SOURCES = ["paper_1905_13002_amd/csrc/small_ops.hpp", "paper_1905_13002_amd/csrc/scan_small_impl.hpp",
-                  "paper_1905_13002_amd/csrc/precompute.hip"]
+                  "paper_1905_13002_amd/csrc/top_epl.hpp", "paper_1905_13002_amd/csrc/precompute.hip"]
 
 
 def sources_sha():
