@@ -243,6 +243,18 @@ pks_status pks_plan_create(const pks_model *model, int32_t B, const int64_t *off
                            int64_t total, const void *y, void *m, void *P, void *ms, void *Ps,
                            pks_precision prec, void *ws, size_t ws_bytes,
                            const char *tune_cache, void *stream, void **plan);
+/*
+ * The same for a time-varying model (one row of F, u, Q, H, d, R per step, as
+ * in pks_filter_tv): the per-step precompute and both passes are captured.
+ * B = 1 with offsets = NULL plans one sequence; packed sequences take
+ * offsets as in pks_filter_tv_batched.  Workspace: pks_workspace_bytes_tv of
+ * `total` steps.  Errors as pks_plan_create; more than 2^31 - 1 steps returns
+ * PKS_E_UNSUPPORTED.
+ */
+pks_status pks_plan_create_tv(const pks_model_tv *model, int32_t B, const int64_t *offsets,
+                              int64_t total, const void *y, void *m, void *P, void *ms, void *Ps,
+                              pks_precision prec, void *ws, size_t ws_bytes,
+                              const char *tune_cache, void *stream, void **plan);
 pks_status pks_plan_launch(void *plan, void *stream);
 pks_status pks_plan_destroy(void *plan);
 

@@ -41,6 +41,8 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 constexpr int kMinEpt = 4;          // smallest elements-per-thread any configuration uses
 constexpr int kMaxDim = 64;
 
+constexpr int64_t kMaxStepsTv = 0x7fffffff;   // time-varying: one constant block per step, indexed by int32
+
 int felem_words(int nx) { return nx * nx + nx + nx * (nx + 1) / 2 + nx + nx * (nx + 1) / 2; }
 int moment_words(int nx) { return nx + nx * (nx + 1) / 2; }
 
@@ -374,6 +376,18 @@ void prof_end(hipStream_t s) {
     if (g_prof.marks.back().stop) (void)hipEventRecord(g_prof.marks.back().stop, s);
 }
 
+pks_status tv_model(const pks_model_tv* t, int64_t T, pks_model* out) {
+    if (!t) return fail(PKS_E_ARG, "model is NULL");
+    if (T > kMaxStepsTv) return fail(PKS_E_UNSUPPORTED, "time-varying models support at most 2^31 - 1 steps");
+    out->nx = t->nx;
+    out->ny = t->ny;
+    out->F = t->F; out->u = t->u; out->Q = t->Q;
+    out->H = t->H; out->d = t->d; out->R = t->R;
+    out->m0 = t->m0; out->P0 = t->P0;
+    out->per_sequence = t->per_sequence;
+    return PKS_OK;
+}
+
 }  // namespace pks
 
 using namespace pks;
@@ -456,21 +470,6 @@ pks_status pks_loglik_batched(const pks_model* model, int32_t B, const int64_t* 
 }
 
 // ---- time-varying models --------------------------------------------------
-namespace {
-constexpr int64_t kMaxStepsTv = 0x7fffffff;   // one constant block per step, indexed by int32
-
-pks_status tv_model(const pks_model_tv* t, int64_t T, pks_model* out) {
-    if (!t) return fail(PKS_E_ARG, "model is NULL");
-    if (T > kMaxStepsTv) return fail(PKS_E_UNSUPPORTED, "time-varying models support at most 2^31 - 1 steps");
-    out->nx = t->nx;
-    out->ny = t->ny;
-    out->F = t->F; out->u = t->u; out->Q = t->Q;
-    out->H = t->H; out->d = t->d; out->R = t->R;
-    out->m0 = t->m0; out->P0 = t->P0;
-    out->per_sequence = t->per_sequence;
-    return PKS_OK;
-}
-}  // namespace
 
 size_t pks_workspace_bytes_tv(int32_t nx, int32_t ny, int64_t T, pks_precision prec) {
     if (nx < 1 || nx > 64 || ny < 1 || ny > 64 || T < 0 || T > kMaxStepsTv) return 0;

@@ -119,6 +119,45 @@ TileConfig tuned_config(int nx, int ny, int32_t B, int64_t total, pks_precision 
 
 using namespace pks;
 
+namespace {
+
+// Capture one filter + smoother pass of a validated request into a HIP graph
+// (on a private stream) and instantiate it.  tv: time-varying model.
+pks_status capture_plan(const pks_model& model, int32_t B, const int64_t* offsets, int64_t total, const void* y,
+                        void* m, void* P, void* ms, void* Ps, pks_precision prec, void* ws, size_t ws_bytes,
+                        const TileConfig& cfg, bool tv, void** plan) {
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        set_last_error(hipGetErrorString(e));
+        return PKS_E_HIP;
+    }
+    Plan* p = new Plan();
+    pks_status st = PKS_OK;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue(model, B, offsets, total, y, m, P, ms, Ps, prec, ws, ws_bytes, 3, &cfg, cap, tv);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cap, &g);
+        p->graph = g;
+        if (st == PKS_OK && e2 != hipSuccess) e = e2;
+    }
+    if (st == PKS_OK && e == hipSuccess && p->graph) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cap);
+    if (st != PKS_OK || e != hipSuccess || !p->exec) {
+        if (p->exec) hipGraphExecDestroy(p->exec);
+        if (p->graph) hipGraphDestroy(p->graph);
+        delete p;
+        if (st != PKS_OK) return st;
+        set_last_error(hipGetErrorString(e));
+        return PKS_E_HIP;
+    }
+    *plan = p;
+    return PKS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 pks_status pks_plan_create(const pks_model* model, int32_t B, const int64_t* offsets, int64_t total,
@@ -139,33 +178,30 @@ pks_status pks_plan_create(const pks_model* model, int32_t B, const int64_t* off
     pks_status st = validate_io(model, B, offsets, total, y, m, P, ms, Ps, prec, ws, 3, batched);
     if (st) return st;
     const TileConfig cfg = tuned_config(model->nx, model->ny, B, total, prec, tune_cache);
-    hipStream_t cap = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        set_last_error(hipGetErrorString(e));
-        return PKS_E_HIP;
+    return capture_plan(*model, B, offsets, total, y, m, P, ms, Ps, prec, ws, ws_bytes, cfg, false, plan);
+}
+
+pks_status pks_plan_create_tv(const pks_model_tv* model, int32_t B, const int64_t* offsets, int64_t total,
+                              const void* y, void* m, void* P, void* ms, void* Ps, pks_precision prec,
+                              void* ws, size_t ws_bytes, const char* tune_cache, void* stream, void** plan) {
+    set_last_error("");
+    (void)stream;
+    if (!plan) {
+        set_last_error("plan is NULL");
+        return PKS_E_ARG;
     }
-    Plan* p = new Plan();
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        st = enqueue(*model, B, offsets, total, y, m, P, ms, Ps, prec, ws, ws_bytes, 3, &cfg, cap);
-        hipGraph_t g = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(cap, &g);
-        p->graph = g;
-        if (st == PKS_OK && e2 != hipSuccess) e = e2;
+    *plan = nullptr;
+    const bool batched = offsets != nullptr;
+    if (!batched && B != 1) {
+        set_last_error("B must be 1 when offsets is NULL");
+        return PKS_E_ARG;
     }
-    if (st == PKS_OK && e == hipSuccess && p->graph) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-    hipStreamDestroy(cap);
-    if (st != PKS_OK || e != hipSuccess || !p->exec) {
-        if (p->exec) hipGraphExecDestroy(p->exec);
-        if (p->graph) hipGraphDestroy(p->graph);
-        delete p;
-        if (st != PKS_OK) return st;
-        set_last_error(hipGetErrorString(e));
-        return PKS_E_HIP;
-    }
-    *plan = p;
-    return PKS_OK;
+    pks_model mo;
+    pks_status st = tv_model(model, total, &mo);
+    if (!st) st = validate_io(&mo, B, offsets, total, y, m, P, ms, Ps, prec, ws, 3, batched);
+    if (st) return st;
+    const TileConfig cfg = tuned_config(mo.nx, mo.ny, B, total, prec, tune_cache);
+    return capture_plan(mo, B, offsets, total, y, m, P, ms, Ps, prec, ws, ws_bytes, cfg, true, plan);
 }
 
 pks_status pks_plan_launch(void* plan, void* stream) {

@@ -22,4 +22,8 @@ pks_status validate_io(const pks_model* model, int32_t B, const int64_t* offsets
 
 void set_last_error(const char* msg);
 
+// A time-varying model viewed as a pks_model whose arrays hold one row per
+// step (checks the step limit of time-varying models).
+pks_status tv_model(const pks_model_tv* t, int64_t T, pks_model* out);
+
 }  // namespace pks

@@ -31,7 +31,7 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched",
             "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth",
             "pks_filter_smooth_noalloc", "pks_noalloc_scratch_bytes", "pks_set_debug_poison",
-            "pks_debug_poison"]
+            "pks_debug_poison", "pks_plan_create_tv"]
 
 
 class PksError(RuntimeError):
@@ -94,6 +94,8 @@ def _load():
         "pks_smooth_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, sz, vp]),
         "pks_plan_create": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz,
                                            ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
+        "pks_plan_create_tv": (ctypes.c_int, [mt, i32, vp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp, sz,
+                                              ctypes.c_char_p, vp, ctypes.POINTER(vp)]),
         "pks_loglik": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz, vp]),
         "pks_loglik_batched": (ctypes.c_int, [mp, i32, vp, i64, vp, vp, vp, vp, vp, i32, ctypes.c_int, vp, sz,
                                               vp]),
@@ -199,11 +201,6 @@ def workspace_bytes(nx: int, ny: int, total: int, B: int = 1, precision="fp64", 
 def workspace(nx, ny, total, B=1, precision="fp64", device="cuda", time_varying=False) -> torch.Tensor:
     return torch.empty(workspace_bytes(nx, ny, total, B, precision, time_varying), dtype=torch.uint8,
                        device=device)
-
-
-def _single_only(model: "DeviceModel"):
-    if model.time_varying:
-        raise ValueError("time-varying models are not captured into plans: use the eager calls")
 
 
 def _ws_for(model: "DeviceModel", total, B, prec, device):
@@ -322,11 +319,11 @@ def loglik_batched(model: DeviceModel, offsets: torch.Tensor, y: torch.Tensor, m
 
 
 class Plan:
-    """A captured filter + smoother (HIP graph) bound to fixed buffers."""
+    """A captured filter + smoother (HIP graph) bound to fixed buffers; time-varying
+    models (to_device(..., time_varying=True)) capture their per-step precompute too."""
 
     def __init__(self, model: DeviceModel, y: torch.Tensor, offsets: Optional[torch.Tensor] = None,
                  precision="fp64", tune_cache: Optional[str] = None, stream=None):
-        _single_only(model)
         prec = _prec(precision)
         self.prec = prec
         self.model = model
@@ -340,10 +337,11 @@ class Plan:
         self.P = _out((total, nx, nx), prec, dev)
         self.ms = _out((total, nx), prec, dev)
         self.Ps = _out((total, nx, nx), prec, dev)
-        self.ws = workspace(nx, model.ny, total, B, prec, dev)
+        self.ws = workspace(nx, model.ny, total, B, prec, dev, model.time_varying)
         self._struct = model.struct()
         h = ctypes.c_void_p()
-        _check(lib.pks_plan_create(ctypes.byref(self._struct), B, _ptr(offsets), total, _ptr(y), _ptr(self.m),
+        create = lib.pks_plan_create_tv if model.time_varying else lib.pks_plan_create
+        _check(create(ctypes.byref(self._struct), B, _ptr(offsets), total, _ptr(y), _ptr(self.m),
                                    _ptr(self.P), _ptr(self.ms), _ptr(self.Ps), prec, _ptr(self.ws),
                                    self.ws.numel(), tune_cache.encode() if tune_cache else None, _stream(stream),
                                    ctypes.byref(h)))

@@ -262,9 +262,51 @@ def test_tv_equal_rows_batched_equals_time_invariant_batched(pks):
         assert torch.equal(x, z)
 
 
-def test_tv_rejected_by_plans(pks):
-    model = wl.random_tv_model(2, 1, 10, np.random.default_rng(1))
-    dm = pks.to_device(model, time_varying=True)
-    y = torch.zeros(10, 1, dtype=torch.float64, device="cuda")
-    with pytest.raises(ValueError):
-        pks.Plan(dm, y)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("batched", [False, True])
+def test_tv_plan(pks, precision, batched):
+    """A time-varying model captured into a plan (per-step precompute and both
+    passes in one graph): against the oracle, every replay (with eager calls
+    on the same stream in between) bitwise equal to the first, and equal to
+    the eager call where that runs the same kernels (the batched eager path
+    has no fused filter + smoother call, so in the mixed mode, where the plan
+    fuses the filter down-sweep with the smoother reduce, its smoothed moments
+    differ from the separate eager calls in rounding only)."""
+    rng = np.random.default_rng(71 + (3 if batched else 0))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    floor = "rms" if precision == "mixed" else "none"
+    if batched:
+        model, y, offsets = _packed_tv(3, 2, [300, 0, 1, 2, 700, 65], rng, True)
+        ref = _ref_packed(model, y, offsets, True, precision)
+        dm = pks.to_device(model, per_sequence=True, time_varying=True)
+        od = torch.as_tensor(offsets).cuda()
+    else:
+        model = wl.random_tv_model(4, 2, 3000, rng)
+        y, _ = wl.simulate_tv(model, rng)
+        ref = ref_tv(model, y, precision)
+        dm = pks.to_device(model, time_varying=True)
+        od = None
+    yd = torch.as_tensor(np.ascontiguousarray(y)).to("cuda", dt)
+    if batched:
+        em, eP = pks.filter_batched(dm, od, yd, precision)
+        ems, ePs = pks.smooth_batched(dm, od, em, eP, precision)
+    else:
+        em, eP, ems, ePs = pks.filter_smooth(dm, yd, precision)
+    plan = pks.Plan(dm, yd, od, precision)
+    first = None
+    same_kernels = not (batched and precision == "mixed")
+    for rep in range(3):
+        out = [t.clone() for t in plan.launch()]
+        torch.cuda.synchronize()
+        first = first or out
+        for k, g, e, f in zip(("m", "P", "ms", "Ps"), out, (em, eP, ems, ePs), first):
+            assert torch.equal(g, f), (rep, k)
+            if k in ("m", "P") or same_kernels:
+                assert torch.equal(g, e), (rep, k)
+            err = wl.max_rel_err(g.double().cpu().numpy(), ref[k], floor)
+            assert err <= TOL[precision], (rep, k, err)
+        if batched:                                   # eager work between replays
+            pks.filter_batched(dm, od, yd, precision)
+        else:
+            pks.filter(dm, yd, precision)
+    plan.close()
