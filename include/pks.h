@@ -137,6 +137,17 @@ pks_status pks_filter_smooth(const pks_model *model, int64_t T, const void *y, v
 pks_status pks_filter_batched(const pks_model *model, int32_t B, const int64_t *offsets,
                               int64_t total, const void *y, void *m, void *P,
                               pks_precision prec, void *ws, size_t ws_bytes, void *stream);
+/*
+ * Checks DEVICE offsets [B+1] against the packing rules above (offsets[0] =
+ * 0, non-decreasing, none above total, offsets[B] = total) with a kernel on
+ * `stream` and synchronises it.  PKS_OK if they hold; else PKS_E_ARG with
+ * *first_bad (host pointer, may be NULL) = the smallest offending index b.
+ * Uses the third int of the workspace `ws` (any workspace of this library,
+ * at least 256 bytes; the numeric flag is left alone).  B < 1, NULL offsets
+ * or ws: PKS_E_ARG without a launch (*first_bad = -1).
+ */
+pks_status pks_check_offsets(int32_t B, const int64_t *offsets, int64_t total, void *ws, int32_t *first_bad,
+                             void *stream);
 pks_status pks_smooth_batched(const pks_model *model, int32_t B, const int64_t *offsets,
                               int64_t total, const void *m, const void *P, void *ms, void *Ps,
                               pks_precision prec, void *ws, size_t ws_bytes, void *stream);

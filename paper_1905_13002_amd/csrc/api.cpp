@@ -394,6 +394,27 @@ using namespace pks;
 
 extern "C" {
 
+pks_status pks_check_offsets(int32_t B, const int64_t* offsets, int64_t total, void* ws, int32_t* first_bad,
+                             void* stream) {
+    g_last_error.clear();
+    if (first_bad) *first_bad = -1;
+    if (B < 1) return fail(PKS_E_ARG, "B = %d must be >= 1", B);
+    if (!offsets) return fail(PKS_E_ARG, "offsets is NULL");
+    if (!ws) return fail(PKS_E_ARG, "workspace is NULL");
+    if (total < 0) return fail(PKS_E_ARG, "negative number of steps");
+    hipStream_t s = (hipStream_t)stream;
+    // the third word of the workspace's status block (the numeric flag uses the first two)
+    int* result = static_cast<int*>(ws) + 2;
+    hipError_t e = launch_offsets_check(offsets, B, total, result, s);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, result, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "offsets check");
+    if (h == 0x7fffffff) return PKS_OK;
+    if (first_bad) *first_bad = h;
+    return fail(PKS_E_ARG, "offsets break the packing rules at index %d", h);
+}
+
 pks_status pks_set_debug_poison(int32_t on) {
     pks::g_poison.store(on ? 1 : 0);
     return PKS_OK;

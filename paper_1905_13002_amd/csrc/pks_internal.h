@@ -180,6 +180,10 @@ hipError_t launch_poison(void* p, size_t bytes, hipStream_t s);
 // the per-model failure flags and the integer tables are left alone)
 hipError_t poison_workspace(void* ws, const WsLayout& L, hipStream_t s);
 
+// Check of packed-sequence offsets (device [B+1]) against the packing rules;
+// *result (device int) becomes the smallest offending index, or 0x7fffffff.
+hipError_t launch_offsets_check(const int64_t* offsets, int B, int64_t total, int* result, hipStream_t s);
+
 // marginal likelihood (loglik.hip)
 constexpr int kLLBlock = 4096;      // steps per block of the prefix sums
 int64_t ll_blocks(int64_t total);

@@ -101,6 +101,18 @@ __global__ void k_poison(unsigned long long* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0xFFF80000FFF80000ull;
 }
 
+// Offsets check (pks_check_offsets): result = the smallest index b at which
+// offsets break a packing rule (offsets[0] = 0, non-decreasing, at most
+// total, offsets[B] = total), else left at its initial 0x7fffffff.
+__global__ void k_offsets_init(int* result) { *result = 0x7fffffff; }
+__global__ void k_offsets_check(const int64_t* off, int B, int64_t total, int* result) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= B; b += gridDim.x * blockDim.x) {
+        const int64_t v = off[b];
+        const bool bad = (b == 0 && v != 0) || (b > 0 && v < off[b - 1]) || v > total || (b == B && v != total);
+        if (bad) atomicMin(result, b);
+    }
+}
+
 // out[m x n] = op(A) op(B); A is [m x k] (or [k x m] if ta), B is [k x n] (or [n x k] if tb)
 __device__ void bmm(double* out, const double* A, bool ta, const double* B, bool tb, int m, int k, int n,
                     double alpha = 1.0, const double* add = nullptr) {
@@ -698,6 +710,13 @@ hipError_t launch_poison(void* p, size_t bytes, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const size_t blocks = std::min<size_t>(1024, (n + 255) / 256);
     hipLaunchKernelGGL(k_poison, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<unsigned long long*>(p), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets_check(const int64_t* offsets, int B, int64_t total, int* result, hipStream_t s) {
+    hipLaunchKernelGGL(k_offsets_init, dim3(1), dim3(1), 0, s, result);
+    const int blocks = (int)std::min<int64_t>(1024, ((int64_t)B + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_offsets_check, dim3(blocks), dim3(256), 0, s, offsets, B, total, result);
     return hipGetLastError();
 }
 

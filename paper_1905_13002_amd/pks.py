@@ -31,7 +31,7 @@ EXPORTED = ["pks_workspace_bytes", "pks_filter", "pks_smooth", "pks_filter_smoot
             "pks_filter_tv_batched", "pks_smooth_tv_batched", "pks_loglik_tv_batched",
             "pks_hmm_workspace_bytes", "pks_hmm_filter", "pks_hmm_smooth", "pks_hmm_filter_smooth",
             "pks_filter_smooth_noalloc", "pks_noalloc_scratch_bytes", "pks_set_debug_poison",
-            "pks_debug_poison", "pks_plan_create_tv"]
+            "pks_debug_poison", "pks_plan_create_tv", "pks_check_offsets"]
 
 
 class PksError(RuntimeError):
@@ -73,6 +73,7 @@ def _load():
         "pks_filter_smooth_noalloc": (ctypes.c_int, [mp, i64, vp, vp, vp, vp, vp, ctypes.c_int, vp]),
         "pks_noalloc_scratch_bytes": (sz, []),
         "pks_set_debug_poison": (ctypes.c_int, [i32]),
+        "pks_check_offsets": (ctypes.c_int, [i32, vp, i64, vp, ctypes.POINTER(i32), vp]),
         "pks_debug_poison": (i32, []),
         "pks_hmm_filter": (ctypes.c_int, [hp, i64, vp, vp, vp, vp, sz, vp]),
         "pks_hmm_smooth": (ctypes.c_int, [hp, i64, vp, vp, vp, sz, vp]),
@@ -366,6 +367,19 @@ class Plan:
 def autotune(nx, ny, B, total, precision="fp64", cache_path: Optional[str] = None, stream=None):
     _check(lib.pks_autotune(nx, ny, B, int(total), _prec(precision),
                             cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def check_offsets(offsets: torch.Tensor, total: int, ws: Optional[torch.Tensor] = None, stream=None):
+    """Checks device offsets [B+1] against the packing rules (synchronises):
+    returns (True, -1), or (False, the smallest offending index)."""
+    B = offsets.shape[0] - 1
+    ws = ws if ws is not None else torch.empty(256, dtype=torch.uint8, device=offsets.device)
+    bad = ctypes.c_int32(-1)
+    st = lib.pks_check_offsets(B, _ptr(offsets), int(total), _ptr(ws), ctypes.byref(bad), _stream(stream))
+    if st == PKS_E_ARG and bad.value >= 0:
+        return False, int(bad.value)
+    _check(st)
+    return True, -1
 
 
 def set_debug_poison(on: bool):

@@ -113,6 +113,14 @@ def test_batched_argument_errors():
     assert lib.pks_filter_batched(ctypes.byref(m), 3, FAKE, -5, *args) == pks.PKS_E_ARG
 
 
+def test_check_offsets_argument_errors():
+    bad = ctypes.c_int32(7)
+    assert lib.pks_check_offsets(0, FAKE, 10, FAKE, ctypes.byref(bad), None) == pks.PKS_E_ARG and bad.value == -1
+    assert lib.pks_check_offsets(3, None, 10, FAKE, None, None) == pks.PKS_E_ARG
+    assert lib.pks_check_offsets(3, FAKE, 10, None, None, None) == pks.PKS_E_ARG
+    assert lib.pks_check_offsets(3, FAKE, -1, FAKE, None, None) == pks.PKS_E_ARG
+
+
 def test_plan_and_tuner_argument_errors():
     assert lib.pks_plan_destroy(None) == pks.PKS_OK
     assert lib.pks_plan_launch(None, None) == pks.PKS_E_ARG

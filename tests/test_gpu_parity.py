@@ -367,6 +367,20 @@ def test_nan_in_y_propagates(pks):
     assert np.isnan(out["m"][1234:]).all()
 
 
+def test_check_offsets(pks):
+    """pks_check_offsets on well-formed offsets and on each broken rule (only
+    the check kernel reads the malformed arrays)."""
+    cases = [([0, 3, 3, 10], 10, -1), ([1, 3, 5, 10], 10, 0), ([0, 5, 4, 10], 10, 2), ([0, 3, 12, 10], 10, 2),
+             ([0, 3, 5, 9], 10, 3), ([0, 0, 0, 0], 0, -1)]
+    for offs, total, want in cases:
+        ok, first = pks.check_offsets(torch.tensor(offs, dtype=torch.int64, device="cuda"), total)
+        assert (ok, first) == (want < 0, want), (offs, total, ok, first)
+    big = torch.arange(0, 100001, dtype=torch.int64, device="cuda") * 3
+    assert pks.check_offsets(big, 300000) == (True, -1)
+    big[77777] = 0
+    assert pks.check_offsets(big, 300000) == (False, 77777)
+
+
 def test_empty_sequence_is_noop(pks):
     mo = wl.cv_model()
     dm = pks.to_device(mo)
