@@ -21,7 +21,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = (["scan_large_f64.hip", "scan_large_f32.hip", "scan_large_f64_seg.hip", "scan_large_f32_seg.hip",
             "api.cpp", "plan.cpp", "precompute.hip", "scan_small.hip", "scan_large.hip", "loglik.hip",
-            "hmm.hip", "noalloc.hip"]
+            "hmm.hip", "noalloc.hip", "scan_w16.hip"]
            + ["scan_small_n%d_%s.hip" % (n, t) for n in (4, 3, 2, 1) for t in ("f64", "f32")])
 
 # The small-state scan units hold the top-level kernels, whose 4 x 4 products
@@ -32,6 +32,7 @@ SOURCES = (["scan_large_f64.hip", "scan_large_f32.hip", "scan_large_f64_seg.hip"
 # or chosen by the compiler under a tighter register budget) is exact.
 PER_FILE = {"scan_small_n%d_%s.hip" % (n, t): ["-mllvm", "-amdgpu-mfma-vgpr-form"]
             for n in (4, 3, 2, 1) for t in ("f64", "f32")}
+PER_FILE["scan_w16.hip"] = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 ARCH = os.environ.get("PKS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

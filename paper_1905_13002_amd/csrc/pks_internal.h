@@ -210,4 +210,11 @@ size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);
 int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed);
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
 
+// register-resident large-state path (scan_w16.hip): one sequence, one
+// time-invariant model, 5 <= nx <= 16, ny <= 16
+bool w16_applies(int nx, int ny, bool single_invariant);
+int64_t w16_default_blocks(int64_t total);
+size_t w16_ws_bytes(int64_t total);
+hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
+
 }  // namespace pks

@@ -48,6 +48,7 @@ int64_t large_blocks(int64_t total, int nx, int ny, bool mixed) {
 }  // namespace lg
 
 int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed) {
+    if (w16_applies(nx, ny, true)) return w16_default_blocks(total);
     return lg::large_blocks(total, nx, ny, mixed);
 }
 
@@ -59,11 +60,17 @@ size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec) {
     const size_t fw = (size_t)flay(nx).words;
     size_t slot = 0;
     slot_mask_of(nx, ny, mixed, &slot);
-    return 2 * ((rs * fw * nb + 255) & ~size_t(255)) + slot * nb;
+    const size_t lds_path = 2 * ((rs * fw * nb + 255) & ~size_t(255)) + slot * nb;
+    // a single sequence of a time-invariant model with nx <= 16 takes the
+    // register-resident path (packed sequences keep the path above)
+    const size_t reg_path = w16_applies(nx, ny, true) ? w16_ws_bytes(total) : 0;
+    return lds_path > reg_path ? lds_path : reg_path;
 }
 
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
     using namespace lg;
+    if (w16_applies(a.nx, a.ny, a.offsets == nullptr && a.step_stride == 0))
+        return launch_w16(a, region, mixed, smoother, s);
     LargeArgs la;
     la.s = a;
     const int64_t nb_max = large_blocks(a.total, a.nx, a.ny, mixed);

@@ -1,0 +1,752 @@
+// scan_w16.hip -- the filtering and smoothing scans of one sequence with one
+// time-invariant model for 5 <= nx <= 16 and ny <= 16, every element held in
+// the registers of one wavefront.
+//
+// Register layout of a 16 x 16 matrix X (smaller dimensions padded with
+// zeros): lane l = 16 lk + li holds X(4 v + lk, li) in component v of an
+// f64x4 -- the accumulator layout of v_mfma_f64_16x16x4f64.  In that layout
+// component s of the tile of L^T and component s of the tile of R are
+// exactly the A and B operands of the s-th K-slice of the product L R, so a
+// product is four MFMAs with no data movement:
+//     L R = mm(tile(L^T), tile(R)),   (L R)^T = mm(tile(R), tile(L^T)).
+// Every matrix is therefore kept in the form its consumers read (C, J, L, P
+// are symmetric, so their tiles serve both ways); a transpose, when one is
+// needed, is a product with the identity.  A vector x is held replicated
+// across the columns (lane: x(4 v + lk)), so a matrix-vector product is an
+// MFMA product as well.
+//
+// The time axis is cut into blocks (the block-level elements of Section
+// III-C), one wavefront per block:
+//   reduce : fold the block's single-step elements (Lemma 1 / Lemma 3) into
+//            its block element with the operators of Lemma 2 / Lemma 4,
+//   scan   : Kogge-Stone over the block elements, ceil(log2 blocks) launches
+//            (filter: out[i] = in[i - d] (x) in[i]; smoother: in[i] (x) in[i + d]),
+//   down   : re-fold the block from the moments before it (after it, for the
+//            smoother), writing the filtered (smoothed) moments.
+// The solves are 16 x 16 inverses by Gauss-Jordan elimination in the same
+// register layout: with partial pivoting for I + C_i J_j (Lemma 2) and its
+// carry form I + P J (pivot rows chosen in place, the rows of the inverse
+// gathered at the end), without pivoting for the positive definite
+// F P F^T + Q of Lemma 3 (a non-positive pivot there is the numeric failure).
+// All arithmetic is FP64 in both precisions (the constants come from the
+// double copy the precompute writes); the precision sets the type of y and of
+// the moments in memory.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pks_internal.h"
+
+namespace pks {
+namespace w16 {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 256;                    // doubles of one tile in memory (lane-major)
+// block element records (doubles): filter A, C, J tiles then b, eta;
+// smoother E, L tiles then g
+constexpr int kFA = 0, kFC = kTile, kFJ = 2 * kTile, kFb = 3 * kTile, kFeta = 3 * kTile + 16, kFRec = 3 * kTile + 32;
+constexpr int kSE = 0, kSL = kTile, kSg = 2 * kTile, kSRec = 2 * kTile + 16;
+constexpr int kStage = 16 * 17;               // LDS doubles per wave: the row gather of a pivoted inverse
+constexpr int kThreads = 64;
+constexpr int64_t kMaxBlocks = 2048;
+
+struct W16Args {
+    ScanArgs s;
+    int64_t blen, nblocks;
+    double* agg[2];          // ping-pong block elements [nblocks][kFRec]
+    int final_buf;
+};
+
+__device__ __forceinline__ int lane_i() { return threadIdx.x & 15; }          // column
+__device__ __forceinline__ int lane_k() { return (threadIdx.x >> 4) & 3; }    // row within a group of four
+
+__device__ __forceinline__ f64x4 zero4() { return f64x4{0.0, 0.0, 0.0, 0.0}; }
+
+__device__ __forceinline__ f64x4 eye() {
+    const int li = lane_i(), lk = lane_k();
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = (4 * v + lk == li) ? 1.0 : 0.0;
+    return t;
+}
+
+// L R + acc, given the tile of L^T and the tile of R.  KS: the K-slices of four
+// that hold the contraction (entries beyond 4 KS of L's columns or R's rows
+// are zero), so a contraction over ny <= 8 takes two MFMAs; a compile-time
+// count, since a branch around each MFMA costs more than the MFMA
+template <int KS = 4>
+__device__ __forceinline__ f64x4 mm(const f64x4& lt, const f64x4& r, f64x4 acc) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[s], r[s], acc, 0, 0, 0);
+    return acc;
+}
+template <int KS = 4>
+__device__ __forceinline__ f64x4 mm(const f64x4& lt, const f64x4& r) { return mm<KS>(lt, r, zero4()); }
+
+// (X + X^T) / 2 + add, given the tiles of X and X^T
+__device__ __forceinline__ f64x4 sym(const f64x4& x, const f64x4& xt, const f64x4& add) {
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = 0.5 * (x[v] + xt[v]) + add[v];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// memory <-> registers
+// ---------------------------------------------------------------------------
+// tile of the rows x cols matrix X (row stride ld), zero outside it
+template <typename T>
+__device__ __forceinline__ f64x4 load_tile(const T* X, int rows, int cols, int ld) {
+    const int li = lane_i(), lk = lane_k();
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        t[v] = (r < rows && li < cols) ? double(X[r * ld + li]) : 0.0;
+    }
+    return t;
+}
+// tile of X^T for the rows x cols matrix X
+template <typename T>
+__device__ __forceinline__ f64x4 load_tile_t(const T* X, int rows, int cols, int ld) {
+    const int li = lane_i(), lk = lane_k();
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        t[v] = (li < rows && r < cols) ? double(X[li * ld + r]) : 0.0;
+    }
+    return t;
+}
+// replicated vector x[0..n), zero beyond
+template <typename T>
+__device__ __forceinline__ f64x4 load_vec(const T* x, int n) {
+    const int lk = lane_k();
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        t[v] = r < n ? double(x[r]) : 0.0;
+    }
+    return t;
+}
+template <typename T>
+__device__ __forceinline__ void store_tile(T* X, const f64x4& t, int n) {
+    const int li = lane_i(), lk = lane_k();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        if (r < n && li < n) X[r * n + li] = T(t[v]);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_vec(T* x, const f64x4& t, int n) {
+    const int li = lane_i(), lk = lane_k();
+    if (li != 0) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        if (r < n) x[r] = T(t[v]);
+    }
+}
+// records: tiles lane-major (each lane's four doubles contiguous)
+__device__ __forceinline__ void put_tile(double* p, const f64x4& t) {
+    reinterpret_cast<f64x4*>(p)[threadIdx.x & 63] = t;
+}
+__device__ __forceinline__ f64x4 get_tile(const double* p) {
+    return reinterpret_cast<const f64x4*>(p)[threadIdx.x & 63];
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// lane k of the lane's own row of 16 (DPP row_newbcast; k a constant after unrolling)
+__device__ __forceinline__ unsigned newbcast(unsigned x, int k) {
+    switch (k) {
+#define PKS_NB(K) case K: return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x150 + K, 0xf, 0xf, false);
+        PKS_NB(0) PKS_NB(1) PKS_NB(2) PKS_NB(3) PKS_NB(4) PKS_NB(5) PKS_NB(6) PKS_NB(7)
+        PKS_NB(8) PKS_NB(9) PKS_NB(10) PKS_NB(11) PKS_NB(12) PKS_NB(13) PKS_NB(14) PKS_NB(15)
+#undef PKS_NB
+        default: return x;
+    }
+}
+__device__ __forceinline__ double col_bcast(double x, int k) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = newbcast((unsigned)u, k), hi = newbcast((unsigned)(u >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// the value of lane 16 g + (lane % 16), g uniform: permlane16_swap of x with
+// itself gives rows (0,0,2,2) and (1,1,3,3), permlane32_swap of one of those
+// with itself its lower or upper half in both halves
+__device__ __forceinline__ unsigned rowbcast(unsigned x, int g) {
+    const auto q = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    const unsigned t = (g & 1) ? q[1] : q[0];
+    const auto r = __builtin_amdgcn_permlane32_swap(t, t, false, false);
+    return (g & 2) ? r[1] : r[0];
+}
+__device__ __forceinline__ double row_bcast(double x, int g) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = rowbcast((unsigned)u, g), hi = rowbcast((unsigned)(u >> 32), g);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// 1 / x: the hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r)), within an ulp or two of the quotient
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double pick(const f64x4& t, int q) {
+    return q == 0 ? t[0] : (q == 1 ? t[1] : (q == 2 ? t[2] : t[3]));
+}
+
+// ---------------------------------------------------------------------------
+// Inverses by Gauss-Jordan elimination in the register layout.  The pivot's
+// column reaches the lanes of each row of 16 by a DPP broadcast, the pivot row
+// reaches the other rows of 16 by the permlane swaps.  Only the first n pivots
+// are taken: the matrices are padded with the identity, on which the
+// remaining steps change nothing.
+// ---------------------------------------------------------------------------
+// Symmetric positive definite a: the pivots are the diagonal, in order, and
+// the inverse is formed in place.  `ok` is cleared by a pivot that is not
+// positive (the matrix is not positive definite) or not finite.
+__device__ __forceinline__ f64x4 inv_spd(f64x4 a, int n, bool& ok) {
+    const int li = lane_i(), lk = lane_k();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < n) {        // a guard, not an exit: the loop stays fully unrolled
+            const int q = k >> 2, g = k & 3;
+            const double pv = readlane_d(a[q], (g << 4) | k);          // a(k, k)
+            double ck[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ck[v] = col_bcast(a[v], k);    // a(4 v + lk, k)
+            const double rk = row_bcast(a[q], g);                      // a(k, li)
+            ok = ok && pv > 0.0 && isfinite(pv);
+            const double r = recip(pv);
+            const double rr = rk * r;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double f = ck[v] * r;
+                if (4 * v + lk == k) a[v] = li == k ? r : rr;           // the pivot row
+                else a[v] = li == k ? -f : fma(-f, rk, a[v]);
+            }
+        }
+    }
+    return a;
+}
+
+// General a: partial pivoting without row exchanges (the pivot of column k is
+// the entry of largest magnitude among the rows not used yet, lower rows
+// winning ties), elimination on [a | I]; row k of the inverse is then row p_k
+// of the right half, gathered through the LDS stage.  `ok` is cleared by a
+// zero or non-finite pivot.
+__device__ __forceinline__ f64x4 inv_piv(f64x4 a, int n, double* st, bool& ok) {
+    const int li = lane_i(), lk = lane_k();
+    f64x4 b = eye();
+    unsigned used = 0;
+    unsigned long long perm = 0xFEDCBA9876543210ull;      // p_k = k beyond n
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k >= n) continue;
+        double ck[4];
+        unsigned best = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ck[v] = col_bcast(a[v], k);                          // a(4 v + lk, k)
+            const int row = 4 * v + lk;
+            // |entry| as float with the low mantissa bits dropped, then the row
+            const unsigned bits = __float_as_uint((float)fabs(ck[v]));
+            const unsigned key = ((used >> row) & 1u) ? 0u : (((bits >> 4) << 5) | 16u | (unsigned)(15 - row));
+            best = best > key ? best : key;
+        }
+        const unsigned g0 = (unsigned)__builtin_amdgcn_readlane((int)best, 0);
+        const unsigned g1 = (unsigned)__builtin_amdgcn_readlane((int)best, 16);
+        const unsigned g2 = (unsigned)__builtin_amdgcn_readlane((int)best, 32);
+        const unsigned g3 = (unsigned)__builtin_amdgcn_readlane((int)best, 48);
+        const unsigned m01 = g0 > g1 ? g0 : g1, m23 = g2 > g3 ? g2 : g3;
+        const unsigned key = m01 > m23 ? m01 : m23;
+        const int p = 15 - (int)(key & 15u);
+        used |= 1u << p;
+        perm = (perm & ~(15ull << (4 * k))) | ((unsigned long long)p << (4 * k));
+        const int q = p >> 2, g = p & 3;
+        const double pv = readlane_d(pick(f64x4{ck[0], ck[1], ck[2], ck[3]}, q), g << 4);   // a(p, k)
+        const double ra = row_bcast(pick(a, q), g);              // row p of a and of b
+        const double rb = row_bcast(pick(b, q), g);
+        ok = ok && pv != 0.0 && isfinite(pv);
+        const double r = recip(pv);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool prow = 4 * v + lk == p;
+            const double f = ck[v] * r;
+            a[v] = prow ? ra * r : fma(-f, ra, a[v]);
+            b[v] = prow ? rb * r : fma(-f, rb, b[v]);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) st[(4 * v + lk) * 17 + li] = b[v];
+    wave_sync_lds();
+    f64x4 out;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int p = (int)((perm >> (4 * (4 * v + lk))) & 15ull);
+        out[v] = st[p * 17 + li];
+    }
+    wave_sync_lds();
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// operators (KY: K-slices of a contraction over ny; contractions over nx take all four)
+// ---------------------------------------------------------------------------
+struct FE {                 // filtering element (Lemma 1 / 2): tiles of A, C, J; b, eta
+    f64x4 A, b, C, eta, J;
+};
+
+// constants of the filter kernels (double copy): tiles of A^T, C, J, K^T, W^T,
+// G^T and S (the identity beyond ny), replicated c and w
+struct FConst {
+    f64x4 AT, C, J, KT, WT, GT, S, c, w;
+    int n, ny;
+};
+
+// Output half of Lemma 2, given X1 = M^-1 A_i, x2 = M^-1 (b_i + C_i eta_j) and
+// X3 = M^-1 C_i (M = I + C_i J_j) and the tile of A_j^T:
+//   A = A_j X1, b = A_j x2 + b_j, C = A_j X3 A_j^T + C_j,
+//   eta = X1^T (eta_j - J_j b_i) + eta_i, J = X1^T J_j A_i + J_i
+__device__ __forceinline__ void fout(FE& e, const f64x4& X1, const f64x4& x2, const f64x4& X3, const f64x4& AjT,
+                                     const f64x4& bj, const f64x4& Cj, const f64x4& etaj, const f64x4& Jj) {
+    const f64x4 w = mm(-Jj, e.b, etaj);
+    const f64x4 JA = mm(Jj, e.A);
+    e.A = mm(AjT, X1);
+    e.b = mm(AjT, x2, bj);
+    const f64x4 U = mm(X3, AjT);                     // X3^T A_j^T
+    e.C = sym(mm(AjT, U), mm(U, AjT), Cj);      // A_j sym(X3) A_j^T + C_j
+    e.eta = mm(X1, w, e.eta);
+    e.J = sym(mm(X1, JA), mm(JA, X1), e.J);
+}
+
+// e <- e (x) (A_j, b_j, C_j, eta_j, J_j), Lemma 2, for two block elements: the
+// inverse of M^T = I + J_j C_i (its tile is M^-1 as a left factor) with
+// pivoting
+__device__ __forceinline__ void fcombine(FE& e, const f64x4& AjT, const f64x4& bj, const f64x4& Cj, const f64x4& etaj,
+                                         const f64x4& Jj, const f64x4& I, double* st, int n) {
+    bool ok = true;
+    const f64x4 NT = inv_piv(mm(Jj, e.C, I), n, st, ok);
+    const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
+    fout(e, mm(NT, e.A), mm(NT, v), mm(NT, e.C), AjT, bj, Cj, etaj, Jj);
+}
+
+// e <- e (x) a_j for a single step j > 1, where J_j = G^T S^-1 G (G = H F,
+// S = H Q H^T + R): M^-1 = I - K G with K = C_i G^T Sigma^-1 and the ny x ny
+// positive definite Sigma = S + G C_i G^T, so
+//   X1 = A_i - K (G A_i), x2 = v - K (G v), X3 = C_i - K (G C_i).
+template <int KY>
+__device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64x4& bj, const f64x4& etaj) {
+
+    const f64x4 Y = mm(e.C, f.GT);                   // C_i G^T
+    const f64x4 YT = mm(f.GT, e.C);                  // G C_i
+    bool ok = true;
+    const f64x4 Z = inv_spd(sym(mm(f.GT, Y), mm(Y, f.GT), f.S), f.ny, ok);
+    const f64x4 nKT = -mm<KY>(Z, YT);                    // tile of -K^T
+    const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
+    const f64x4 X1 = mm<KY>(nKT, mm(f.GT, e.A), e.A);
+    const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
+    const f64x4 X3 = mm<KY>(nKT, YT, e.C);
+    fout(e, X1, x2, X3, f.AT, bj, f.C, etaj, f.J);
+}
+
+// filtered moments (m, P) <- (m, P) (x) a_j for a single step j > 1 (the
+// prefix element has A = 0): with K = P G^T Sigma^-1, Sigma = S + G P G^T,
+//   m = A_j (v - K G v) + b_j (v = m + P eta_j), P = A_j (P - K G P) A_j^T + C_j
+template <int KY>
+__device__ __forceinline__ void fcarry_fresh(f64x4& m, f64x4& P, const FConst& f, const f64x4& bj, const f64x4& etaj) {
+
+    const f64x4 Y = mm(P, f.GT);                     // P G^T
+    const f64x4 YT = mm(f.GT, P);                    // G P
+    bool ok = true;
+    const f64x4 Z = inv_spd(sym(mm(f.GT, Y), mm(Y, f.GT), f.S), f.ny, ok);
+    const f64x4 nKT = -mm<KY>(Z, YT);
+    const f64x4 v = mm(P, etaj, m);
+    const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
+    const f64x4 X3 = mm<KY>(nKT, YT, P);
+    m = mm(f.AT, x2, bj);
+    const f64x4 U = mm(X3, f.AT);
+    P = sym(mm(f.AT, U), mm(U, f.AT), f.C);
+}
+
+// constants of the smoother kernels: tiles of F^T and Q (the identity beyond
+// nx), replicated u
+struct SConst {
+    f64x4 FT, Q, u;
+    int n;
+};
+
+// smoothing element of step k (Lemma 3) from the filtered (m, P):
+//   E = P F^T (F P F^T + Q)^-1, g = m - E (F m + u), L = P - E F P,
+// returned as the tile of E^T, g and L
+__device__ __forceinline__ void selem(const f64x4& m, const f64x4& P, const SConst& c, bool& ok, f64x4& ET, f64x4& g,
+                                      f64x4& L) {
+
+    const f64x4 FP = mm(c.FT, P);
+    const f64x4 PFT = mm(P, c.FT);
+    const f64x4 Z = inv_spd(sym(mm(c.FT, PFT), mm(PFT, c.FT), c.Q), c.n, ok);
+    ET = mm(Z, FP);                                  // (F P F^T + Q)^-1 F P
+    g = mm(-ET, mm(c.FT, m, c.u), m);
+    const f64x4 EFP = mm(ET, FP), EFPt = mm(FP, ET);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) L[v] = P[v] - 0.5 * (EFP[v] + EFPt[v]);
+}
+
+// (E, g, L) <- e_k (x) (E, g, L), Lemma 4, e_k given by the tile of E_k^T:
+//   E = E_k E, g = E_k g + g_k, L = E_k L E_k^T + L_k
+__device__ __forceinline__ void sfold(f64x4& E, f64x4& g, f64x4& L, const f64x4& EkT, const f64x4& gk,
+                                      const f64x4& Lk) {
+    E = mm(EkT, E);
+    g = mm(EkT, g, gk);
+    const f64x4 T1T = mm(L, EkT);                    // (E_k L)^T
+    L = sym(mm(T1T, EkT), mm(EkT, T1T), Lk);
+}
+// smoothed moments (m, P) <- e_k (x) (m, P) (the suffix element has E = 0)
+__device__ __forceinline__ void scarry(f64x4& m, f64x4& P, const f64x4& EkT, const f64x4& gk, const f64x4& Lk) {
+    m = mm(EkT, m, gk);
+    const f64x4 T1T = mm(P, EkT);
+    P = sym(mm(T1T, EkT), mm(EkT, T1T), Lk);
+}
+
+__host__ __device__ inline int slices(int n) { return (n + 3) >> 2; }
+
+// the identity beyond n on the diagonal of t
+__device__ __forceinline__ f64x4 pad_eye(f64x4 t, int n) {
+    const int li = lane_i(), lk = lane_k();
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        if (4 * v + lk == li && li >= n) t[v] = 1.0;
+    return t;
+}
+
+__device__ __forceinline__ FConst load_fconst(const ScanArgs& a, const ConstLayout& CL) {
+    const double* cst = a.consts64;
+    const int n = a.nx, m = a.ny;
+    FConst f;
+    f.AT = load_tile_t(cst + CL.A, n, n, n);
+    f.C = load_tile(cst + CL.C, n, n, n);
+    f.J = load_tile(cst + CL.J, n, n, n);
+    f.KT = load_tile_t(cst + CL.K, n, m, m);
+    f.WT = load_tile_t(cst + CL.W, n, m, m);
+    f.GT = load_tile_t(cst + CL.G, m, n, n);
+    f.S = pad_eye(load_tile(cst + CL.S, m, m, m), m);
+    f.c = load_vec(cst + CL.c, n);
+    f.w = load_vec(cst + CL.w, n);
+    f.n = n;
+    f.ny = m;
+
+    return f;
+}
+
+__device__ __forceinline__ SConst load_sconst(const ScanArgs& a, const ConstLayout& CL) {
+    const double* cst = a.consts64;
+    const int n = a.nx;
+    SConst c;
+    c.FT = load_tile_t(cst + CL.F, n, n, n);
+    c.Q = pad_eye(load_tile(cst + CL.Q, n, n, n), n);
+    c.u = load_vec(cst + CL.u, n);
+    c.n = n;
+
+    return c;
+}
+
+__device__ __forceinline__ int64_t blk_end(const W16Args& w, int64_t k0) {
+    return k0 + w.blen < w.s.total ? k0 + w.blen : w.s.total;
+}
+
+// ---------------------------------------------------------------------------
+// filter kernels
+// ---------------------------------------------------------------------------
+template <typename R, int KY>
+__global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
+    const ScanArgs& a = w.s;
+    const ConstLayout CL = const_layout(a.nx, a.ny);
+    const int n = a.nx, ny = a.ny;
+    const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.model_fail[0]) atomicMin(a.status, 0);
+    const FConst f = load_fconst(a, CL);
+    const R* y = static_cast<const R*>(a.y);
+    FE e;
+    f64x4 yk = load_vec(y + k0 * ny, ny);
+    if (k0 == 0) {          // the first step: A = 0, eta = 0, J = 0
+        const double* cst = a.consts64;
+        e.A = zero4();
+        e.b = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
+        e.C = load_tile(cst + CL.C1, n, n, n);
+        e.eta = zero4();
+        e.J = zero4();
+    } else {
+        e.A = mm(f.AT, eye());
+        e.b = mm<KY>(f.KT, yk, f.c);
+        e.C = f.C;
+        e.eta = mm<KY>(f.WT, yk, f.w);
+        e.J = f.J;
+    }
+    for (int64_t k = k0 + 1; k < k1; ++k) {
+        yk = load_vec(y + k * ny, ny);
+        fcombine_fresh<KY>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w));
+    }
+    double* rec = w.agg[0] + (size_t)blockIdx.x * kFRec;
+    put_tile(rec + kFA, e.A);
+    put_tile(rec + kFC, e.C);
+    put_tile(rec + kFJ, e.J);
+    store_vec(rec + kFb, e.b, 16);
+    store_vec(rec + kFeta, e.eta, 16);
+}
+
+// out[i] = in[i - d] (x) in[i] (i >= d), else in[i]
+__global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const double* in, double* out, int64_t d) {
+    __shared__ double st[kStage];
+    const int64_t i = blockIdx.x;
+    const double* rj = in + (size_t)i * kFRec;
+    double* ro = out + (size_t)i * kFRec;
+    const f64x4 Aj = get_tile(rj + kFA), Cj = get_tile(rj + kFC), Jj = get_tile(rj + kFJ);
+    const f64x4 bj = load_vec(rj + kFb, 16), etaj = load_vec(rj + kFeta, 16);
+    FE e;
+    if (i < d) {
+        e.A = Aj; e.C = Cj; e.J = Jj; e.b = bj; e.eta = etaj;
+    } else {
+        const int n = w.s.nx;
+        const double* ri = in + (size_t)(i - d) * kFRec;
+        e.A = get_tile(ri + kFA);
+        e.C = get_tile(ri + kFC);
+        e.J = get_tile(ri + kFJ);
+        e.b = load_vec(ri + kFb, 16);
+        e.eta = load_vec(ri + kFeta, 16);
+        const f64x4 I = eye();
+        fcombine(e, mm(Aj, I), bj, Cj, etaj, Jj, I, st, n);
+    }
+    put_tile(ro + kFA, e.A);
+    put_tile(ro + kFC, e.C);
+    put_tile(ro + kFJ, e.J);
+    store_vec(ro + kFb, e.b, 16);
+    store_vec(ro + kFeta, e.eta, 16);
+}
+
+template <typename R, int KY>
+__global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
+    const ScanArgs& a = w.s;
+    const ConstLayout CL = const_layout(a.nx, a.ny);
+    const int n = a.nx, ny = a.ny;
+    const int64_t blk = blockIdx.x, k0 = blk * w.blen, k1 = blk_end(w, k0);
+    const FConst f = load_fconst(a, CL);
+    const R* y = static_cast<const R*>(a.y);
+    R* mo = static_cast<R*>(a.m);
+    R* Po = static_cast<R*>(a.P);
+    f64x4 m = zero4(), P = zero4();
+    if (blk > 0) {           // the filtered moments at the end of the previous block
+        const double* rec = w.agg[w.final_buf] + (size_t)(blk - 1) * kFRec;
+        m = load_vec(rec + kFb, 16);
+        P = get_tile(rec + kFC);
+    }
+    for (int64_t k = k0; k < k1; ++k) {
+        const f64x4 yk = load_vec(y + k * ny, ny);
+        if (k == 0) {
+            const double* cst = a.consts64;
+            m = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
+            P = load_tile(cst + CL.C1, n, n, n);
+        } else {
+            fcarry_fresh<KY>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w));
+        }
+        store_vec(mo + k * n, m, n);
+        store_tile(Po + k * n * n, P, n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// smoother kernels
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void load_moments(const ScanArgs& a, int64_t k, f64x4& m, f64x4& P) {
+    const int n = a.nx;
+    m = load_vec(static_cast<const R*>(a.m) + k * n, n);
+    P = load_tile(static_cast<const R*>(a.P) + k * n * n, n, n, n);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
+    const ScanArgs& a = w.s;
+    const ConstLayout CL = const_layout(a.nx, a.ny);
+    const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
+    const SConst c = load_sconst(a, CL);
+    bool ok = true;
+    f64x4 m, P, E, g, L;
+    load_moments<R>(a, k1 - 1, m, P);
+    if (k1 == a.total) {    // the last step: E = 0, g = m, L = P
+        E = zero4();
+        g = m;
+        L = P;
+    } else {
+        f64x4 ET;
+        selem(m, P, c, ok, ET, g, L);
+        E = mm(ET, eye());
+    }
+    for (int64_t k = k1 - 2; k >= k0; --k) {
+        load_moments<R>(a, k, m, P);
+        f64x4 ET, gk, Lk;
+        selem(m, P, c, ok, ET, gk, Lk);
+        sfold(E, g, L, ET, gk, Lk);
+    }
+    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
+    double* rec = w.agg[0] + (size_t)blockIdx.x * kSRec;
+    put_tile(rec + kSE, E);
+    put_tile(rec + kSL, L);
+    store_vec(rec + kSg, g, 16);
+}
+
+// out[i] = in[i] (x) in[i + d] (i + d < nb), else in[i]
+__global__ __launch_bounds__(kThreads) void k_w16_smoother_ks(W16Args w, const double* in, double* out, int64_t d) {
+    const int64_t i = blockIdx.x;
+    const double* ri = in + (size_t)i * kSRec;
+    double* ro = out + (size_t)i * kSRec;
+    const f64x4 Ei = get_tile(ri + kSE), Li = get_tile(ri + kSL), gi = load_vec(ri + kSg, 16);
+    f64x4 E, g, L;
+    if (i + d >= w.nblocks) {
+        E = Ei; g = gi; L = Li;
+    } else {
+
+        const double* rj = in + (size_t)(i + d) * kSRec;
+        E = get_tile(rj + kSE);
+        L = get_tile(rj + kSL);
+        g = load_vec(rj + kSg, 16);
+        sfold(E, g, L, mm(Ei, eye()), gi, Li);
+    }
+    put_tile(ro + kSE, E);
+    put_tile(ro + kSL, L);
+    store_vec(ro + kSg, g, 16);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
+    const ScanArgs& a = w.s;
+    const ConstLayout CL = const_layout(a.nx, a.ny);
+    const int n = a.nx;
+    const int64_t blk = blockIdx.x, k0 = blk * w.blen, k1 = blk_end(w, k0);
+    const SConst c = load_sconst(a, CL);
+    bool ok = true;
+    R* mso = static_cast<R*>(a.ms);
+    R* Pso = static_cast<R*>(a.Ps);
+    f64x4 ms = zero4(), Ps = zero4();
+    if (blk + 1 < w.nblocks) {   // the smoothed moments at the start of the next block
+        const double* rec = w.agg[w.final_buf] + (size_t)(blk + 1) * kSRec;
+        ms = load_vec(rec + kSg, 16);
+        Ps = get_tile(rec + kSL);
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+        f64x4 m, P;
+        load_moments<R>(a, k, m, P);
+        if (k == a.total - 1) {
+            ms = m;
+            Ps = P;
+        } else {
+            f64x4 ET, gk, Lk;
+            selem(m, P, c, ok, ET, gk, Lk);
+            scarry(ms, Ps, ET, gk, Lk);
+        }
+        store_vec(mso + k * n, ms, n);
+        store_tile(Pso + k * n * n, Ps, n);
+    }
+    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int64_t blocks_for(int64_t total) {
+    int64_t nb = (total + 3) / 4;
+    if (nb > kMaxBlocks) nb = kMaxBlocks;
+    return nb < 1 ? 1 : nb;
+}
+
+size_t buffer_bytes(int64_t nb) { return ((size_t)nb * kFRec * sizeof(double) + 255) & ~size_t(255); }
+
+template <typename R>
+hipError_t run(W16Args w, bool smoother, hipStream_t s) {
+    const dim3 grid((unsigned)w.nblocks), block(kThreads);
+    int cur = 0;
+    if (!smoother) {
+        prof_begin("k_w16_filter_reduce", s);
+        switch (slices(w.s.ny)) {
+            case 1: hipLaunchKernelGGL((k_w16_filter_reduce<R, 1>), grid, block, 0, s, w); break;
+            case 2: hipLaunchKernelGGL((k_w16_filter_reduce<R, 2>), grid, block, 0, s, w); break;
+            case 3: hipLaunchKernelGGL((k_w16_filter_reduce<R, 3>), grid, block, 0, s, w); break;
+            default: hipLaunchKernelGGL((k_w16_filter_reduce<R, 4>), grid, block, 0, s, w); break;
+        }
+        prof_end(s);
+        for (int64_t d = 1; d < w.nblocks; d <<= 1) {
+            prof_begin("k_w16_filter_ks", s);
+            hipLaunchKernelGGL(k_w16_filter_ks, grid, block, 0, s, w, w.agg[cur], w.agg[cur ^ 1], d);
+            prof_end(s);
+            cur ^= 1;
+        }
+        w.final_buf = cur;
+        prof_begin("k_w16_filter_down", s);
+        switch (slices(w.s.ny)) {
+            case 1: hipLaunchKernelGGL((k_w16_filter_down<R, 1>), grid, block, 0, s, w); break;
+            case 2: hipLaunchKernelGGL((k_w16_filter_down<R, 2>), grid, block, 0, s, w); break;
+            case 3: hipLaunchKernelGGL((k_w16_filter_down<R, 3>), grid, block, 0, s, w); break;
+            default: hipLaunchKernelGGL((k_w16_filter_down<R, 4>), grid, block, 0, s, w); break;
+        }
+        prof_end(s);
+    } else {
+        prof_begin("k_w16_smoother_reduce", s);
+        hipLaunchKernelGGL(k_w16_smoother_reduce<R>, grid, block, 0, s, w);
+        prof_end(s);
+        for (int64_t d = 1; d < w.nblocks; d <<= 1) {
+            prof_begin("k_w16_smoother_ks", s);
+            hipLaunchKernelGGL(k_w16_smoother_ks, grid, block, 0, s, w, w.agg[cur], w.agg[cur ^ 1], d);
+            prof_end(s);
+            cur ^= 1;
+        }
+        w.final_buf = cur;
+        prof_begin("k_w16_smoother_down", s);
+        hipLaunchKernelGGL(k_w16_smoother_down<R>, grid, block, 0, s, w);
+        prof_end(s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace w16
+
+bool w16_applies(int nx, int ny, bool single_invariant) {
+    return single_invariant && nx >= 5 && nx <= 16 && ny >= 1 && ny <= 16;
+}
+
+int64_t w16_default_blocks(int64_t total) { return w16::blocks_for(total); }
+
+size_t w16_ws_bytes(int64_t total) { return 2 * w16::buffer_bytes(w16::blocks_for(total)); }
+
+hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
+    using namespace w16;
+    W16Args w;
+    w.s = a;
+    const int64_t nb_max = blocks_for(a.total);
+    // a tuned block count is honoured up to the count the workspace is sized for
+    w.nblocks = (a.large_blocks > 0 && a.large_blocks < nb_max) ? a.large_blocks : nb_max;
+    w.blen = (a.total + w.nblocks - 1) / w.nblocks;
+    w.nblocks = (a.total + w.blen - 1) / w.blen;
+    char* base = static_cast<char*>(region);
+    w.agg[0] = reinterpret_cast<double*>(base);
+    w.agg[1] = reinterpret_cast<double*>(base + buffer_bytes(nb_max));
+    w.final_buf = 0;
+    return mixed ? run<float>(w, smoother, s) : run<double>(w, smoother, s);
+}
+
+}  // namespace pks
