@@ -78,6 +78,8 @@ def kernel_model(nx, ny, rs, tv=False):
         "k_filter_down": per_step["down_f"], "k_large_filter_down": per_step["down_f"],
         "k_smoother_reduce": per_step["reduce_s"], "k_large_smoother_reduce": per_step["reduce_s"],
         "k_smoother_down": per_step["down_s"], "k_large_smoother_down": per_step["down_s"],
+        "k_w16_filter_reduce": per_step["reduce_f"], "k_w16_filter_down": per_step["down_f"],
+        "k_w16_smoother_reduce": per_step["reduce_s"], "k_w16_smoother_down": per_step["down_s"],
     }
     if tv:
         out["k_precompute"] = dict(bytes=rows, flops=pre_flops)
@@ -451,30 +453,35 @@ def main():
         ms = torch.empty_like(m)
         Ps = torch.empty_like(P)
         ws = pks.workspace(nx, ny, T, w.B, prec, dev, time_varying=tv)
+        # the pass two ways: replays of the captured pass (pks_plan_create /
+        # pks_plan_launch: precompute, filter and smoother in one HIP graph)
+        # and the eager calls (into buffers of their own).  The timed step is
+        # the plan for packed sequences and the eager call for one sequence
+        # (where the replay measured a few per cent slower); the other is
+        # reported beside it.
+        plan = pks.Plan(dm, y, off, prec)
+        plan_sec = time_steps(plan.launch, args.steps, args.warmup, torch)
         if batched:
-            plan = pks.Plan(dm, y, off, prec)
-            m, P, ms, Ps = plan.m, plan.P, plan.ms, plan.Ps
-            step = plan.launch
+            eager = lambda: (pks.smooth_batched(dm, off, *pks.filter_batched(dm, off, y, prec, ws=ws, out=(m, P)),
+                                                prec, ws=ws, out=(ms, Ps)))
         else:
-            step = lambda: pks.filter_smooth(dm, y, prec, ws=ws, out=(m, P, ms, Ps))
-        sec = time_steps(step, args.steps, args.warmup, torch)
-        # per-kernel durations: HIP events around every launch, same workload
+            eager = lambda: pks.filter_smooth(dm, y, prec, ws=ws, out=(m, P, ms, Ps))
+        eager_sec = time_steps(eager, args.steps, args.warmup, torch)
+        sec = plan_sec if batched else eager_sec
+        # per-kernel durations: HIP events around every launch of the eager
+        # path (graph replays hide individual launches), same workload
         pks.profile_start()
         for _ in range(args.steps):
-            if batched:
-                # graph replays hide individual launches: time the eager path
-                mm, PP = pks.filter_batched(dm, off, y, prec, ws=ws, out=(m, P))
-                pks.smooth_batched(dm, off, mm, PP, prec, ws=ws, out=(ms, Ps))
-            else:
-                step()
+            eager()
         prof = pks.profile_stop()
         torch.cuda.synchronize()
-        if batched:
-            step()
-            torch.cuda.synchronize()
-        out = {k: v.double().cpu().numpy() for k, v in (("m", m), ("P", P), ("ms", ms), ("Ps", Ps))}
-        results[prec] = dict(sec=sec, prof=prof, out=out)
-        progress("%s timed: %.4f ms per pass" % (prec, sec * 1e3))
+        # the checked outputs: the timed path's
+        src = (plan.m, plan.P, plan.ms, plan.Ps) if batched else (m, P, ms, Ps)
+        out = {k: v.double().cpu().numpy() for k, v in zip(("m", "P", "ms", "Ps"), src)}
+        plan.close()
+        results[prec] = dict(sec=sec, plan_sec=plan_sec, eager_sec=eager_sec, prof=prof, out=out)
+        progress("%s timed: %.4f ms per pass (plan replay %.4f ms, eager calls %.4f ms)"
+                 % (prec, sec * 1e3, plan_sec * 1e3, eager_sec * 1e3))
 
     # accuracy against the oracle (FP64; the mixed reference uses the float32-rounded y).
     # Batched workloads: a sample of sequences (first, last and evenly spaced).
@@ -514,6 +521,10 @@ def main():
             errs[prec] = e
             progress("%s checked against the oracle on %d sequences" % (prec, len(sample)))
 
+    # one sequence of one model with 5 <= nx <= 16 runs the register-resident
+    # path, whose arithmetic is FP64 in both precisions
+    f64_mixed = (not batched) and (not tv) and 5 <= nx <= 16 and ny <= 16
+
     # roofline of the dominant kernel (FP64 headline)
     def roofline(prec):
         rs = 8 if prec == "fp64" else 4
@@ -526,7 +537,7 @@ def main():
         if km is None:
             return dom, per_launch, None
         t_mem = km["bytes"] * T / (HBM_PEAK_GBS * 1e9)
-        peak_f = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+        peak_f = FP64_PEAK_TFLOPS if (prec == "fp64" or f64_mixed) else FP32_PEAK_TFLOPS
         t_alu = km["flops"] * T / (peak_f * 1e12)
         tr = measured_traffic(w.name, prec, dom)
         if t_mem >= t_alu:
@@ -554,7 +565,7 @@ def main():
             bytes_step += (2 * nx * nx + nx + ny * nx + ny + ny * ny) * 8
         flops_step = (f["f_full"] + f["f_carry"] + 2 * f["f_elem"] + 2 * f["s_elem"] + f["s_full"]
                       + f["s_carry"])
-        peak_f = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+        peak_f = FP64_PEAK_TFLOPS if (prec == "fp64" or f64_mixed) else FP32_PEAK_TFLOPS
         t_mem = bytes_step * T / (HBM_PEAK_GBS * 1e9)
         t_alu = flops_step * T / (peak_f * 1e12)
         tr = measured_pass_traffic(w.name, prec)
@@ -629,13 +640,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded simulation of the model)",
         "config": {"workload": w.name, "T": T, "B": w.B, "nx": nx, "ny": ny, "time_varying": tv,
-                   "path": "plan (hipGraph)" if batched else ("pks_filter_smooth_tv" if tv else "pks_filter_smooth")},
+                   "path": ("plan (hipGraph: pks_plan_create%s / pks_plan_launch)" % ("_tv" if tv else "")) if batched
+                   else ("pks_filter_smooth_tv" if tv else "pks_filter_smooth")},
+        "plan_ms_per_step": results["fp64"]["plan_sec"] * 1e3,
+        "eager_ms_per_step": results["fp64"]["eager_sec"] * 1e3,
         "max_rel_err": {k: float("%.3e" % v) for k, v in errs["fp64"].items()},
         "err_sample": "all steps" if not batched else "%d of %d sequences" % (len(sample), w.B),
         "roofline": rl64,
         "kernels_ms": {k: round(v, 4) for k, v in kern64.items()},
         "mixed": {
-            "value": T / secm, "ms_per_step": secm * 1e3, "dtype": "f32 storage/products, f64 solves",
+            "value": T / secm, "ms_per_step": secm * 1e3,
+            "plan_ms_per_step": results["mixed"]["plan_sec"] * 1e3,
+            "eager_ms_per_step": results["mixed"]["eager_sec"] * 1e3,
+            "dtype": "f32 storage, f64 arithmetic" if f64_mixed else "f32 storage/products, f64 solves",
             "speedup_vs_fp64": sec64 / secm,
             "max_rel_err": {k: float("%.3e" % v) for k, v in errs["mixed"].items()},
             "roofline": rlm,

@@ -212,6 +212,22 @@ __device__ __forceinline__ double pick(const f64x4& t, int q) {
     return q == 0 ? t[0] : (q == 1 ? t[1] : (q == 2 ? t[2] : t[3]));
 }
 
+// the tile of X^T through the wave's LDS stage (exact; keeps the matrix cores
+// free for products)
+__device__ __forceinline__ f64x4 tr(const f64x4& x, double* st) {
+    const int li = lane_i(), lk = lane_k();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) st[(4 * v + lk) * 17 + li] = x[v];
+    wave_sync_lds();
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = st[li * 17 + 4 * v + lk];
+    wave_sync_lds();
+    return t;
+}
+// (X + X^T) / 2 + add
+__device__ __forceinline__ f64x4 symt(const f64x4& x, const f64x4& add, double* st) { return sym(x, tr(x, st), add); }
+
 // ---------------------------------------------------------------------------
 // Inverses by Gauss-Jordan elimination in the register layout.  The pivot's
 // column reaches the lanes of each row of 16 by a DPP broadcast, the pivot row
@@ -326,15 +342,15 @@ struct FConst {
 //   A = A_j X1, b = A_j x2 + b_j, C = A_j X3 A_j^T + C_j,
 //   eta = X1^T (eta_j - J_j b_i) + eta_i, J = X1^T J_j A_i + J_i
 __device__ __forceinline__ void fout(FE& e, const f64x4& X1, const f64x4& x2, const f64x4& X3, const f64x4& AjT,
-                                     const f64x4& bj, const f64x4& Cj, const f64x4& etaj, const f64x4& Jj) {
+                                     const f64x4& bj, const f64x4& Cj, const f64x4& etaj, const f64x4& Jj, double* st) {
     const f64x4 w = mm(-Jj, e.b, etaj);
     const f64x4 JA = mm(Jj, e.A);
     e.A = mm(AjT, X1);
     e.b = mm(AjT, x2, bj);
     const f64x4 U = mm(X3, AjT);                     // X3^T A_j^T
-    e.C = sym(mm(AjT, U), mm(U, AjT), Cj);      // A_j sym(X3) A_j^T + C_j
+    e.C = symt(mm(AjT, U), Cj, st);                 // A_j sym(X3) A_j^T + C_j
     e.eta = mm(X1, w, e.eta);
-    e.J = sym(mm(X1, JA), mm(JA, X1), e.J);
+    e.J = symt(mm(X1, JA), e.J, st);
 }
 
 // e <- e (x) (A_j, b_j, C_j, eta_j, J_j), Lemma 2, for two block elements: the
@@ -345,7 +361,7 @@ __device__ __forceinline__ void fcombine(FE& e, const f64x4& AjT, const f64x4& b
     bool ok = true;
     const f64x4 NT = inv_piv(mm(Jj, e.C, I), n, st, ok);
     const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
-    fout(e, mm(NT, e.A), mm(NT, v), mm(NT, e.C), AjT, bj, Cj, etaj, Jj);
+    fout(e, mm(NT, e.A), mm(NT, v), mm(NT, e.C), AjT, bj, Cj, etaj, Jj, st);
 }
 
 // e <- e (x) a_j for a single step j > 1, where J_j = G^T S^-1 G (G = H F,
@@ -353,37 +369,38 @@ __device__ __forceinline__ void fcombine(FE& e, const f64x4& AjT, const f64x4& b
 // positive definite Sigma = S + G C_i G^T, so
 //   X1 = A_i - K (G A_i), x2 = v - K (G v), X3 = C_i - K (G C_i).
 template <int KY>
-__device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64x4& bj, const f64x4& etaj) {
+__device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64x4& bj, const f64x4& etaj, double* st) {
 
     const f64x4 Y = mm(e.C, f.GT);                   // C_i G^T
-    const f64x4 YT = mm(f.GT, e.C);                  // G C_i
+    const f64x4 YT = tr(Y, st);                      // G C_i
     bool ok = true;
-    const f64x4 Z = inv_spd(sym(mm(f.GT, Y), mm(Y, f.GT), f.S), f.ny, ok);
+    const f64x4 Z = inv_spd(symt(mm(f.GT, Y), f.S, st), f.ny, ok);
     const f64x4 nKT = -mm<KY>(Z, YT);                    // tile of -K^T
     const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
     const f64x4 X1 = mm<KY>(nKT, mm(f.GT, e.A), e.A);
     const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
     const f64x4 X3 = mm<KY>(nKT, YT, e.C);
-    fout(e, X1, x2, X3, f.AT, bj, f.C, etaj, f.J);
+    fout(e, X1, x2, X3, f.AT, bj, f.C, etaj, f.J, st);
 }
 
 // filtered moments (m, P) <- (m, P) (x) a_j for a single step j > 1 (the
 // prefix element has A = 0): with K = P G^T Sigma^-1, Sigma = S + G P G^T,
 //   m = A_j (v - K G v) + b_j (v = m + P eta_j), P = A_j (P - K G P) A_j^T + C_j
 template <int KY>
-__device__ __forceinline__ void fcarry_fresh(f64x4& m, f64x4& P, const FConst& f, const f64x4& bj, const f64x4& etaj) {
+__device__ __forceinline__ void fcarry_fresh(f64x4& m, f64x4& P, const FConst& f, const f64x4& bj, const f64x4& etaj,
+                                             double* st) {
 
     const f64x4 Y = mm(P, f.GT);                     // P G^T
-    const f64x4 YT = mm(f.GT, P);                    // G P
+    const f64x4 YT = tr(Y, st);                      // G P
     bool ok = true;
-    const f64x4 Z = inv_spd(sym(mm(f.GT, Y), mm(Y, f.GT), f.S), f.ny, ok);
+    const f64x4 Z = inv_spd(symt(mm(f.GT, Y), f.S, st), f.ny, ok);
     const f64x4 nKT = -mm<KY>(Z, YT);
     const f64x4 v = mm(P, etaj, m);
     const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
     const f64x4 X3 = mm<KY>(nKT, YT, P);
     m = mm(f.AT, x2, bj);
     const f64x4 U = mm(X3, f.AT);
-    P = sym(mm(f.AT, U), mm(U, f.AT), f.C);
+    P = symt(mm(f.AT, U), f.C, st);
 }
 
 // constants of the smoother kernels: tiles of F^T and Q (the identity beyond
@@ -396,15 +413,15 @@ struct SConst {
 // smoothing element of step k (Lemma 3) from the filtered (m, P):
 //   E = P F^T (F P F^T + Q)^-1, g = m - E (F m + u), L = P - E F P,
 // returned as the tile of E^T, g and L
-__device__ __forceinline__ void selem(const f64x4& m, const f64x4& P, const SConst& c, bool& ok, f64x4& ET, f64x4& g,
-                                      f64x4& L) {
+__device__ __forceinline__ void selem(const f64x4& m, const f64x4& P, const SConst& c, double* st, bool& ok, f64x4& ET,
+                                      f64x4& g, f64x4& L) {
 
     const f64x4 FP = mm(c.FT, P);
-    const f64x4 PFT = mm(P, c.FT);
-    const f64x4 Z = inv_spd(sym(mm(c.FT, PFT), mm(PFT, c.FT), c.Q), c.n, ok);
+    const f64x4 PFT = tr(FP, st);                     // P F^T
+    const f64x4 Z = inv_spd(symt(mm(c.FT, PFT), c.Q, st), c.n, ok);
     ET = mm(Z, FP);                                  // (F P F^T + Q)^-1 F P
     g = mm(-ET, mm(c.FT, m, c.u), m);
-    const f64x4 EFP = mm(ET, FP), EFPt = mm(FP, ET);
+    const f64x4 EFP = mm(ET, FP), EFPt = tr(EFP, st);
 #pragma unroll
     for (int v = 0; v < 4; ++v) L[v] = P[v] - 0.5 * (EFP[v] + EFPt[v]);
 }
@@ -412,17 +429,18 @@ __device__ __forceinline__ void selem(const f64x4& m, const f64x4& P, const SCon
 // (E, g, L) <- e_k (x) (E, g, L), Lemma 4, e_k given by the tile of E_k^T:
 //   E = E_k E, g = E_k g + g_k, L = E_k L E_k^T + L_k
 __device__ __forceinline__ void sfold(f64x4& E, f64x4& g, f64x4& L, const f64x4& EkT, const f64x4& gk,
-                                      const f64x4& Lk) {
+                                      const f64x4& Lk, double* st) {
     E = mm(EkT, E);
     g = mm(EkT, g, gk);
     const f64x4 T1T = mm(L, EkT);                    // (E_k L)^T
-    L = sym(mm(T1T, EkT), mm(EkT, T1T), Lk);
+    L = symt(mm(T1T, EkT), Lk, st);
 }
 // smoothed moments (m, P) <- e_k (x) (m, P) (the suffix element has E = 0)
-__device__ __forceinline__ void scarry(f64x4& m, f64x4& P, const f64x4& EkT, const f64x4& gk, const f64x4& Lk) {
+__device__ __forceinline__ void scarry(f64x4& m, f64x4& P, const f64x4& EkT, const f64x4& gk, const f64x4& Lk,
+                                       double* st) {
     m = mm(EkT, m, gk);
     const f64x4 T1T = mm(P, EkT);
-    P = sym(mm(T1T, EkT), mm(EkT, T1T), Lk);
+    P = symt(mm(T1T, EkT), Lk, st);
 }
 
 __host__ __device__ inline int slices(int n) { return (n + 3) >> 2; }
@@ -476,6 +494,7 @@ __device__ __forceinline__ int64_t blk_end(const W16Args& w, int64_t k0) {
 // ---------------------------------------------------------------------------
 template <typename R, int KY>
 __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
+    __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = a.nx, ny = a.ny;
@@ -493,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
         e.eta = zero4();
         e.J = zero4();
     } else {
-        e.A = mm(f.AT, eye());
+        e.A = tr(f.AT, st);
         e.b = mm<KY>(f.KT, yk, f.c);
         e.C = f.C;
         e.eta = mm<KY>(f.WT, yk, f.w);
@@ -501,7 +520,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
     }
     for (int64_t k = k0 + 1; k < k1; ++k) {
         yk = load_vec(y + k * ny, ny);
-        fcombine_fresh<KY>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w));
+        fcombine_fresh<KY>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
     }
     double* rec = w.agg[0] + (size_t)blockIdx.x * kFRec;
     put_tile(rec + kFA, e.A);
@@ -531,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const dou
         e.b = load_vec(ri + kFb, 16);
         e.eta = load_vec(ri + kFeta, 16);
         const f64x4 I = eye();
-        fcombine(e, mm(Aj, I), bj, Cj, etaj, Jj, I, st, n);
+        fcombine(e, tr(Aj, st), bj, Cj, etaj, Jj, I, st, n);
     }
     put_tile(ro + kFA, e.A);
     put_tile(ro + kFC, e.C);
@@ -542,6 +561,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const dou
 
 template <typename R, int KY>
 __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
+    __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = a.nx, ny = a.ny;
@@ -563,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
             m = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
             P = load_tile(cst + CL.C1, n, n, n);
         } else {
-            fcarry_fresh<KY>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w));
+            fcarry_fresh<KY>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
         }
         store_vec(mo + k * n, m, n);
         store_tile(Po + k * n * n, P, n);
@@ -582,6 +602,7 @@ __device__ __forceinline__ void load_moments(const ScanArgs& a, int64_t k, f64x4
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
+    __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
@@ -595,14 +616,14 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
         L = P;
     } else {
         f64x4 ET;
-        selem(m, P, c, ok, ET, g, L);
-        E = mm(ET, eye());
+        selem(m, P, c, st, ok, ET, g, L);
+        E = tr(ET, st);
     }
     for (int64_t k = k1 - 2; k >= k0; --k) {
         load_moments<R>(a, k, m, P);
         f64x4 ET, gk, Lk;
-        selem(m, P, c, ok, ET, gk, Lk);
-        sfold(E, g, L, ET, gk, Lk);
+        selem(m, P, c, st, ok, ET, gk, Lk);
+        sfold(E, g, L, ET, gk, Lk, st);
     }
     if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
     double* rec = w.agg[0] + (size_t)blockIdx.x * kSRec;
@@ -613,6 +634,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
 
 // out[i] = in[i] (x) in[i + d] (i + d < nb), else in[i]
 __global__ __launch_bounds__(kThreads) void k_w16_smoother_ks(W16Args w, const double* in, double* out, int64_t d) {
+    __shared__ double st[kStage];
     const int64_t i = blockIdx.x;
     const double* ri = in + (size_t)i * kSRec;
     double* ro = out + (size_t)i * kSRec;
@@ -626,7 +648,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_ks(W16Args w, const d
         E = get_tile(rj + kSE);
         L = get_tile(rj + kSL);
         g = load_vec(rj + kSg, 16);
-        sfold(E, g, L, mm(Ei, eye()), gi, Li);
+        sfold(E, g, L, tr(Ei, st), gi, Li, st);
     }
     put_tile(ro + kSE, E);
     put_tile(ro + kSL, L);
@@ -635,6 +657,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_ks(W16Args w, const d
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
+    __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = a.nx;
@@ -657,8 +680,8 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
             Ps = P;
         } else {
             f64x4 ET, gk, Lk;
-            selem(m, P, c, ok, ET, gk, Lk);
-            scarry(ms, Ps, ET, gk, Lk);
+            selem(m, P, c, st, ok, ET, gk, Lk);
+            scarry(ms, Ps, ET, gk, Lk, st);
         }
         store_vec(mso + k * n, ms, n);
         store_tile(Pso + k * n * n, Ps, n);

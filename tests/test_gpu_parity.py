@@ -301,6 +301,30 @@ def test_plan_replays_match_eager(pks, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("workload,T", [(1, 1024), (2, 65536), (3, 6000)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plan_single_sequence(pks, workload, T, precision):
+    """One sequence through a captured plan (the launch the benchmark times):
+    every replay bitwise equal to the eager filter_smooth, and against the
+    oracle (small states, and nx = 16 through the register-resident path)."""
+    w = wl.workload(workload, T=T)
+    dm = pks.to_device(w.model)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    yd = torch.as_tensor(w.y).to("cuda", dt)
+    eager = pks.filter_smooth(dm, yd, precision)
+    plan = pks.Plan(dm, yd, None, precision)
+    for _ in range(3):
+        outs = [t.clone() for t in plan.launch()]
+        torch.cuda.synchronize()
+        for e, o in zip(eager, outs):
+            assert torch.equal(e.contiguous().view(torch.int64 if e.element_size() == 8 else torch.int32),
+                               o.contiguous().view(torch.int64 if o.element_size() == 8 else torch.int32))
+    plan.close()
+    out = {k: v.double().cpu().numpy() for k, v in zip(("m", "P", "ms", "Ps"), outs)}
+    ref = oracle_run(w.model, ref_input(w.y, precision))
+    assert_parity(out, ref, precision, "plan, one sequence, workload %d T=%d" % (workload, T))
+
+
 def test_numeric_flag_single_and_batched(pks):
     mo = wl.cv_model(1.0, 0.25)
     bad = wl.Model(mo.F, mo.Q, mo.H, -np.eye(2), mo.m0, mo.P0)

@@ -87,10 +87,14 @@ def test_tv_irregular_cv_T2pow20(pks, precision):
     check_tv(pks, w.model, w.y, precision, "irregular cv T=2^20", floor="none")
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 2), (6, 3)])
+@pytest.mark.parametrize("nx,ny", [(4, 2), (6, 3), (20, 3)])
 def test_tv_with_equal_rows_equals_time_invariant(pks, nx, ny):
-    """A time-varying model whose rows are all one model: the same constants,
-    kernels and arithmetic as the time-invariant call, so bitwise the same."""
+    """A time-varying model whose rows are all one model.  For nx <= 4 and
+    nx > 16 the time-invariant call runs the same constants, kernels and
+    arithmetic, so the results are bitwise the same; for 5 <= nx <= 16 one
+    sequence of a time-invariant model runs the register-resident kernels
+    (the time-varying one the packed-sequence kernels): the same mathematics
+    in another order, compared at the parity tolerance."""
     rng = np.random.default_rng(31 + nx)
     mo = wl.random_small_model(nx, ny, rng) if nx <= 4 else wl.random_stable_model(nx, ny, rng,
                                                                                      with_offsets=True)
@@ -98,6 +102,7 @@ def test_tv_with_equal_rows_equals_time_invariant(pks, nx, ny):
     y, _ = wl.simulate(mo, T, rng)
     rep = lambda a: None if a is None else np.broadcast_to(a, (T,) + a.shape).copy()
     tv = wl.Model(rep(mo.F), rep(mo.Q), rep(mo.H), rep(mo.R), mo.m0, mo.P0, rep(mo.u), rep(mo.d))
+    same_kernels = nx <= 4 or nx > 16
     for precision in ("fp64", "mixed"):
         dt = torch.float64 if precision == "fp64" else torch.float32
         yd = torch.as_tensor(y).to("cuda", dt)
@@ -105,7 +110,12 @@ def test_tv_with_equal_rows_equals_time_invariant(pks, nx, ny):
         b = pks.filter_smooth(pks.to_device(tv, time_varying=True), yd, precision)
         torch.cuda.synchronize()
         for x, z in zip(a, b):
-            assert torch.equal(x, z), precision
+            if same_kernels:
+                assert torch.equal(x, z), precision
+            else:
+                err = wl.max_rel_err(x.double().cpu().numpy(), z.double().cpu().numpy(),
+                                     "rms" if precision == "mixed" else "none")
+                assert err <= TOL[precision], (precision, err)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
