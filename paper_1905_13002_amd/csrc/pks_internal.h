@@ -216,5 +216,10 @@ bool w16_applies(int nx, int ny, bool single_invariant);
 int64_t w16_default_blocks(int64_t total);
 size_t w16_ws_bytes(int64_t total);
 hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
+// the model constants of one time-invariant model with 5 <= nx <= 16, ny <= 16
+// in one wavefront (what: 1, 2 or 3 as for launch_precompute); false: not
+// applicable, nothing launched
+bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* consts64, float* consts32, int* status,
+                           int* model_fail, int what, bool reset, hipStream_t s);
 
 }  // namespace pks

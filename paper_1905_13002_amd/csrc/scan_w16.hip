@@ -518,8 +518,11 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
         e.eta = mm<KY>(f.WT, yk, f.w);
         e.J = f.J;
     }
+    // y of the next step is loaded while the current one is folded
+    f64x4 ynext = load_vec(y + (k0 + 1 < k1 ? k0 + 1 : k0) * ny, ny);
     for (int64_t k = k0 + 1; k < k1; ++k) {
-        yk = load_vec(y + k * ny, ny);
+        yk = ynext;
+        ynext = load_vec(y + (k + 1 < k1 ? k + 1 : k) * ny, ny);
         fcombine_fresh<KY>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
     }
     double* rec = w.agg[0] + (size_t)blockIdx.x * kFRec;
@@ -576,8 +579,10 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
         m = load_vec(rec + kFb, 16);
         P = get_tile(rec + kFC);
     }
+    f64x4 ynext = load_vec(y + k0 * ny, ny);
     for (int64_t k = k0; k < k1; ++k) {
-        const f64x4 yk = load_vec(y + k * ny, ny);
+        const f64x4 yk = ynext;
+        ynext = load_vec(y + (k + 1 < k1 ? k + 1 : k) * ny, ny);
         if (k == 0) {
             const double* cst = a.consts64;
             m = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
@@ -619,8 +624,13 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
         selem(m, P, c, st, ok, ET, g, L);
         E = tr(ET, st);
     }
+    // the moments of the next step down are loaded while the current one is folded
+    f64x4 mn, Pn;
+    load_moments<R>(a, k1 - 2 >= k0 ? k1 - 2 : k0, mn, Pn);
     for (int64_t k = k1 - 2; k >= k0; --k) {
-        load_moments<R>(a, k, m, P);
+        m = mn;
+        P = Pn;
+        load_moments<R>(a, k - 1 >= k0 ? k - 1 : k0, mn, Pn);
         f64x4 ET, gk, Lk;
         selem(m, P, c, st, ok, ET, gk, Lk);
         sfold(E, g, L, ET, gk, Lk, st);
@@ -672,9 +682,11 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
         ms = load_vec(rec + kSg, 16);
         Ps = get_tile(rec + kSL);
     }
+    f64x4 mn, Pn;
+    load_moments<R>(a, k1 - 1, mn, Pn);
     for (int64_t k = k1 - 1; k >= k0; --k) {
-        f64x4 m, P;
-        load_moments<R>(a, k, m, P);
+        const f64x4 m = mn, P = Pn;
+        load_moments<R>(a, k - 1 >= k0 ? k - 1 : k0, mn, Pn);
         if (k == a.total - 1) {
             ms = m;
             Ps = P;
@@ -687,6 +699,123 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
         store_tile(Pso + k * n * n, Ps, n);
     }
     if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Model constants of one model (5 <= nx <= 16, ny <= 16) in one wavefront,
+// the same fields and formulas as the cooperative precompute kernel (Lemma 1
+// for k > 1 and for the first step, the smoother's F, Q, u), with the
+// positive definite solves as register inverses (a non-positive pivot marks
+// the model as failed, its constants NaN).
+// ---------------------------------------------------------------------------
+struct PreArgs {
+    int nx, ny;
+    const double *F, *u, *Q, *H, *d, *R, *m0, *P0;
+    double* consts64;
+    float* consts32;     // nullptr: FP64 only
+    int* status;
+    int* model_fail;
+    int what;            // 1: filter constants, 2: smoother constants, 3: both
+    int reset;
+};
+
+template <typename T>
+__device__ __forceinline__ void put_mat(T* X, const f64x4& t, int rows, int cols) {
+    const int li = lane_i(), lk = lane_k();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * v + lk;
+        if (r < rows && li < cols) X[r * cols + li] = T(t[v]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void put_fields(T* o, const ConstLayout& CL, int n, int m, int what, const f64x4& A,
+                                           const f64x4& C, const f64x4& J, const f64x4& K, const f64x4& W,
+                                           const f64x4& c, const f64x4& w, const f64x4& K1, const f64x4& c1,
+                                           const f64x4& C1, const f64x4& G, const f64x4& S, const f64x4& e,
+                                           const f64x4& F, const f64x4& Q, const f64x4& u) {
+    if (what & 1) {
+        put_mat(o + CL.A, A, n, n);
+        put_mat(o + CL.C, C, n, n);
+        put_mat(o + CL.J, J, n, n);
+        put_mat(o + CL.K, K, n, m);
+        put_mat(o + CL.W, W, n, m);
+        store_vec(o + CL.c, c, n);
+        store_vec(o + CL.w, w, n);
+        put_mat(o + CL.K1, K1, n, m);
+        store_vec(o + CL.c1, c1, n);
+        put_mat(o + CL.C1, C1, n, n);
+        put_mat(o + CL.G, G, m, n);
+        put_mat(o + CL.S, S, m, m);
+        store_vec(o + CL.e, e, m);
+    }
+    if (what & 2) {
+        put_mat(o + CL.F, F, n, n);
+        put_mat(o + CL.Q, Q, n, n);
+        store_vec(o + CL.u, u, n);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_w16_precompute(PreArgs a) {
+    __shared__ double st[kStage];
+    if (threadIdx.x == 0 && (a.reset || a.status[1] != kStatusMagic)) {
+        a.status[0] = kStatusOk;
+        a.status[1] = kStatusMagic;
+    }
+    const int n = a.nx, m = a.ny;
+    const ConstLayout CL = const_layout(n, m);
+    const f64x4 F = load_tile(a.F, n, n, n), FT = load_tile_t(a.F, n, n, n);
+    const f64x4 Q = load_tile(a.Q, n, n, n);
+    const f64x4 u = a.u ? load_vec(a.u, n) : zero4();
+    const f64x4 Z0 = zero4();
+    bool ok = true;
+    f64x4 A = Z0, C = Z0, J = Z0, K = Z0, W = Z0, c = Z0, w = Z0, K1 = Z0, c1 = Z0, C1 = Z0, G = Z0, S = Z0, e = Z0;
+    if (a.what & 1) {
+        const f64x4 HT = load_tile_t(a.H, m, n, n), R = load_tile(a.R, m, m, m);
+        const f64x4 d = a.d ? load_vec(a.d, m) : Z0;
+        // k > 1: S = H Q H^T + R, K = Q H^T S^-1, G = H F, W = G^T S^-1,
+        // J = W G, A = F - K G, C = Q - K H Q, e = H u + d, c = u - K e, w = -W e
+        const f64x4 T1 = mm(HT, Q);                               // H Q
+        S = symt(mm(tr(T1, st), HT, R), Z0, st);
+        const f64x4 Si = inv_spd(S, m, ok);
+        const f64x4 Kt = mm(Si, T1);                              // S^-1 H Q
+        G = mm(HT, F);
+        const f64x4 Zt = mm(Si, G);                               // S^-1 H F
+        K = tr(Kt, st);
+        W = tr(Zt, st);
+        J = symt(mm(G, Zt), Z0, st);
+        const f64x4 nKt = -Kt;
+        A = mm(nKt, G, F);
+        C = symt(mm(nKt, T1, Q), Z0, st);
+        e = mm(HT, u, d);
+        c = mm(nKt, e, u);
+        w = mm(-Zt, e);
+        // the first step: m1 = F m0 + u, P1 = F P0 F^T + Q, S1 = H P1 H^T + R,
+        // K1 = P1 H^T S1^-1, c1 = m1 - K1 (H m1 + d), C1 = P1 - K1 S1 K1^T
+        const f64x4 m1 = mm(FT, load_vec(a.m0, n), u);
+        const f64x4 FP0 = mm(FT, load_tile(a.P0, n, n, n));
+        const f64x4 P1 = symt(mm(tr(FP0, st), FT, Q), Z0, st);
+        const f64x4 T2 = mm(HT, P1);                              // H P1
+        const f64x4 S1 = symt(mm(tr(T2, st), HT, R), Z0, st);
+        const f64x4 K1t = mm(inv_spd(S1, m, ok), T2);             // S1^-1 H P1
+        K1 = tr(K1t, st);
+        c1 = mm(-K1t, mm(HT, m1, d), m1);
+        const f64x4 U = mm(K1t, S1);                              // K1 S1
+        C1 = symt(mm(-tr(U, st), K1t, P1), Z0, st);
+    }
+    const f64x4 Fs = (a.what & 2) ? F : Z0, Qs = (a.what & 2) ? Q : Z0, us = (a.what & 2) ? u : Z0;
+    if (ok) {
+        put_fields(a.consts64, CL, n, m, a.what, A, C, J, K, W, c, w, K1, c1, C1, G, S, e, Fs, Qs, us);
+        if (a.consts32)
+            put_fields(a.consts32, CL, n, m, a.what, A, C, J, K, W, c, w, K1, c1, C1, G, S, e, Fs, Qs, us);
+    } else {
+        for (int i = threadIdx.x; i < CL.words; i += kThreads) {
+            a.consts64[i] = __builtin_nan("");
+            if (a.consts32) a.consts32[i] = __builtin_nanf("");
+        }
+    }
+    if ((a.what & 1) && threadIdx.x == 0) a.model_fail[0] = ok ? 0 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -755,6 +884,25 @@ bool w16_applies(int nx, int ny, bool single_invariant) {
 int64_t w16_default_blocks(int64_t total) { return w16::blocks_for(total); }
 
 size_t w16_ws_bytes(int64_t total) { return 2 * w16::buffer_bytes(w16::blocks_for(total)); }
+
+bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* consts64, float* consts32, int* status,
+                           int* model_fail, int what, bool reset, hipStream_t s) {
+    if (!w16_applies(nx, ny, true) || what < 1 || what > 3) return false;
+    w16::PreArgs p;
+    p.nx = nx;
+    p.ny = ny;
+    p.F = model.F; p.u = model.u; p.Q = model.Q;
+    p.H = model.H; p.d = model.d; p.R = model.R;
+    p.m0 = model.m0; p.P0 = model.P0;
+    p.consts64 = consts64;
+    p.consts32 = consts32;
+    p.status = status;
+    p.model_fail = model_fail;
+    p.what = what;
+    p.reset = reset ? 1 : 0;
+    hipLaunchKernelGGL(w16::k_w16_precompute, dim3(1), dim3(w16::kThreads), 0, s, p);
+    return true;
+}
 
 hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
     using namespace w16;
