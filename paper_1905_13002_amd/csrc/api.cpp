@@ -226,11 +226,11 @@ pks_status enqueue(const pks_model& model, int32_t B, const int64_t* offsets, in
     if (!small) {
         void* region = static_cast<char*>(ws) + L.large;
         if (passes & 1) {
-            e = launch_large(a, region, mixed, false, s);
+            e = launch_large(a, region, mixed, false, passes == 3, s);
             if (e != hipSuccess) return hip_fail(e, "filter kernels");
         }
         if (passes & 2) {
-            e = launch_large(a, region, mixed, true, s);
+            e = launch_large(a, region, mixed, true, passes == 3, s);
             if (e != hipSuccess) return hip_fail(e, "smoother kernels");
         }
         return PKS_OK;

@@ -208,14 +208,16 @@ hipError_t launch_hmm(int K, int64_t T, const double* Pi, const double* p0, cons
 size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec);
 // the default (and largest) number of time blocks of the large-state scans
 int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed);
-hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
+// both: the filter and the smoother of one call (the smoother follows the
+// filter on the same stream and workspace)
+hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s);
 
 // register-resident large-state path (scan_w16.hip): one sequence, one
 // time-invariant model, 5 <= nx <= 16, ny <= 16
 bool w16_applies(int nx, int ny, bool single_invariant);
 int64_t w16_default_blocks(int64_t total);
 size_t w16_ws_bytes(int64_t total);
-hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s);
+hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s);
 // the model constants of one time-invariant model with 5 <= nx <= 16, ny <= 16
 // in one wavefront (what: 1, 2 or 3 as for launch_precompute); false: not
 // applicable, nothing launched

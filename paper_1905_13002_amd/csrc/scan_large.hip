@@ -67,10 +67,10 @@ size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec) {
     return lds_path > reg_path ? lds_path : reg_path;
 }
 
-hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
+hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s) {
     using namespace lg;
     if (w16_applies(a.nx, a.ny, a.offsets == nullptr && a.step_stride == 0))
-        return launch_w16(a, region, mixed, smoother, s);
+        return launch_w16(a, region, mixed, smoother, both, s);
     LargeArgs la;
     la.s = a;
     const int64_t nb_max = large_blocks(a.total, a.nx, a.ny, mixed);

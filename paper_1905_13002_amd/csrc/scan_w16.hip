@@ -56,6 +56,10 @@ struct W16Args {
     int64_t blen, nblocks;
     double* agg[2];          // ping-pong block elements [nblocks][kFRec]
     int final_buf;
+    // smoothing elements of every step [total][kSRec], written by the filter
+    // down-sweep of a combined filter + smoother call and read by the
+    // smoother kernels instead of rebuilding them (nullptr: rebuilt)
+    double* elem;
 };
 
 __device__ __forceinline__ int lane_i() { return threadIdx.x & 15; }          // column
@@ -562,6 +566,15 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const dou
     store_vec(ro + kFeta, e.eta, 16);
 }
 
+// x rounded to the storage type R (the value a later kernel reads back)
+template <typename R>
+__device__ __forceinline__ f64x4 stored(const f64x4& x) {
+    f64x4 t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = double(R(x[v]));
+    return t;
+}
+
 template <typename R, int KY>
 __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     __shared__ double st[kStage];
@@ -570,6 +583,9 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     const int n = a.nx, ny = a.ny;
     const int64_t blk = blockIdx.x, k0 = blk * w.blen, k1 = blk_end(w, k0);
     const FConst f = load_fconst(a, CL);
+    SConst sc = {};
+    if (w.elem) sc = load_sconst(a, CL);
+    bool ok = true;
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
     R* Po = static_cast<R*>(a.P);
@@ -592,7 +608,18 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
         }
         store_vec(mo + k * n, m, n);
         store_tile(Po + k * n * n, P, n);
+        if (w.elem && k + 1 < a.total) {
+            // the smoothing element of step k (Lemma 3), from the moments as
+            // stored (the same inputs the smoother kernels would read back)
+            f64x4 ET, g, L;
+            selem(stored<R>(m), stored<R>(P), sc, st, ok, ET, g, L);
+            double* e = w.elem + (size_t)k * kSRec;
+            put_tile(e + kSE, ET);
+            put_tile(e + kSL, L);
+            store_vec(e + kSg, g, 16);
+        }
     }
+    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -611,9 +638,38 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
-    const SConst c = load_sconst(a, CL);
     bool ok = true;
     f64x4 m, P, E, g, L;
+    if (w.elem) {           // the elements the filter down-sweep stored
+        if (k1 == a.total) {
+            load_moments<R>(a, k1 - 1, m, P);
+            E = zero4();
+            g = m;
+            L = P;
+        } else {
+            const double* e = w.elem + (size_t)(k1 - 1) * kSRec;
+            E = tr(get_tile(e + kSE), st);
+            L = get_tile(e + kSL);
+            g = load_vec(e + kSg, 16);
+        }
+        // the next element down is loaded while the current one is folded
+        const double* e = w.elem + (size_t)(k1 - 2 >= k0 ? k1 - 2 : k0) * kSRec;
+        f64x4 ETn = get_tile(e + kSE), gn = load_vec(e + kSg, 16), Ln = get_tile(e + kSL);
+        for (int64_t k = k1 - 2; k >= k0; --k) {
+            const f64x4 ETk = ETn, gk = gn, Lk = Ln;
+            e = w.elem + (size_t)(k - 1 >= k0 ? k - 1 : k0) * kSRec;
+            ETn = get_tile(e + kSE);
+            gn = load_vec(e + kSg, 16);
+            Ln = get_tile(e + kSL);
+            sfold(E, g, L, ETk, gk, Lk, st);
+        }
+        double* rec = w.agg[0] + (size_t)blockIdx.x * kSRec;
+        put_tile(rec + kSE, E);
+        put_tile(rec + kSL, L);
+        store_vec(rec + kSg, g, 16);
+        return;
+    }
+    const SConst c = load_sconst(a, CL);
     load_moments<R>(a, k1 - 1, m, P);
     if (k1 == a.total) {    // the last step: E = 0, g = m, L = P
         E = zero4();
@@ -681,6 +737,26 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
         const double* rec = w.agg[w.final_buf] + (size_t)(blk + 1) * kSRec;
         ms = load_vec(rec + kSg, 16);
         Ps = get_tile(rec + kSL);
+    }
+    if (w.elem) {           // the elements the filter down-sweep stored
+        // the element of step k - 1 is loaded while step k is folded (the last
+        // step of the sequence has none: its slot is never read)
+        const int64_t kl = a.total - 1;
+        auto slot = [&](int64_t k) { return w.elem + (size_t)(k < kl ? k : (kl > 0 ? kl - 1 : 0)) * kSRec; };
+        const double* e = slot(k1 - 1);
+        f64x4 ETn = get_tile(e + kSE), gn = load_vec(e + kSg, 16), Ln = get_tile(e + kSL);
+        for (int64_t k = k1 - 1; k >= k0; --k) {
+            const f64x4 ETk = ETn, gk = gn, Lk = Ln;
+            e = slot(k - 1 >= k0 ? k - 1 : k0);
+            ETn = get_tile(e + kSE);
+            gn = load_vec(e + kSg, 16);
+            Ln = get_tile(e + kSL);
+            if (k == kl) load_moments<R>(a, k, ms, Ps);
+            else scarry(ms, Ps, ETk, gk, Lk, st);
+            store_vec(mso + k * n, ms, n);
+            store_tile(Pso + k * n * n, Ps, n);
+        }
+        return;
     }
     f64x4 mn, Pn;
     load_moments<R>(a, k1 - 1, mn, Pn);
@@ -829,6 +905,13 @@ int64_t blocks_for(int64_t total) {
 
 size_t buffer_bytes(int64_t nb) { return ((size_t)nb * kFRec * sizeof(double) + 255) & ~size_t(255); }
 
+// sequences up to this length keep every step's smoothing element between
+// the filter down-sweep and the smoother kernels (4.2 KB a step)
+constexpr int64_t kMaxStoredSteps = int64_t(1) << 18;
+size_t elem_bytes(int64_t total) {
+    return total <= kMaxStoredSteps ? (((size_t)total * kSRec * sizeof(double) + 255) & ~size_t(255)) : 0;
+}
+
 template <typename R>
 hipError_t run(W16Args w, bool smoother, hipStream_t s) {
     const dim3 grid((unsigned)w.nblocks), block(kThreads);
@@ -883,7 +966,7 @@ bool w16_applies(int nx, int ny, bool single_invariant) {
 
 int64_t w16_default_blocks(int64_t total) { return w16::blocks_for(total); }
 
-size_t w16_ws_bytes(int64_t total) { return 2 * w16::buffer_bytes(w16::blocks_for(total)); }
+size_t w16_ws_bytes(int64_t total) { return 2 * w16::buffer_bytes(w16::blocks_for(total)) + w16::elem_bytes(total); }
 
 bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* consts64, float* consts32, int* status,
                            int* model_fail, int what, bool reset, hipStream_t s) {
@@ -904,7 +987,7 @@ bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* const
     return true;
 }
 
-hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipStream_t s) {
+hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s) {
     using namespace w16;
     W16Args w;
     w.s = a;
@@ -917,6 +1000,9 @@ hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, hipSt
     w.agg[0] = reinterpret_cast<double*>(base);
     w.agg[1] = reinterpret_cast<double*>(base + buffer_bytes(nb_max));
     w.final_buf = 0;
+    // a combined filter + smoother call passes the smoothing elements from
+    // the filter down-sweep to the smoother kernels
+    w.elem = (both && elem_bytes(a.total) > 0) ? reinterpret_cast<double*>(base + 2 * buffer_bytes(nb_max)) : nullptr;
     return mixed ? run<float>(w, smoother, s) : run<double>(w, smoother, s);
 }
 

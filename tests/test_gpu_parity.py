@@ -165,6 +165,19 @@ def test_separate_calls_match_fused(pks, prec):
             assert wl.max_rel_err(a[k], b[k], floor="rms") <= 1e-5, k
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separate_calls_match_fused_register_path(pks, prec):
+    """nx = 16 (register-resident kernels): the combined call's filter
+    down-sweep also builds every smoothing element (from the moments as
+    stored) for the smoother kernels, which the separate pks_smooth rebuilds
+    from the same stored moments: bitwise equal in both precisions."""
+    w = wl.workload(3, T=3000)
+    a = gpu_run(pks, w.model, w.y, prec)
+    b = gpu_run(pks, w.model, w.y, prec, separate=True)
+    for k in ("m", "P", "ms", "Ps"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("ept,ept1", [(4, 0), (8, 0), (16, 0), (4, 1), (8, 2), (16, 1), (4, 4), (8, 8), (16, 4)])
 def test_every_tile_configuration(pks, tmp_path, monkeypatch, ept, ept1):
     T = 150001
