@@ -265,7 +265,7 @@ def summarize_counters(base, wid):
     import sqlite3
 
     def short(n):
-        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "").replace("lg::", "")
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::", "").replace("lg::", "").replace("w16::", "")
         m = re.match(r"void (\w+<[^>]*>)", n)
         return m.group(1) if m else n
 
@@ -341,7 +341,7 @@ def summarize_trace(base, wid, op="filter_smooth"):
     cur = sqlite3.connect(os.path.join(base, db[0])).cursor()
     rows = []
     for n, calls, tot, avg in cur.execute("select name, total_calls, total_duration, average from top_kernels"):
-        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::lg::", "").replace("pks::", "")
+        n = n.replace("pks::(anonymous namespace)::", "").replace("pks::lg::", "").replace("pks::w16::", "").replace("pks::", "")
         m = re.match(r"void (\w+<[^>]*>)", n)
         n = m.group(1) if m else n
         if n.startswith("k_"):
