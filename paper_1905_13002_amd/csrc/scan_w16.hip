@@ -372,17 +372,48 @@ __device__ __forceinline__ void fcombine(FE& e, const f64x4& AjT, const f64x4& b
 // S = H Q H^T + R): M^-1 = I - K G with K = C_i G^T Sigma^-1 and the ny x ny
 // positive definite Sigma = S + G C_i G^T, so
 //   X1 = A_i - K (G A_i), x2 = v - K (G v), X3 = C_i - K (G C_i).
-template <int KY>
-__device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64x4& bj, const f64x4& etaj, double* st) {
+// Y = X G^T, v = X eta + c, G Y and G v.  PK (ny < 16): the last column of
+// G^T's tile is free, so eta rides there (and c in the same column of the
+// accumulator) -- X (G^T | eta) + (0 | c) is one product, G (Y | v) another --
+// and the column is then broadcast along the rows (DPP) and cleared.
+template <bool PK>
+__device__ __forceinline__ void yv(const f64x4& X, const FConst& f, const f64x4& eta, const f64x4& c, f64x4& Y,
+                                   f64x4& v, f64x4& GY, f64x4& Gv) {
+    if constexpr (PK) {
+        const bool last = lane_i() == 15;
+        f64x4 GTe, c15;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            GTe[q] = last ? eta[q] : f.GT[q];
+            c15[q] = last ? c[q] : 0.0;
+        }
+        const f64x4 Yx = mm(X, GTe, c15);
+        const f64x4 GYx = mm(f.GT, Yx);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = col_bcast(Yx[q], 15);
+            Y[q] = last ? 0.0 : Yx[q];
+            Gv[q] = col_bcast(GYx[q], 15);
+            GY[q] = last ? 0.0 : GYx[q];
+        }
+    } else {
+        Y = mm(X, f.GT);
+        v = mm(X, eta, c);
+        GY = mm(f.GT, Y);
+        Gv = mm(f.GT, v);
+    }
+}
 
-    const f64x4 Y = mm(e.C, f.GT);                   // C_i G^T
+template <int KY, bool PK>
+__device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64x4& bj, const f64x4& etaj, double* st) {
+    f64x4 Y, v, GY, Gv;
+    yv<PK>(e.C, f, etaj, e.b, Y, v, GY, Gv);          // C_i G^T, b_i + C_i eta_j, G C_i G^T, G v
     const f64x4 YT = tr(Y, st);                      // G C_i
     bool ok = true;
-    const f64x4 Z = inv_spd(symt(mm(f.GT, Y), f.S, st), f.ny, ok);
-    const f64x4 nKT = -mm<KY>(Z, YT);                    // tile of -K^T
-    const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
+    const f64x4 Z = inv_spd(symt(GY, f.S, st), f.ny, ok);
+    const f64x4 nKT = -mm<KY>(Z, YT);                // tile of -K^T
     const f64x4 X1 = mm<KY>(nKT, mm(f.GT, e.A), e.A);
-    const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
+    const f64x4 x2 = mm<KY>(nKT, Gv, v);
     const f64x4 X3 = mm<KY>(nKT, YT, e.C);
     fout(e, X1, x2, X3, f.AT, bj, f.C, etaj, f.J, st);
 }
@@ -390,17 +421,16 @@ __device__ __forceinline__ void fcombine_fresh(FE& e, const FConst& f, const f64
 // filtered moments (m, P) <- (m, P) (x) a_j for a single step j > 1 (the
 // prefix element has A = 0): with K = P G^T Sigma^-1, Sigma = S + G P G^T,
 //   m = A_j (v - K G v) + b_j (v = m + P eta_j), P = A_j (P - K G P) A_j^T + C_j
-template <int KY>
+template <int KY, bool PK>
 __device__ __forceinline__ void fcarry_fresh(f64x4& m, f64x4& P, const FConst& f, const f64x4& bj, const f64x4& etaj,
                                              double* st) {
-
-    const f64x4 Y = mm(P, f.GT);                     // P G^T
+    f64x4 Y, v, GY, Gv;
+    yv<PK>(P, f, etaj, m, Y, v, GY, Gv);              // P G^T, m + P eta_j, G P G^T, G v
     const f64x4 YT = tr(Y, st);                      // G P
     bool ok = true;
-    const f64x4 Z = inv_spd(symt(mm(f.GT, Y), f.S, st), f.ny, ok);
+    const f64x4 Z = inv_spd(symt(GY, f.S, st), f.ny, ok);
     const f64x4 nKT = -mm<KY>(Z, YT);
-    const f64x4 v = mm(P, etaj, m);
-    const f64x4 x2 = mm<KY>(nKT, mm(f.GT, v), v);
+    const f64x4 x2 = mm<KY>(nKT, Gv, v);
     const f64x4 X3 = mm<KY>(nKT, YT, P);
     m = mm(f.AT, x2, bj);
     const f64x4 U = mm(X3, f.AT);
@@ -496,7 +526,7 @@ __device__ __forceinline__ int64_t blk_end(const W16Args& w, int64_t k0) {
 // ---------------------------------------------------------------------------
 // filter kernels
 // ---------------------------------------------------------------------------
-template <typename R, int KY>
+template <typename R, int KY, bool PK>
 __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
     __shared__ double st[kStage];
     const ScanArgs& a = w.s;
@@ -527,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
     for (int64_t k = k0 + 1; k < k1; ++k) {
         yk = ynext;
         ynext = load_vec(y + (k + 1 < k1 ? k + 1 : k) * ny, ny);
-        fcombine_fresh<KY>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
+        fcombine_fresh<KY, PK>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
     }
     double* rec = w.agg[0] + (size_t)blockIdx.x * kFRec;
     put_tile(rec + kFA, e.A);
@@ -575,7 +605,7 @@ __device__ __forceinline__ f64x4 stored(const f64x4& x) {
     return t;
 }
 
-template <typename R, int KY>
+template <typename R, int KY, bool PK>
 __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     __shared__ double st[kStage];
     const ScanArgs& a = w.s;
@@ -604,7 +634,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
             m = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
             P = load_tile(cst + CL.C1, n, n, n);
         } else {
-            fcarry_fresh<KY>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
+            fcarry_fresh<KY, PK>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
         }
         store_vec(mo + k * n, m, n);
         store_tile(Po + k * n * n, P, n);
@@ -918,11 +948,12 @@ hipError_t run(W16Args w, bool smoother, hipStream_t s) {
     int cur = 0;
     if (!smoother) {
         prof_begin("k_w16_filter_reduce", s);
-        switch (slices(w.s.ny)) {
-            case 1: hipLaunchKernelGGL((k_w16_filter_reduce<R, 1>), grid, block, 0, s, w); break;
-            case 2: hipLaunchKernelGGL((k_w16_filter_reduce<R, 2>), grid, block, 0, s, w); break;
-            case 3: hipLaunchKernelGGL((k_w16_filter_reduce<R, 3>), grid, block, 0, s, w); break;
-            default: hipLaunchKernelGGL((k_w16_filter_reduce<R, 4>), grid, block, 0, s, w); break;
+        switch (w.s.ny < 16 ? slices(w.s.ny) : 5) {
+            case 1: hipLaunchKernelGGL((k_w16_filter_reduce<R, 1, true>), grid, block, 0, s, w); break;
+            case 2: hipLaunchKernelGGL((k_w16_filter_reduce<R, 2, true>), grid, block, 0, s, w); break;
+            case 3: hipLaunchKernelGGL((k_w16_filter_reduce<R, 3, true>), grid, block, 0, s, w); break;
+            case 4: hipLaunchKernelGGL((k_w16_filter_reduce<R, 4, true>), grid, block, 0, s, w); break;
+            default: hipLaunchKernelGGL((k_w16_filter_reduce<R, 4, false>), grid, block, 0, s, w); break;   // ny = 16
         }
         prof_end(s);
         for (int64_t d = 1; d < w.nblocks; d <<= 1) {
@@ -933,11 +964,12 @@ hipError_t run(W16Args w, bool smoother, hipStream_t s) {
         }
         w.final_buf = cur;
         prof_begin("k_w16_filter_down", s);
-        switch (slices(w.s.ny)) {
-            case 1: hipLaunchKernelGGL((k_w16_filter_down<R, 1>), grid, block, 0, s, w); break;
-            case 2: hipLaunchKernelGGL((k_w16_filter_down<R, 2>), grid, block, 0, s, w); break;
-            case 3: hipLaunchKernelGGL((k_w16_filter_down<R, 3>), grid, block, 0, s, w); break;
-            default: hipLaunchKernelGGL((k_w16_filter_down<R, 4>), grid, block, 0, s, w); break;
+        switch (w.s.ny < 16 ? slices(w.s.ny) : 5) {
+            case 1: hipLaunchKernelGGL((k_w16_filter_down<R, 1, true>), grid, block, 0, s, w); break;
+            case 2: hipLaunchKernelGGL((k_w16_filter_down<R, 2, true>), grid, block, 0, s, w); break;
+            case 3: hipLaunchKernelGGL((k_w16_filter_down<R, 3, true>), grid, block, 0, s, w); break;
+            case 4: hipLaunchKernelGGL((k_w16_filter_down<R, 4, true>), grid, block, 0, s, w); break;
+            default: hipLaunchKernelGGL((k_w16_filter_down<R, 4, false>), grid, block, 0, s, w); break;   // ny = 16
         }
         prof_end(s);
     } else {

@@ -489,7 +489,7 @@ def test_batched_B4096_full(pks, precision):
 # large state dimensions (workgroup per block element)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx,ny,T", [(5, 2, 777), (6, 6, 500), (8, 3, 1025), (8, 9, 300), (16, 8, 2000),
-                                     (12, 12, 257), (37, 33, 300), (40, 40, 150)])
+                                     (12, 12, 257), (10, 15, 400), (16, 16, 500), (37, 33, 300), (40, 40, 150)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_large_random_models(pks, nx, ny, T, precision):
     rng = np.random.default_rng(900 + 7 * nx + ny)
