@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "pks_internal.h"
 
@@ -60,6 +61,7 @@ struct W16Args {
     // down-sweep of a combined filter + smoother call and read by the
     // smoother kernels instead of rebuilding them (nullptr: rebuilt)
     double* elem;
+    int pivot_always;        // 1: the scan's combines skip the unpivoted attempt (PKS_PIVOTED_INVERSE=1)
 };
 
 __device__ __forceinline__ int lane_i() { return threadIdx.x & 15; }          // column
@@ -242,7 +244,8 @@ __device__ __forceinline__ f64x4 symt(const f64x4& x, const f64x4& add, double* 
 // Symmetric positive definite a: the pivots are the diagonal, in order, and
 // the inverse is formed in place.  `ok` is cleared by a pivot that is not
 // positive (the matrix is not positive definite) or not finite.
-__device__ __forceinline__ f64x4 inv_spd(f64x4 a, int n, bool& ok) {
+template <bool SPD = true>
+__device__ __forceinline__ f64x4 inv_diag(f64x4 a, int n, bool& ok) {
     const int li = lane_i(), lk = lane_k();
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -253,7 +256,7 @@ __device__ __forceinline__ f64x4 inv_spd(f64x4 a, int n, bool& ok) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) ck[v] = col_bcast(a[v], k);    // a(4 v + lk, k)
             const double rk = row_bcast(a[q], g);                      // a(k, li)
-            ok = ok && pv > 0.0 && isfinite(pv);
+            ok = ok && (SPD ? pv > 0.0 : pv != 0.0) && isfinite(pv);
             const double r = recip(pv);
             const double rr = rk * r;
 #pragma unroll
@@ -266,6 +269,8 @@ __device__ __forceinline__ f64x4 inv_spd(f64x4 a, int n, bool& ok) {
     }
     return a;
 }
+
+__device__ __forceinline__ f64x4 inv_spd(const f64x4& a, int n, bool& ok) { return inv_diag<true>(a, n, ok); }
 
 // General a: partial pivoting without row exchanges (the pivot of column k is
 // the entry of largest magnitude among the rows not used yet, lower rows
@@ -360,10 +365,25 @@ __device__ __forceinline__ void fout(FE& e, const f64x4& X1, const f64x4& x2, co
 // e <- e (x) (A_j, b_j, C_j, eta_j, J_j), Lemma 2, for two block elements: the
 // inverse of M^T = I + J_j C_i (its tile is M^-1 as a left factor) with
 // pivoting
+// The inverse is first formed without pivoting and kept when its residual
+// |M^T (M^T)^-1 - I| is below 1e-11 in every entry (the result is then as
+// accurate as a pivoted one); otherwise it is formed again with pivoting.
 __device__ __forceinline__ void fcombine(FE& e, const f64x4& AjT, const f64x4& bj, const f64x4& Cj, const f64x4& etaj,
-                                         const f64x4& Jj, const f64x4& I, double* st, int n) {
-    bool ok = true;
-    const f64x4 NT = inv_piv(mm(Jj, e.C, I), n, st, ok);
+                                         const f64x4& Jj, const f64x4& I, double* st, int n, bool pivot_always) {
+    bool ok = !pivot_always;
+    const f64x4 MT = mm(Jj, e.C, I);
+    f64x4 NT = I;
+    double dev = 1.0;
+    if (ok) {
+        NT = inv_diag<false>(MT, n, ok);
+        const f64x4 R = mm(mm(e.C, Jj, I), NT);          // M^T (M^T)^-1 (the tile of M as left operand)
+        dev = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dev = fmax(dev, fabs(R[v] - I[v]));
+#pragma unroll
+        for (int mk = 1; mk < 64; mk <<= 1) dev = fmax(dev, __shfl_xor(dev, mk, 64));
+    }
+    if (!(ok && dev <= 1e-11)) NT = inv_piv(MT, n, st, ok);
     const f64x4 v = mm(e.C, etaj, e.b);               // b_i + C_i eta_j
     fout(e, mm(NT, e.A), mm(NT, v), mm(NT, e.C), AjT, bj, Cj, etaj, Jj, st);
 }
@@ -587,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const dou
         e.b = load_vec(ri + kFb, 16);
         e.eta = load_vec(ri + kFeta, 16);
         const f64x4 I = eye();
-        fcombine(e, tr(Aj, st), bj, Cj, etaj, Jj, I, st, n);
+        fcombine(e, tr(Aj, st), bj, Cj, etaj, Jj, I, st, n, w.pivot_always != 0);
     }
     put_tile(ro + kFA, e.A);
     put_tile(ro + kFC, e.C);
@@ -1034,6 +1054,8 @@ hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool 
     w.final_buf = 0;
     // a combined filter + smoother call passes the smoothing elements from
     // the filter down-sweep to the smoother kernels
+    const char* pv = getenv("PKS_PIVOTED_INVERSE");
+    w.pivot_always = (pv && pv[0] == '1') ? 1 : 0;
     w.elem = (both && elem_bytes(a.total) > 0) ? reinterpret_cast<double*>(base + 2 * buffer_bytes(nb_max)) : nullptr;
     return mixed ? run<float>(w, smoother, s) : run<double>(w, smoother, s);
 }

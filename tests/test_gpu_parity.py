@@ -165,6 +165,24 @@ def test_separate_calls_match_fused(pks, prec):
             assert wl.max_rel_err(a[k], b[k], floor="rms") <= 1e-5, k
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_register_path_pivoted_inverse(pks, monkeypatch, precision):
+    """nx = 16: the block-element combines of the scan invert I + J C without
+    pivoting when the residual allows and with pivoting otherwise; with the
+    pivoted inverse forced (PKS_PIVOTED_INVERSE=1) the results agree with the
+    default ones and with the oracle."""
+    w = wl.workload(3, T=6000)
+    ref = oracle_run(w.model, ref_input(w.y, precision))
+    a = gpu_run(pks, w.model, w.y, precision)
+    monkeypatch.setenv("PKS_PIVOTED_INVERSE", "1")
+    b = gpu_run(pks, w.model, w.y, precision)
+    monkeypatch.delenv("PKS_PIVOTED_INVERSE")
+    assert_parity(a, ref, precision, "register path, default inverse")
+    assert_parity(b, ref, precision, "register path, pivoted inverse")
+    for k in ("m", "P", "ms", "Ps"):
+        assert wl.max_rel_err(a[k], b[k], "rms" if precision == "mixed" else "none") <= TOL[precision], k
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_separate_calls_match_fused_register_path(pks, prec):
     """nx = 16 (register-resident kernels): the combined call's filter
