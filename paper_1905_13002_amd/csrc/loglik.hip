@@ -688,7 +688,10 @@ bool launch_small_ll(const LLArgs& a, hipStream_t s) {
 template <typename R, bool SEG>
 void launch_steps(const LLArgs& a, hipStream_t s) {
     prof_begin("k_ll_steps", s);
-    if (a.nx >= 32 || a.ny >= 32) {
+    if (!SEG && a.sstride == 0 && w16_applies(a.nx, a.ny, true)) {
+        launch_ll_w16(a.nx, a.ny, a.total, a.m0, a.P0, a.consts64, a.cG, a.cS, a.ce, a.y, a.m, a.P, a.step, a.status,
+                      sizeof(R) == 4, s);
+    } else if (a.nx >= 32 || a.ny >= 32) {
         const size_t lds = sizeof(double) * (size_t)ll_large_words(a.nx, a.ny);
         const int threads = 256;
         const unsigned grid = (unsigned)std::min<int64_t>(a.total, 4096);

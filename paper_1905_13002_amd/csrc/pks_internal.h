@@ -218,6 +218,11 @@ bool w16_applies(int nx, int ny, bool single_invariant);
 int64_t w16_default_blocks(int64_t total);
 size_t w16_ws_bytes(int64_t total);
 hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s);
+// the marginal likelihood factors of one sequence with one time-invariant
+// model, 5 <= nx <= 16, ny <= 16 (register tiles); false: not applicable
+bool launch_ll_w16(int nx, int ny, int64_t total, const double* m0, const double* P0, const double* consts64, int cG,
+                   int cS, int ce, const void* y, const void* m, const void* P, double* step, int* status, bool mixed,
+                   hipStream_t s);
 // the model constants of one time-invariant model with 5 <= nx <= 16, ny <= 16
 // in one wavefront (what: 1, 2 or 3 as for launch_precompute); false: not
 // applicable, nothing launched

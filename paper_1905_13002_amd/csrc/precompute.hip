@@ -697,10 +697,11 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
     a.use_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
     const int threads = (a.use_lds && nx <= 16 && ny <= 16) ? 64 : kThreads;
     // one time-invariant model with 5 <= nx <= 16: the register-tile kernel
-    if (!tv && nmodels == 1 && a.what >= 1 && a.what <= 3 && w16_applies(nx, ny, true)) {
+    // (the likelihood's mode 4 takes the filter constants, which include G, S, e)
+    if (!tv && nmodels == 1 && a.what >= 1 && a.what <= 4 && w16_applies(nx, ny, true)) {
         prof_begin("k_w16_precompute", s);
         launch_w16_precompute(nx, ny, model, a.consts64, a.mixed ? a.consts32 : nullptr, a.status, a.model_fail,
-                              a.what, reset, s);
+                              a.what == 4 ? 1 : a.what, reset, s);
         prof_end(s);
         return hipGetLastError();
     }

@@ -244,8 +244,14 @@ __device__ __forceinline__ f64x4 symt(const f64x4& x, const f64x4& add, double* 
 // Symmetric positive definite a: the pivots are the diagonal, in order, and
 // the inverse is formed in place.  `ok` is cleared by a pivot that is not
 // positive (the matrix is not positive definite) or not finite.
+// det (optional): the product of the pivots as a mantissa product and an
+// exponent sum (the pivots are the diagonal of the LDL^T factorisation)
+struct Det {
+    double mant = 1.0;
+    int exp = 0;
+};
 template <bool SPD = true>
-__device__ __forceinline__ f64x4 inv_diag(f64x4 a, int n, bool& ok) {
+__device__ __forceinline__ f64x4 inv_diag(f64x4 a, int n, bool& ok, Det* det = nullptr) {
     const int li = lane_i(), lk = lane_k();
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -257,6 +263,11 @@ __device__ __forceinline__ f64x4 inv_diag(f64x4 a, int n, bool& ok) {
             for (int v = 0; v < 4; ++v) ck[v] = col_bcast(a[v], k);    // a(4 v + lk, k)
             const double rk = row_bcast(a[q], g);                      // a(k, li)
             ok = ok && (SPD ? pv > 0.0 : pv != 0.0) && isfinite(pv);
+            if (det) {
+                int ex;
+                det->mant *= frexp(pv, &ex);
+                det->exp += ex;
+            }
             const double r = recip(pv);
             const double rr = rk * r;
 #pragma unroll
@@ -945,6 +956,115 @@ __global__ __launch_bounds__(kThreads) void k_w16_precompute(PreArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Marginal likelihood factors (Section III-C) of one sequence with one model,
+// 5 <= nx <= 16, ny <= 16: log N(y_k; G m_{k-1} + e, G P_{k-1} G^T + S0) from
+// the filtered moments of the previous step (the prior at k = 0), one wave per
+// run of consecutive steps.  The residual is a compensated dot product (the
+// Dot2 scheme of Ogita, Rump and Oishi: every product's and every addition's
+// rounding error kept and added at the end), one row per lane; the covariance
+// is a register-tile product; its inverse and log-determinant come from the
+// unpivoted Gauss-Jordan elimination (the pivots of a positive definite
+// matrix are the diagonal of its LDL^T factorisation).
+// ---------------------------------------------------------------------------
+struct LLW {
+    int nx, ny;
+    int64_t total, per_wave;
+    const double *m0, *P0, *cst;
+    int cG, cS, ce;
+    const void *y, *m, *P;
+    double* step;
+    int* status;
+};
+
+struct Dot2 {
+    double s, c;
+};
+__device__ __forceinline__ void dot2_add(Dot2& a, double x) {
+#pragma clang fp contract(off)
+    const double t = a.s + x;
+    const double z = t - a.s;
+    a.c += (a.s - (t - z)) + (x - z);
+    a.s = t;
+}
+__device__ __forceinline__ void dot2_sub_prod(Dot2& a, double g, double x) {
+#pragma clang fp contract(off)
+    const double p = g * x;
+    const double e = fma(g, x, -p);       // g x = p + e exactly
+    dot2_add(a, -p);
+    a.c -= e;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_ll_w16(LLW a) {
+    __shared__ double st[kStage];
+    const int n = a.nx, m = a.ny, li = lane_i();
+    const f64x4 GT = load_tile_t(a.cst + a.cG, m, n, n);
+    const f64x4 S0 = pad_eye(load_tile(a.cst + a.cS, m, m, m), m);
+    double Grow[16];                          // row li of G (the residual's row of this lane)
+#pragma unroll
+    for (int l = 0; l < 16; ++l) Grow[l] = (li < m && l < n) ? a.cst[a.cG + li * n + l] : 0.0;
+    const double e_i = li < m ? a.cst[a.ce + li] : 0.0;
+    const R* gy = static_cast<const R*>(a.y);
+    const R* gm = static_cast<const R*>(a.m);
+    const R* gP = static_cast<const R*>(a.P);
+    const int64_t k0 = (int64_t)blockIdx.x * a.per_wave;
+    const int64_t k1 = k0 + a.per_wave < a.total ? k0 + a.per_wave : a.total;
+    // the previous step's moments (the prior at k = 0) and y_k; the next
+    // step's are loaded while the current one is evaluated
+    auto fetch = [&](int64_t k, f64x4& P, double (&mv)[16], double& yk) {
+        if (k == 0) {
+            P = load_tile(a.P0, n, n, n);
+#pragma unroll
+            for (int l = 0; l < 16; ++l) mv[l] = l < n ? a.m0[l] : 0.0;
+        } else {
+            P = load_tile(gP + (k - 1) * n * n, n, n, n);
+#pragma unroll
+            for (int l = 0; l < 16; ++l) mv[l] = l < n ? double(gm[(k - 1) * n + l]) : 0.0;
+        }
+        yk = li < m ? double(gy[k * m + li]) : 0.0;
+    };
+    f64x4 Pn;
+    double mn[16], yn;
+    fetch(k0, Pn, mn, yn);
+    for (int64_t k = k0; k < k1; ++k) {
+        const f64x4 P = Pn;
+        double mv[16];
+#pragma unroll
+        for (int l = 0; l < 16; ++l) mv[l] = mn[l];
+        const double yk = yn;
+        fetch(k + 1 < k1 ? k + 1 : k, Pn, mn, yn);
+        // r_i = y_i - e_i - (G m)_i for i = li
+        Dot2 acc{yk, 0.0};
+        dot2_add(acc, -e_i);
+#pragma unroll
+        for (int l = 0; l < 16; ++l) dot2_sub_prod(acc, Grow[l], mv[l]);
+        const double ri = acc.s + acc.c;
+        f64x4 r;                              // replicated: r(4 v + lk)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r[v] = __shfl(ri, (threadIdx.x & 48) | (4 * v + lane_k()), 64);
+        // S = G P G^T + S0, its inverse and log-determinant, r^T S^-1 r
+        bool ok = true;
+        Det det;
+        const f64x4 Z = inv_diag<true>(symt(mm(GT, mm(P, GT)), S0, st), m, ok, &det);
+        const double logdet = log(det.mant) + det.exp * 0.69314718055994530942;   // log 2
+        const f64x4 Zr = mm(Z, r);
+        double q = 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q += r[v] * Zr[v];
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        if ((threadIdx.x & 63) == 0) {
+            double ll = -0.5 * (m * 1.8378770664093454836 + q + logdet);   // log(2 pi) = 1.83787...
+            if (!ok) {
+                ll = __builtin_nan("");
+                atomicMin(a.status, 0);
+            }
+            a.step[k] = ll;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 int64_t blocks_for(int64_t total) {
@@ -1036,6 +1156,33 @@ bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* const
     p.what = what;
     p.reset = reset ? 1 : 0;
     hipLaunchKernelGGL(w16::k_w16_precompute, dim3(1), dim3(w16::kThreads), 0, s, p);
+    return true;
+}
+
+bool launch_ll_w16(int nx, int ny, int64_t total, const double* m0, const double* P0, const double* consts64, int cG,
+                   int cS, int ce, const void* y, const void* m, const void* P, double* step, int* status, bool mixed,
+                   hipStream_t s) {
+    if (!w16_applies(nx, ny, true) || total < 1) return false;
+    w16::LLW a;
+    a.nx = nx;
+    a.ny = ny;
+    a.total = total;
+    const int64_t waves = total < 2048 ? total : 2048;
+    a.per_wave = (total + waves - 1) / waves;
+    a.m0 = m0;
+    a.P0 = P0;
+    a.cst = consts64;
+    a.cG = cG;
+    a.cS = cS;
+    a.ce = ce;
+    a.y = y;
+    a.m = m;
+    a.P = P;
+    a.step = step;
+    a.status = status;
+    const dim3 grid((unsigned)((total + a.per_wave - 1) / a.per_wave)), block(w16::kThreads);
+    if (mixed) hipLaunchKernelGGL(w16::k_ll_w16<float>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(w16::k_ll_w16<double>, grid, block, 0, s, a);
     return true;
 }
 

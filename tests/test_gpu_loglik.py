@@ -198,11 +198,13 @@ def test_loglik_random_small_models(pks, nx, ny, precision):
 
 
 @pytest.mark.parametrize("nx,ny,T", [(4, 6, 700), (1, 9, 300), (5, 2, 777), (8, 3, 1100), (16, 8, 2000),
-                                     (33, 17, 150), (64, 32, 120), (64, 64, 40)])
+                                     (12, 15, 500), (16, 16, 300), (33, 17, 150), (64, 32, 120), (64, 64, 40)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_loglik_one_wave_per_step(pks, nx, ny, T, precision):
-    """Sizes outside nx, ny <= 4: the one-wavefront-per-step kernel, and from
-    nx or ny = 32 on the one-workgroup-per-step kernel with matrix-core products."""
+    """Sizes outside nx, ny <= 4: the one-wavefront-per-step kernel (packed
+    sequences, and nx < 5 or nx > 16), the register-tile kernel (one sequence,
+    5 <= nx <= 16, ny <= 16), and from nx or ny = 32 on the
+    one-workgroup-per-step kernel with matrix-core products."""
     rng = np.random.default_rng(400 + nx + 3 * ny)
     model = wl.random_stable_model(nx, ny, rng, radius=0.95)
     y, _ = wl.simulate(model, T, rng)
