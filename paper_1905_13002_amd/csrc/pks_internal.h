@@ -212,9 +212,10 @@ int64_t large_default_blocks(int nx, int ny, int64_t total, bool mixed);
 // filter on the same stream and workspace)
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s);
 
-// register-resident large-state path (scan_w16.hip): one sequence, one
-// time-invariant model, 5 <= nx <= 16, ny <= 16
-bool w16_applies(int nx, int ny, bool single_invariant);
+// register-resident large-state path (scan_w16.hip): time-invariant models
+// (one sequence or packed sequences, shared or per-sequence models),
+// 5 <= nx <= 16, ny <= 16
+bool w16_applies(int nx, int ny, bool time_invariant);
 int64_t w16_default_blocks(int64_t total);
 size_t w16_ws_bytes(int64_t total);
 hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s);
@@ -223,10 +224,10 @@ hipError_t launch_w16(ScanArgs a, void* region, bool mixed, bool smoother, bool 
 bool launch_ll_w16(int nx, int ny, int64_t total, const double* m0, const double* P0, const double* consts64, int cG,
                    int cS, int ce, const void* y, const void* m, const void* P, double* step, int* status, bool mixed,
                    hipStream_t s);
-// the model constants of one time-invariant model with 5 <= nx <= 16, ny <= 16
-// in one wavefront (what: 1, 2 or 3 as for launch_precompute); false: not
-// applicable, nothing launched
-bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* consts64, float* consts32, int* status,
-                           int* model_fail, int what, bool reset, hipStream_t s);
+// the model constants of time-invariant models with 5 <= nx <= 16, ny <= 16,
+// one wavefront per model (what: 1, 2 or 3 as for launch_precompute); false:
+// not applicable, nothing launched
+bool launch_w16_precompute(int nx, int ny, int32_t nmodels, const pks_model& model, double* consts64, float* consts32,
+                           int* status, int* model_fail, int what, bool reset, hipStream_t s);
 
 }  // namespace pks

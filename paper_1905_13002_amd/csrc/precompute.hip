@@ -696,12 +696,12 @@ hipError_t launch_precompute(int nx, int ny, int32_t nmodels, const pks_model& m
     const size_t lds_bytes = sizeof(double) * (size_t)(a.cw + a.sw);
     a.use_lds = lds_bytes <= 48 * 1024 ? 1 : 0;
     const int threads = (a.use_lds && nx <= 16 && ny <= 16) ? 64 : kThreads;
-    // one time-invariant model with 5 <= nx <= 16: the register-tile kernel
+    // time-invariant models with 5 <= nx <= 16: the register-tile kernel (one wave per model)
     // (the likelihood's mode 4 takes the filter constants, which include G, S, e)
-    if (!tv && nmodels == 1 && a.what >= 1 && a.what <= 4 && w16_applies(nx, ny, true)) {
+    if (!tv && a.what >= 1 && a.what <= 4 && w16_applies(nx, ny, true)) {
         prof_begin("k_w16_precompute", s);
-        launch_w16_precompute(nx, ny, model, a.consts64, a.mixed ? a.consts32 : nullptr, a.status, a.model_fail,
-                              a.what == 4 ? 1 : a.what, reset, s);
+        launch_w16_precompute(nx, ny, nmodels, model, a.consts64, a.mixed ? a.consts32 : nullptr, a.status,
+                              a.model_fail, a.what == 4 ? 1 : a.what, reset, s);
         prof_end(s);
         return hipGetLastError();
     }

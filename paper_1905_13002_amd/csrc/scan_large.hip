@@ -61,15 +61,15 @@ size_t large_ws_bytes(int nx, int ny, int64_t total, pks_precision prec) {
     size_t slot = 0;
     slot_mask_of(nx, ny, mixed, &slot);
     const size_t lds_path = 2 * ((rs * fw * nb + 255) & ~size_t(255)) + slot * nb;
-    // a single sequence of a time-invariant model with nx <= 16 takes the
-    // register-resident path (packed sequences keep the path above)
+    // time-invariant models with nx <= 16 (one sequence or packed sequences)
+    // take the register-resident path
     const size_t reg_path = w16_applies(nx, ny, true) ? w16_ws_bytes(total) : 0;
     return lds_path > reg_path ? lds_path : reg_path;
 }
 
 hipError_t launch_large(ScanArgs a, void* region, bool mixed, bool smoother, bool both, hipStream_t s) {
     using namespace lg;
-    if (w16_applies(a.nx, a.ny, a.offsets == nullptr && a.step_stride == 0))
+    if (w16_applies(a.nx, a.ny, a.step_stride == 0))
         return launch_w16(a, region, mixed, smoother, both, s);
     LargeArgs la;
     la.s = a;

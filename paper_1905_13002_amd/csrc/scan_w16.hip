@@ -1,6 +1,7 @@
-// scan_w16.hip -- the filtering and smoothing scans of one sequence with one
-// time-invariant model for 5 <= nx <= 16 and ny <= 16, every element held in
-// the registers of one wavefront.
+// scan_w16.hip -- the filtering and smoothing scans of time-invariant models
+// (one sequence or packed sequences) for 5 <= nx <= 16 and ny <= 16, every
+// element held in the registers of one wavefront; also the model constants
+// and the likelihood factors of one sequence at these sizes.
 //
 // Register layout of a 16 x 16 matrix X (smaller dimensions padded with
 // zeros): lane l = 16 lk + li holds X(4 v + lk, li) in component v of an
@@ -519,8 +520,13 @@ __device__ __forceinline__ f64x4 pad_eye(f64x4 t, int n) {
     return t;
 }
 
-__device__ __forceinline__ FConst load_fconst(const ScanArgs& a, const ConstLayout& CL) {
-    const double* cst = a.consts64;
+// constants of model b (one block per model; a shared model has stride 0)
+__device__ __forceinline__ const double* cst_of(const ScanArgs& a, int b) {
+    return a.consts64 + (int64_t)b * a.model_stride;
+}
+
+__device__ __forceinline__ FConst load_fconst(const ScanArgs& a, const ConstLayout& CL, int b) {
+    const double* cst = cst_of(a, b);
     const int n = a.nx, m = a.ny;
     FConst f;
     f.AT = load_tile_t(cst + CL.A, n, n, n);
@@ -534,24 +540,74 @@ __device__ __forceinline__ FConst load_fconst(const ScanArgs& a, const ConstLayo
     f.w = load_vec(cst + CL.w, n);
     f.n = n;
     f.ny = m;
-
     return f;
 }
 
-__device__ __forceinline__ SConst load_sconst(const ScanArgs& a, const ConstLayout& CL) {
-    const double* cst = a.consts64;
+__device__ __forceinline__ SConst load_sconst(const ScanArgs& a, const ConstLayout& CL, int b) {
+    const double* cst = cst_of(a, b);
     const int n = a.nx;
     SConst c;
     c.FT = load_tile_t(cst + CL.F, n, n, n);
     c.Q = pad_eye(load_tile(cst + CL.Q, n, n, n), n);
     c.u = load_vec(cst + CL.u, n);
     c.n = n;
-
     return c;
+}
+
+// the first-step element of sequence b's model: b_1 = c1 + K1 y_1, C_1 = C1
+template <int KY>
+__device__ __forceinline__ void first_step(const ScanArgs& a, const ConstLayout& CL, int b, const f64x4& yk, f64x4& b1,
+                                           f64x4& C1) {
+    const double* cst = cst_of(a, b);
+    b1 = mm<KY>(load_tile_t(cst + CL.K1, a.nx, a.ny, a.ny), yk, load_vec(cst + CL.c1, a.nx));
+    C1 = load_tile(cst + CL.C1, a.nx, a.nx, a.nx);
 }
 
 __device__ __forceinline__ int64_t blk_end(const W16Args& w, int64_t k0) {
     return k0 + w.blen < w.s.total ? k0 + w.blen : w.s.total;
+}
+
+// The sequence holding step k: [start, end) and its index b (wave-uniform).
+// One sequence (offsets == nullptr): [0, total).  Packed sequences are
+// separated by the exact zeros of a first step (A = 0) and of a last step
+// (E = 0): at a sequence's first step the filtering accumulator's A, b, C are
+// replaced by the first-step element, at its last step the smoothing
+// accumulator by (0, m, P); the scans over block elements pass a right
+// (filter) or left (smoother) operand with A = 0 (E = 0) through, so a failed
+// sequence cannot reach the next one.
+struct SeqT {
+    int b;
+    int64_t start, end;
+};
+__device__ __forceinline__ SeqT seq_find(const ScanArgs& a, int64_t k) {
+    SeqT q;
+    if (!a.offsets) {
+        q.b = 0;
+        q.start = 0;
+        q.end = a.total;
+        return q;
+    }
+    int lo = 0, hi = a.B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.offsets[mid] <= k) lo = mid; else hi = mid;
+    }
+    q.b = lo;
+    q.start = a.offsets[lo];
+    q.end = a.offsets[lo + 1];
+    return q;
+}
+__device__ __forceinline__ void seq_next(const ScanArgs& a, SeqT& q, int64_t k) {
+    if (a.offsets)
+        while (k >= q.end && q.b < a.B - 1) { ++q.b; q.start = q.end; q.end = a.offsets[q.b + 1]; }
+}
+__device__ __forceinline__ void seq_prev(const ScanArgs& a, SeqT& q, int64_t k) {
+    if (a.offsets)
+        while (k < q.start && q.b > 0) { --q.b; q.end = q.start; q.start = a.offsets[q.b]; }
+}
+// every entry of the tile exactly zero (wave-uniform)
+__device__ __forceinline__ bool all_zero(const f64x4& t) {
+    return __all(t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0 && t[3] == 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -562,18 +618,20 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
     __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
-    const int n = a.nx, ny = a.ny;
+    const int ny = a.ny;
     const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.model_fail[0]) atomicMin(a.status, 0);
-    const FConst f = load_fconst(a, CL);
+    if (blockIdx.x == 0)     // models whose precompute failed
+        for (int b = threadIdx.x; b < a.nmodels; b += kThreads)
+            if (a.model_fail[b]) atomicMin(a.status, b);
+    SeqT q = seq_find(a, k0);
+    int mb = a.model_stride ? q.b : 0;        // the model whose constants are loaded
+    FConst f = load_fconst(a, CL, mb);
     const R* y = static_cast<const R*>(a.y);
     FE e;
     f64x4 yk = load_vec(y + k0 * ny, ny);
-    if (k0 == 0) {          // the first step: A = 0, eta = 0, J = 0
-        const double* cst = a.consts64;
+    if (k0 == q.start) {     // a first step: A = 0, eta = 0, J = 0
+        first_step<KY>(a, CL, q.b, yk, e.b, e.C);
         e.A = zero4();
-        e.b = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
-        e.C = load_tile(cst + CL.C1, n, n, n);
         e.eta = zero4();
         e.J = zero4();
     } else {
@@ -588,6 +646,16 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_reduce(W16Args w) {
     for (int64_t k = k0 + 1; k < k1; ++k) {
         yk = ynext;
         ynext = load_vec(y + (k + 1 < k1 ? k + 1 : k) * ny, ny);
+        seq_next(a, q, k);
+        if (k == q.start) {  // a sequence starts: its first-step element replaces A, b, C
+            first_step<KY>(a, CL, q.b, yk, e.b, e.C);
+            e.A = zero4();
+            if (a.model_stride && q.b != mb) {
+                mb = q.b;
+                f = load_fconst(a, CL, mb);
+            }
+            continue;
+        }
         fcombine_fresh<KY, PK>(e, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
     }
     double* rec = w.agg[0] + (size_t)blockIdx.x * kFRec;
@@ -619,6 +687,13 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_ks(W16Args w, const dou
         e.eta = load_vec(ri + kFeta, 16);
         const f64x4 I = eye();
         fcombine(e, tr(Aj, st), bj, Cj, etaj, Jj, I, st, n, w.pivot_always != 0);
+        if (w.s.offsets && all_zero(Aj)) {
+            // the right operand starts a sequence: its A, b, C pass through
+            // (exactly what A_j = 0 gives, without 0 * NaN from the left)
+            e.A = Aj;
+            e.b = bj;
+            e.C = Cj;
+        }
     }
     put_tile(ro + kFA, e.A);
     put_tile(ro + kFC, e.C);
@@ -643,9 +718,11 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = a.nx, ny = a.ny;
     const int64_t blk = blockIdx.x, k0 = blk * w.blen, k1 = blk_end(w, k0);
-    const FConst f = load_fconst(a, CL);
+    SeqT q = seq_find(a, k0);
+    int mb = a.model_stride ? q.b : 0;
+    FConst f = load_fconst(a, CL, mb);
     SConst sc = {};
-    if (w.elem) sc = load_sconst(a, CL);
+    if (w.elem) sc = load_sconst(a, CL, mb);
     bool ok = true;
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
@@ -660,27 +737,31 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     for (int64_t k = k0; k < k1; ++k) {
         const f64x4 yk = ynext;
         ynext = load_vec(y + (k + 1 < k1 ? k + 1 : k) * ny, ny);
-        if (k == 0) {
-            const double* cst = a.consts64;
-            m = mm<KY>(load_tile_t(cst + CL.K1, n, ny, ny), yk, load_vec(cst + CL.c1, n));
-            P = load_tile(cst + CL.C1, n, n, n);
-        } else {
-            fcarry_fresh<KY, PK>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
+        seq_next(a, q, k);
+        if (a.model_stride && q.b != mb) {
+            mb = q.b;
+            f = load_fconst(a, CL, mb);
+            if (w.elem) sc = load_sconst(a, CL, mb);
         }
+        if (k == q.start) first_step<KY>(a, CL, q.b, yk, m, P);
+        else fcarry_fresh<KY, PK>(m, P, f, mm<KY>(f.KT, yk, f.c), mm<KY>(f.WT, yk, f.w), st);
         store_vec(mo + k * n, m, n);
         store_tile(Po + k * n * n, P, n);
-        if (w.elem && k + 1 < a.total) {
+        if (w.elem && k + 1 < q.end) {
             // the smoothing element of step k (Lemma 3), from the moments as
             // stored (the same inputs the smoother kernels would read back)
+            bool okk = true;
             f64x4 ET, g, L;
-            selem(stored<R>(m), stored<R>(P), sc, st, ok, ET, g, L);
+            selem(stored<R>(m), stored<R>(P), sc, st, okk, ET, g, L);
             double* e = w.elem + (size_t)k * kSRec;
             put_tile(e + kSE, ET);
             put_tile(e + kSL, L);
             store_vec(e + kSg, g, 16);
+            if (!okk && threadIdx.x == 0) atomicMin(a.status, q.b);
+            ok = ok && okk;
         }
     }
-    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
+    (void)ok;
 }
 
 // ---------------------------------------------------------------------------
@@ -693,66 +774,78 @@ __device__ __forceinline__ void load_moments(const ScanArgs& a, int64_t k, f64x4
     P = load_tile(static_cast<const R*>(a.P) + k * n * n, n, n, n);
 }
 
+// the smoothing element of step k (not the last of its sequence): stored by
+// the filter down-sweep, or built from the filtered moments
+template <typename R>
+__device__ __forceinline__ void elem_at(const W16Args& w, int64_t k, const SConst& c, double* st, int b, f64x4& ET,
+                                        f64x4& g, f64x4& L) {
+    if (w.elem) {
+        const double* e = w.elem + (size_t)k * kSRec;
+        ET = get_tile(e + kSE);
+        g = load_vec(e + kSg, 16);
+        L = get_tile(e + kSL);
+    } else {
+        f64x4 m, P;
+        load_moments<R>(w.s, k, m, P);
+        bool ok = true;
+        selem(m, P, c, st, ok, ET, g, L);
+        if (!ok && threadIdx.x == 0) atomicMin(w.s.status, b);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_w16_smoother_reduce(W16Args w) {
     __shared__ double st[kStage];
     const ScanArgs& a = w.s;
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int64_t k0 = blockIdx.x * w.blen, k1 = blk_end(w, k0);
-    bool ok = true;
-    f64x4 m, P, E, g, L;
-    if (w.elem) {           // the elements the filter down-sweep stored
-        if (k1 == a.total) {
-            load_moments<R>(a, k1 - 1, m, P);
-            E = zero4();
-            g = m;
-            L = P;
-        } else {
-            const double* e = w.elem + (size_t)(k1 - 1) * kSRec;
-            E = tr(get_tile(e + kSE), st);
-            L = get_tile(e + kSL);
-            g = load_vec(e + kSg, 16);
-        }
-        // the next element down is loaded while the current one is folded
+    SeqT q = seq_find(a, k1 - 1);
+    int mb = a.model_stride ? q.b : 0;
+    SConst c = {};
+    if (!w.elem) c = load_sconst(a, CL, mb);
+    f64x4 E, g, L;
+    if (k1 == q.end) {      // the last step of a sequence: E = 0, g = m, L = P
+        load_moments<R>(a, k1 - 1, g, L);
+        E = zero4();
+    } else {
+        f64x4 ET;
+        elem_at<R>(w, k1 - 1, c, st, q.b, ET, g, L);
+        E = tr(ET, st);
+    }
+    if (w.elem) {           // stored elements: the next one down is loaded while the current one is folded
         const double* e = w.elem + (size_t)(k1 - 2 >= k0 ? k1 - 2 : k0) * kSRec;
         f64x4 ETn = get_tile(e + kSE), gn = load_vec(e + kSg, 16), Ln = get_tile(e + kSL);
         for (int64_t k = k1 - 2; k >= k0; --k) {
+            seq_prev(a, q, k);
             const f64x4 ETk = ETn, gk = gn, Lk = Ln;
             e = w.elem + (size_t)(k - 1 >= k0 ? k - 1 : k0) * kSRec;
             ETn = get_tile(e + kSE);
             gn = load_vec(e + kSg, 16);
             Ln = get_tile(e + kSL);
+            if (k == q.end - 1) {   // a sequence ends here (its slot holds no element): restart
+                load_moments<R>(a, k, g, L);
+                E = zero4();
+            } else {
+                sfold(E, g, L, ETk, gk, Lk, st);
+            }
+        }
+    } else {
+        for (int64_t k = k1 - 2; k >= k0; --k) {
+            seq_prev(a, q, k);
+            if (k == q.end - 1) {   // a sequence ends here: the accumulator restarts
+                load_moments<R>(a, k, g, L);
+                E = zero4();
+                continue;
+            }
+            if (a.model_stride && q.b != mb) {
+                mb = q.b;
+                c = load_sconst(a, CL, mb);
+            }
+            f64x4 ETk, gk, Lk;
+            elem_at<R>(w, k, c, st, q.b, ETk, gk, Lk);
             sfold(E, g, L, ETk, gk, Lk, st);
         }
-        double* rec = w.agg[0] + (size_t)blockIdx.x * kSRec;
-        put_tile(rec + kSE, E);
-        put_tile(rec + kSL, L);
-        store_vec(rec + kSg, g, 16);
-        return;
     }
-    const SConst c = load_sconst(a, CL);
-    load_moments<R>(a, k1 - 1, m, P);
-    if (k1 == a.total) {    // the last step: E = 0, g = m, L = P
-        E = zero4();
-        g = m;
-        L = P;
-    } else {
-        f64x4 ET;
-        selem(m, P, c, st, ok, ET, g, L);
-        E = tr(ET, st);
-    }
-    // the moments of the next step down are loaded while the current one is folded
-    f64x4 mn, Pn;
-    load_moments<R>(a, k1 - 2 >= k0 ? k1 - 2 : k0, mn, Pn);
-    for (int64_t k = k1 - 2; k >= k0; --k) {
-        m = mn;
-        P = Pn;
-        load_moments<R>(a, k - 1 >= k0 ? k - 1 : k0, mn, Pn);
-        f64x4 ET, gk, Lk;
-        selem(m, P, c, st, ok, ET, gk, Lk);
-        sfold(E, g, L, ET, gk, Lk, st);
-    }
-    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
     double* rec = w.agg[0] + (size_t)blockIdx.x * kSRec;
     put_tile(rec + kSE, E);
     put_tile(rec + kSL, L);
@@ -767,10 +860,10 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_ks(W16Args w, const d
     double* ro = out + (size_t)i * kSRec;
     const f64x4 Ei = get_tile(ri + kSE), Li = get_tile(ri + kSL), gi = load_vec(ri + kSg, 16);
     f64x4 E, g, L;
-    if (i + d >= w.nblocks) {
+    // the left operand ending a sequence (E = 0) passes through
+    if (i + d >= w.nblocks || (w.s.offsets && all_zero(Ei))) {
         E = Ei; g = gi; L = Li;
     } else {
-
         const double* rj = in + (size_t)(i + d) * kSRec;
         E = get_tile(rj + kSE);
         L = get_tile(rj + kSL);
@@ -789,8 +882,10 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
     const ConstLayout CL = const_layout(a.nx, a.ny);
     const int n = a.nx;
     const int64_t blk = blockIdx.x, k0 = blk * w.blen, k1 = blk_end(w, k0);
-    const SConst c = load_sconst(a, CL);
-    bool ok = true;
+    SeqT q = seq_find(a, k1 - 1);
+    int mb = a.model_stride ? q.b : 0;
+    SConst c = {};
+    if (!w.elem) c = load_sconst(a, CL, mb);
     R* mso = static_cast<R*>(a.ms);
     R* Pso = static_cast<R*>(a.Ps);
     f64x4 ms = zero4(), Ps = zero4();
@@ -799,43 +894,39 @@ __global__ __launch_bounds__(kThreads) void k_w16_smoother_down(W16Args w) {
         ms = load_vec(rec + kSg, 16);
         Ps = get_tile(rec + kSL);
     }
-    if (w.elem) {           // the elements the filter down-sweep stored
-        // the element of step k - 1 is loaded while step k is folded (the last
-        // step of the sequence has none: its slot is never read)
-        const int64_t kl = a.total - 1;
-        auto slot = [&](int64_t k) { return w.elem + (size_t)(k < kl ? k : (kl > 0 ? kl - 1 : 0)) * kSRec; };
-        const double* e = slot(k1 - 1);
+    if (w.elem) {            // stored elements; step k - 1's is loaded while step k is folded
+        const double* e = w.elem + (size_t)(k1 - 1) * kSRec;
         f64x4 ETn = get_tile(e + kSE), gn = load_vec(e + kSg, 16), Ln = get_tile(e + kSL);
         for (int64_t k = k1 - 1; k >= k0; --k) {
+            seq_prev(a, q, k);
             const f64x4 ETk = ETn, gk = gn, Lk = Ln;
-            e = slot(k - 1 >= k0 ? k - 1 : k0);
+            e = w.elem + (size_t)(k - 1 >= k0 ? k - 1 : k0) * kSRec;
             ETn = get_tile(e + kSE);
             gn = load_vec(e + kSg, 16);
             Ln = get_tile(e + kSL);
-            if (k == kl) load_moments<R>(a, k, ms, Ps);
+            if (k == q.end - 1) load_moments<R>(a, k, ms, Ps);   // (its slot holds no element)
             else scarry(ms, Ps, ETk, gk, Lk, st);
             store_vec(mso + k * n, ms, n);
             store_tile(Pso + k * n * n, Ps, n);
         }
         return;
     }
-    f64x4 mn, Pn;
-    load_moments<R>(a, k1 - 1, mn, Pn);
     for (int64_t k = k1 - 1; k >= k0; --k) {
-        const f64x4 m = mn, P = Pn;
-        load_moments<R>(a, k - 1 >= k0 ? k - 1 : k0, mn, Pn);
-        if (k == a.total - 1) {
-            ms = m;
-            Ps = P;
+        seq_prev(a, q, k);
+        if (k == q.end - 1) {
+            load_moments<R>(a, k, ms, Ps);
         } else {
-            f64x4 ET, gk, Lk;
-            selem(m, P, c, st, ok, ET, gk, Lk);
-            scarry(ms, Ps, ET, gk, Lk, st);
+            if (a.model_stride && q.b != mb) {
+                mb = q.b;
+                c = load_sconst(a, CL, mb);
+            }
+            f64x4 ETk, gk, Lk;
+            elem_at<R>(w, k, c, st, q.b, ETk, gk, Lk);
+            scarry(ms, Ps, ETk, gk, Lk, st);
         }
         store_vec(mso + k * n, ms, n);
         store_tile(Pso + k * n * n, Ps, n);
     }
-    if (!ok && threadIdx.x == 0) atomicMin(a.status, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -854,6 +945,7 @@ struct PreArgs {
     int* model_fail;
     int what;            // 1: filter constants, 2: smoother constants, 3: both
     int reset;
+    int per_sequence;    // model arrays hold one model per workgroup (else one shared)
 };
 
 template <typename T>
@@ -896,12 +988,27 @@ __device__ __forceinline__ void put_fields(T* o, const ConstLayout& CL, int n, i
 
 __global__ __launch_bounds__(kThreads) void k_w16_precompute(PreArgs a) {
     __shared__ double st[kStage];
-    if (threadIdx.x == 0 && (a.reset || a.status[1] != kStatusMagic)) {
+    const int mdl = blockIdx.x;          // the model of this workgroup
+    if (mdl == 0 && threadIdx.x == 0 && (a.reset || a.status[1] != kStatusMagic)) {
         a.status[0] = kStatusOk;
         a.status[1] = kStatusMagic;
     }
     const int n = a.nx, m = a.ny;
     const ConstLayout CL = const_layout(n, m);
+    if (a.per_sequence) {                // this model's rows of the model arrays
+        const int64_t b = mdl;
+        a.F += b * n * n;
+        a.Q += b * n * n;
+        a.H += b * m * n;
+        a.R += b * m * m;
+        a.m0 += b * n;
+        a.P0 += b * n * n;
+        if (a.u) a.u += b * n;
+        if (a.d) a.d += b * m;
+    }
+    a.consts64 += (int64_t)mdl * CL.words;
+    if (a.consts32) a.consts32 += (int64_t)mdl * CL.words;
+    a.model_fail += mdl;
     const f64x4 F = load_tile(a.F, n, n, n), FT = load_tile_t(a.F, n, n, n);
     const f64x4 Q = load_tile(a.Q, n, n, n);
     const f64x4 u = a.u ? load_vec(a.u, n) : zero4();
@@ -1132,17 +1239,17 @@ hipError_t run(W16Args w, bool smoother, hipStream_t s) {
 
 }  // namespace w16
 
-bool w16_applies(int nx, int ny, bool single_invariant) {
-    return single_invariant && nx >= 5 && nx <= 16 && ny >= 1 && ny <= 16;
+bool w16_applies(int nx, int ny, bool time_invariant) {
+    return time_invariant && nx >= 5 && nx <= 16 && ny >= 1 && ny <= 16;
 }
 
 int64_t w16_default_blocks(int64_t total) { return w16::blocks_for(total); }
 
 size_t w16_ws_bytes(int64_t total) { return 2 * w16::buffer_bytes(w16::blocks_for(total)) + w16::elem_bytes(total); }
 
-bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* consts64, float* consts32, int* status,
-                           int* model_fail, int what, bool reset, hipStream_t s) {
-    if (!w16_applies(nx, ny, true) || what < 1 || what > 3) return false;
+bool launch_w16_precompute(int nx, int ny, int32_t nmodels, const pks_model& model, double* consts64, float* consts32,
+                           int* status, int* model_fail, int what, bool reset, hipStream_t s) {
+    if (!w16_applies(nx, ny, true) || what < 1 || what > 3 || nmodels < 1) return false;
     w16::PreArgs p;
     p.nx = nx;
     p.ny = ny;
@@ -1155,7 +1262,8 @@ bool launch_w16_precompute(int nx, int ny, const pks_model& model, double* const
     p.model_fail = model_fail;
     p.what = what;
     p.reset = reset ? 1 : 0;
-    hipLaunchKernelGGL(w16::k_w16_precompute, dim3(1), dim3(w16::kThreads), 0, s, p);
+    p.per_sequence = model.per_sequence ? 1 : 0;
+    hipLaunchKernelGGL(w16::k_w16_precompute, dim3((unsigned)nmodels), dim3(w16::kThreads), 0, s, p);
     return true;
 }
 

@@ -546,6 +546,43 @@ def test_large_batched_per_sequence(pks):
     assert_parity(out, ref, "fp64", "large batched per-sequence")
 
 
+@pytest.mark.parametrize("per_sequence", [True, False])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_batched_register_path(pks, per_sequence, precision):
+    """Packed sequences with nx = 16, ny = 8 (register-resident kernels): 40
+    sequences of uneven length (0, 1, 2 and up to 1500 steps), per-sequence
+    or shared models, every sequence against the oracle."""
+    rng = np.random.default_rng(4242 + per_sequence)
+    B = 40
+    lengths = [0, 1, 2, 3] + list(rng.integers(4, 1500, size=B - 4))
+    rng.shuffle(lengths)
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    models = [wl.random_stable_model(16, 8, np.random.default_rng(300 + (b if per_sequence else 0)), radius=0.97,
+                                     with_offsets=True) for b in range(B)]
+    ys = [wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 8)) for mo, L in zip(models, lengths)]
+    y = np.concatenate(ys)
+    if per_sequence:
+        stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+        model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"), stack("u"),
+                         stack("d"))
+    else:
+        model = models[0]
+    ref = oracle_run(model, ref_input(y, precision), offsets, per_sequence=per_sequence)
+    out = gpu_run(pks, model, y, precision, offsets=offsets, per_sequence=per_sequence)
+    assert_parity(out, ref, precision, "batched nx16 B=%d per_sequence=%s" % (B, per_sequence),
+                  floor="rms" if precision == "mixed" else "none")
+    # the captured pass (its filter down-sweep also stores the smoothing
+    # elements for the smoother kernels): bitwise the separate calls' results
+    dm = pks.to_device(model, per_sequence=per_sequence)
+    yd = torch.as_tensor(y).to("cuda", torch.float64 if precision == "fp64" else torch.float32)
+    plan = pks.Plan(dm, yd, torch.as_tensor(offsets).cuda(), precision)
+    plan.launch()
+    torch.cuda.synchronize()
+    for k in ("m", "P", "ms", "Ps"):
+        assert np.array_equal(getattr(plan, k).double().cpu().numpy(), out[k]), k
+    plan.close()
+
+
 @pytest.mark.parametrize("T", [1, 2, 3, 7])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_large_tiny_T(pks, T, precision):

@@ -156,6 +156,27 @@ def test_large_states(pks, nx, ny, T, prec):
     same_with_and_without(pks, lambda: pks.filter_smooth(dm, y, prec))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_batched(pks, prec):
+    """Packed sequences with nx = 12 (register-resident kernels)."""
+    rng = np.random.default_rng(77)
+    lengths = [300, 0, 1, 450, 2, 260]
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    models = [wl.random_stable_model(12, 5, np.random.default_rng(80 + b), radius=0.95) for b in range(6)]
+    y = np.concatenate([wl.simulate(mo, L, rng)[0] if L else np.zeros((0, 5)) for mo, L in zip(models, lengths)])
+    stack = lambda f: np.stack([getattr(mo, f) for mo in models])
+    model = wl.Model(stack("F"), stack("Q"), stack("H"), stack("R"), stack("m0"), stack("P0"))
+    dm = pks.to_device(model, per_sequence=True)
+    yd = torch.as_tensor(y).to("cuda", torch.float64 if prec == "fp64" else torch.float32)
+    off = torch.as_tensor(offsets).cuda()
+
+    def run():
+        m, P = pks.filter_batched(dm, off, yd, prec)
+        ms, Ps = pks.smooth_batched(dm, off, m, P, prec)
+        return m, P, ms, Ps
+    same_with_and_without(pks, run)
+
+
 def test_hmm(pks):
     w = wl.hmm_workload(K=40, T=5000, seed=11)
     dm = pks.hmm_to_device(w.Pi, w.p0)
