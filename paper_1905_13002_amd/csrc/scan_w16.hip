@@ -723,7 +723,6 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
     FConst f = load_fconst(a, CL, mb);
     SConst sc = {};
     if (w.elem) sc = load_sconst(a, CL, mb);
-    bool ok = true;
     const R* y = static_cast<const R*>(a.y);
     R* mo = static_cast<R*>(a.m);
     R* Po = static_cast<R*>(a.P);
@@ -758,10 +757,8 @@ __global__ __launch_bounds__(kThreads) void k_w16_filter_down(W16Args w) {
             put_tile(e + kSL, L);
             store_vec(e + kSg, g, 16);
             if (!okk && threadIdx.x == 0) atomicMin(a.status, q.b);
-            ok = ok && okk;
         }
     }
-    (void)ok;
 }
 
 // ---------------------------------------------------------------------------
