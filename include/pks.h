@@ -305,10 +305,10 @@ pks_status pks_set_debug_poison(int32_t on);
 int32_t pks_debug_poison(void);
 
 /*
- * Environment variable PKS_PIVOTED_INVERSE=1 (read at every launch): for one
- * sequence of a time-invariant model with 5 <= nx <= 16, the combines of two
- * block elements (Lemma 2) invert I + J_j C_i with partial pivoting straight
- * away.  By default they first invert it without pivoting and keep that
+ * Environment variable PKS_PIVOTED_INVERSE=1 (read at every launch): for
+ * time-invariant models with 5 <= nx <= 16 and ny <= 16 (one sequence or
+ * packed sequences), the combines of two block elements (Lemma 2) invert
+ * I + J_j C_i with partial pivoting straight away.  By default they first invert it without pivoting and keep that
  * inverse when the residual of every entry is below 1e-11, else invert again
  * with pivoting; both give results within the parity tolerances.  For tests.
  */
