@@ -165,6 +165,14 @@ def test_separate_calls_match_fused(pks, prec):
             assert wl.max_rel_err(a[k], b[k], floor="rms") <= 1e-5, k
 
 
+def test_register_path_long_sequence(pks):
+    """nx = 16 beyond 2^18 steps: the combined call rebuilds the smoothing
+    elements in the smoother kernels instead of keeping them (FP64, every step
+    against the oracle)."""
+    w = wl.workload(3, T=(1 << 18) + 4321)
+    check(pks, w.model, w.y, "fp64", "nx16 T=2^18+4321")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_register_path_pivoted_inverse(pks, monkeypatch, precision):
     """nx = 16: the block-element combines of the scan invert I + J C without

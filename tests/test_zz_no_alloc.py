@@ -53,6 +53,23 @@ def test_noalloc_matches_workspace_entry_point(pks, prec):
             assert wl.max_rel_err(a.double().cpu().numpy(), o[k]) <= TOL[prec], (prec, T, k)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_noalloc_register_path(pks, prec):
+    """nx = 16 (register-resident kernels, whose combined call also keeps
+    every step's smoothing element in the scratch): two calls in a row, the
+    second smaller, bitwise equal to the workspace entry point."""
+    rdt = torch.float64 if prec == "fp64" else torch.float32
+    for T in (3000, 1000):
+        w = wl.workload(3, T=T)
+        dm = pks.to_device(w.model)
+        y = torch.as_tensor(w.y).to("cuda", rdt)
+        got = _noalloc(pks, dm, y, prec)
+        ref = pks.filter_smooth(dm, y, prec)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), (prec, T)
+
+
 def test_noalloc_rejects_problems_beyond_the_scratch(pks):
     w = wl.workload(1, T=8)
     dm = pks.to_device(w.model)
