@@ -14,7 +14,11 @@
 namespace pks {
 namespace large {
 
-constexpr int kThreads = 256;           // largest workgroup (launch bound)
+// Launch bound of the scan kernels: the largest workgroup (eight waves), and
+// with it a cap of 256 registers per lane, so that two four-wave workgroups
+// share a compute unit (at a bound of four waves the FP64 filter kernels took
+// up to 266 and ran one workgroup per unit).
+constexpr int kThreads = 512;
 
 __device__ __forceinline__ double rcp64l(double x) {
     double r = __builtin_amdgcn_rcp(x);

@@ -766,6 +766,8 @@ __global__ __launch_bounds__(kThreads) void k_large_smoother_down(LargeArgs la) 
 // ---------------------------------------------------------------------------
 // workgroup size: one wave for nx <= 16 (barriers are then nearly free and
 // the products still give every lane work), two for nx <= 32, four above
+// (eight where the arena's LDS keeps a second workgroup off the unit: see
+// run_large)
 __host__ __device__ inline int large_threads(int nx) { return nx <= 16 ? 64 : (nx <= 32 ? 128 : 256); }
 
 // arenas up to this size live in LDS (gfx950 addresses 160 KB of LDS per
@@ -786,8 +788,14 @@ size_t kind_lds(const LargeArgs& la, int kind) {
 
 template <typename R, bool SEG>
 hipError_t run_large(LargeArgs la, bool smoother, hipStream_t s) {
-    const dim3 grid((unsigned)la.nblocks), block(large_threads(la.s.nx));
+    const dim3 grid((unsigned)la.nblocks);
     const auto in_lds = [&](int kind) { return ((la.slot_mask >> kind) & 1) == 0; };
+    // above nx = 32, a kernel whose LDS arena leaves room for only one
+    // workgroup per compute unit runs eight waves instead of four
+    const auto block_of = [&](int kind) {
+        if (la.s.nx > 32 && in_lds(kind) && kind_lds<R>(la, kind) > kMaxLdsArena / 2) return dim3(kThreads);
+        return dim3(large_threads(la.s.nx));
+    };
     hipError_t e;
     if (!smoother) {
         const size_t l_red = kind_lds<R>(la, kArFRed), l_ks = kind_lds<R>(la, kArFKs),
@@ -799,18 +807,18 @@ hipError_t run_large(LargeArgs la, bool smoother, hipStream_t s) {
         if ((e = allow_lds(kks, l_ks)) != hipSuccess) return e;
         if ((e = allow_lds(kdown, l_down)) != hipSuccess) return e;
         prof_begin("k_large_filter_reduce", s);
-        hipLaunchKernelGGL(kred, grid, block, l_red, s, la);
+        hipLaunchKernelGGL(kred, grid, block_of(kArFRed), l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_filter_ks", s);
-            hipLaunchKernelGGL(kks, grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d);
+            hipLaunchKernelGGL(kks, grid, block_of(kArFKs), l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_filter_down", s);
-        hipLaunchKernelGGL(kdown, grid, block, l_down, s, la);
+        hipLaunchKernelGGL(kdown, grid, block_of(kArFDown), l_down, s, la);
         prof_end(s);
     } else {
         const size_t l_red = kind_lds<R>(la, kArSRed), l_ks = kind_lds<R>(la, kArSKs),
@@ -822,18 +830,18 @@ hipError_t run_large(LargeArgs la, bool smoother, hipStream_t s) {
         if ((e = allow_lds(kks, l_ks)) != hipSuccess) return e;
         if ((e = allow_lds(kdown, l_down)) != hipSuccess) return e;
         prof_begin("k_large_smoother_reduce", s);
-        hipLaunchKernelGGL(kred, grid, block, l_red, s, la);
+        hipLaunchKernelGGL(kred, grid, block_of(kArSRed), l_red, s, la);
         prof_end(s);
         int cur = 0;
         for (int64_t d = 1; d < la.nblocks; d <<= 1) {
             prof_begin("k_large_smoother_ks", s);
-            hipLaunchKernelGGL(kks, grid, block, l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d, la.nblocks);
+            hipLaunchKernelGGL(kks, grid, block_of(kArSKs), l_ks, s, la, la.agg[cur], la.agg[cur ^ 1], d, la.nblocks);
             prof_end(s);
             cur ^= 1;
         }
         la.final_buf = cur;
         prof_begin("k_large_smoother_down", s);
-        hipLaunchKernelGGL(kdown, grid, block, l_down, s, la);
+        hipLaunchKernelGGL(kdown, grid, block_of(kArSDown), l_down, s, la);
         prof_end(s);
     }
     return hipGetLastError();
