@@ -192,23 +192,15 @@ __device__ __forceinline__ void fcombine(const FElem<N, R>& ei, const FElem<N, R
         for (int l = 0; l < N; ++l) s = fma(X1[l * N + r], w[l], s);
         t.eta[r] = s;
     }
-    {
-        R Z[N * N];
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                R s = R(0);
+        for (int c = 0; c <= r; ++c) {
+            R s = R(0);
 #pragma unroll
-                for (int l = 0; l < N; ++l) s = fma(X1[l * N + r], JA[l * N + c], s);
-                Z[r * N + c] = s;
-            }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                t.J[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ei.J[sidx(r, c)]));
-    }
+            for (int l = 0; l < N; ++l) s = fma(X1[l * N + r], JA[l * N + c], s);
+            t.J[sidx(r, c)] = R(double(s) + double(ei.J[sidx(r, c)]));
+        }
     // A_ij = A_j X1 ; b_ij = A_j x2 + b_j ; C_ij = sym(A_j X3 A_j^T) + C_j
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -235,21 +227,15 @@ __device__ __forceinline__ void fcombine(const FElem<N, R>& ei, const FElem<N, R
                 for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[l * N + c], q);
                 Y[r * N + c] = q;
             }
-        R Z[N * N];   // (A_j X3) A_j^T
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+        for (int r = 0; r < N; ++r)   // (A_j X3) A_j^T, lower triangle
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
+            for (int c = 0; c <= r; ++c) {
                 R q = R(0);
 #pragma unroll
                 for (int l = 0; l < N; ++l) q = fma(Y[r * N + l], ej.A[c * N + l], q);
-                Z[r * N + c] = q;
+                t.C[sidx(r, c)] = R(double(q) + double(ej.C[sidx(r, c)]));
             }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                t.C[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
     }
     if (G && all_zero<N, R>(ej.A)) {
 #pragma unroll
@@ -311,26 +297,40 @@ __device__ __forceinline__ void fcarry(Moments<N, R>& x, const FElem<N, R>& ej) 
             for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[l * N + c], q);
             Y[r * N + c] = q;
         }
-    R Z[N * N];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
-        for (int c = 0; c < N; ++c) {
+        for (int c = 0; c <= r; ++c) {
             R q = R(0);
 #pragma unroll
             for (int l = 0; l < N; ++l) q = fma(Y[r * N + l], ej.A[c * N + l], q);
-            Z[r * N + c] = q;
+            x.P[sidx(r, c)] = R(double(q) + double(ej.C[sidx(r, c)]));
         }
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c <= r; ++c)
-            x.P[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
     if (pass) {
 #pragma unroll
         for (int i = 0; i < N; ++i) x.m[i] = ej.b[i];
 #pragma unroll
         for (int i = 0; i < tri(N); ++i) x.P[i] = ej.C[i];
+    }
+}
+
+// Entry (r, c) of the symmetric product Y X^T of the smoothing operators.
+// FP64: one product per entry of the lower triangle.  FP32: both triangles
+// are formed and averaged in double; a smoother with a rank-deficient Q is
+// conditioned like F P F^T + Q, which amplifies the rounding of these
+// products, and the average halves it.
+template <int N, typename R>
+__device__ __forceinline__ double sym_entry(const R (&Y)[N * N], const R* X, int r, int c) {
+    R q = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) q = fma(Y[r * N + l], X[c * N + l], q);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        return double(q);
+    } else {
+        R qt = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) qt = fma(Y[c * N + l], X[r * N + l], qt);
+        return 0.5 * (double(q) + double(qt));
     }
 }
 
@@ -366,21 +366,11 @@ __device__ __forceinline__ void scombine(const SElem<N, R>& ei, const SElem<N, R
             for (int l = 0; l < N; ++l) q = fma(ei.E[r * N + l], ej.L[sidx(l, c)], q);
             Y[r * N + c] = q;
         }
-    R Z[N * N];   // (E_i L_j) E_i^T
 #pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-            R q = R(0);
-#pragma unroll
-            for (int l = 0; l < N; ++l) q = fma(Y[r * N + l], ei.E[c * N + l], q);
-            Z[r * N + c] = q;
-        }
-#pragma unroll
-    for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)   // (E_i L_j) E_i^T, lower triangle
 #pragma unroll
         for (int c = 0; c <= r; ++c)
-            t.L[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ei.L[sidx(r, c)]));
+            t.L[sidx(r, c)] = R(sym_entry<N, R>(Y, ei.E, r, c) + double(ei.L[sidx(r, c)]));
     if (G && all_zero<N, R>(ei.E)) {
 #pragma unroll
         for (int i = 0; i < N * N; ++i) t.E[i] = R(0);
@@ -415,24 +405,13 @@ __device__ __forceinline__ void scarry(const SElem<N, R>& ei, Moments<N, R>& x) 
             for (int l = 0; l < N; ++l) q = fma(ei.E[r * N + l], x.P[sidx(l, c)], q);
             Y[r * N + c] = q;
         }
-    R Z[N * N];
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-            R q = R(0);
-#pragma unroll
-            for (int l = 0; l < N; ++l) q = fma(Y[r * N + l], ei.E[c * N + l], q);
-            Z[r * N + c] = q;
-        }
 #pragma unroll
     for (int r = 0; r < N; ++r) x.m[r] = pass ? ei.g[r] : g[r];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int c = 0; c <= r; ++c)
-            x.P[sidx(r, c)] = pass ? ei.L[sidx(r, c)]
-                                   : R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ei.L[sidx(r, c)]));
+            x.P[sidx(r, c)] = pass ? ei.L[sidx(r, c)] : R(sym_entry<N, R>(Y, ei.E, r, c) + double(ei.L[sidx(r, c)]));
 }
 
 // ---------------------------------------------------------------------------
@@ -456,24 +435,26 @@ __device__ __forceinline__ bool build_selem(const R* __restrict__ F, const R* __
             V[r * N + c] = q;
         }
     // S = sym(V F^T) + Q in double, lower triangle; then Cholesky S = G G^T
+    // (With FP32 products both triangles are formed and averaged in double:
+    // with a rank-deficient Q the Cholesky factorisation below amplifies the
+    // rounding of F P F^T by cond(F P F^T + Q), and the average halves it.)
     double S[tri(N)];
-    {
-        R Z[N * N];
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                R q = R(0);
+        for (int c = 0; c <= r; ++c) {
+            R q = R(0);
 #pragma unroll
-                for (int l = 0; l < N; ++l) q = fma(V[r * N + l], F[c * N + l], q);
-                Z[r * N + c] = q;
+            for (int l = 0; l < N; ++l) q = fma(V[r * N + l], F[c * N + l], q);
+            if constexpr (sizeof(R) == sizeof(double)) {
+                S[sidx(r, c)] = double(q) + double(Q[r * N + c]);
+            } else {
+                R qt = R(0);
+#pragma unroll
+                for (int l = 0; l < N; ++l) qt = fma(V[c * N + l], F[r * N + l], qt);
+                S[sidx(r, c)] = 0.5 * (double(q) + double(qt)) + double(Q[r * N + c]);
             }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                S[sidx(r, c)] = 0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(Q[r * N + c]);
-    }
+        }
     bool ok = true;
     double dinv[N];
 #pragma unroll
@@ -535,24 +516,23 @@ __device__ __forceinline__ bool build_selem(const R* __restrict__ F, const R* __
         for (int l = 0; l < N; ++l) s = fma(-e.E[r * N + l], p[l], s);
         e.g[r] = s;
     }
-    // L = sym(P - E V)
-    {
-        R Z[N * N];
+    // L = P - E V (lower triangle; both triangles averaged with FP32 products)
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                R q = R(0);
+        for (int c = 0; c <= r; ++c) {
+            R q = R(0);
 #pragma unroll
-                for (int l = 0; l < N; ++l) q = fma(e.E[r * N + l], V[l * N + c], q);
-                Z[r * N + c] = q;
+            for (int l = 0; l < N; ++l) q = fma(e.E[r * N + l], V[l * N + c], q);
+            if constexpr (sizeof(R) == sizeof(double)) {
+                e.L[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - double(q));
+            } else {
+                R qt = R(0);
+#pragma unroll
+                for (int l = 0; l < N; ++l) qt = fma(e.E[c * N + l], V[l * N + r], qt);
+                e.L[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - 0.5 * (double(q) + double(qt)));
             }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                e.L[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - 0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])));
-    }
+        }
     return ok;
 }
 
@@ -709,13 +689,10 @@ __device__ __forceinline__ void fcombine_fresh(FElem<N, R>& ei, const FElem<N, R
     for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int c = 0; c <= r; ++c) {
-            R p = R(0), q = R(0);
+            R p = R(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) {
-                p = fma(Y[r * M + l], Zt[l * N + c], p);
-                q = fma(Y[c * M + l], Zt[l * N + r], q);
-            }
-            X3[sidx(r, c)] = R(double(ei.C[sidx(r, c)]) - 0.5 * (double(p) + double(q)));
+            for (int l = 0; l < M; ++l) p = fma(Y[r * M + l], Zt[l * N + c], p);
+            X3[sidx(r, c)] = R(double(ei.C[sidx(r, c)]) - double(p));
         }
     // J_j b_i = W Gb ; J_j A_i = W GA
     R w[N], JA[N * N];
@@ -741,23 +718,15 @@ __device__ __forceinline__ void fcombine_fresh(FElem<N, R>& ei, const FElem<N, R
         for (int l = 0; l < N; ++l) q = fma(X1[l * N + r], w[l], q);
         t.eta[r] = q;
     }
-    {
-        R Z[N * N];
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+    for (int r = 0; r < N; ++r)
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                R q = R(0);
+        for (int c = 0; c <= r; ++c) {
+            R q = R(0);
 #pragma unroll
-                for (int l = 0; l < N; ++l) q = fma(X1[l * N + r], JA[l * N + c], q);
-                Z[r * N + c] = q;
-            }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                t.J[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ei.J[sidx(r, c)]));
-    }
+            for (int l = 0; l < N; ++l) q = fma(X1[l * N + r], JA[l * N + c], q);
+            t.J[sidx(r, c)] = R(double(q) + double(ei.J[sidx(r, c)]));
+        }
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         R q = ej.b[r];
@@ -783,21 +752,15 @@ __device__ __forceinline__ void fcombine_fresh(FElem<N, R>& ei, const FElem<N, R
                 for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[sidx(l, c)], q);
                 Yj[r * N + c] = q;
             }
-        R Z[N * N];
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+        for (int r = 0; r < N; ++r)   // (A_j X3) A_j^T, lower triangle
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
+            for (int c = 0; c <= r; ++c) {
                 R q = R(0);
 #pragma unroll
                 for (int l = 0; l < N; ++l) q = fma(Yj[r * N + l], ej.A[c * N + l], q);
-                Z[r * N + c] = q;
+                t.C[sidx(r, c)] = R(double(q) + double(ej.C[sidx(r, c)]));
             }
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                t.C[sidx(r, c)] = R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
     }
     if (G && all_zero<N, R>(ej.A)) {
 #pragma unroll
@@ -867,13 +830,10 @@ __device__ __forceinline__ void fcarry_fresh(Moments<N, R>& x, const FElem<N, R>
     for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int c = 0; c <= r; ++c) {
-            R p = R(0), q = R(0);
+            R p = R(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) {
-                p = fma(Y[r * M + l], Zt[l * N + c], p);
-                q = fma(Y[c * M + l], Zt[l * N + r], q);
-            }
-            X3[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - 0.5 * (double(p) + double(q)));
+            for (int l = 0; l < M; ++l) p = fma(Y[r * M + l], Zt[l * N + c], p);
+            X3[sidx(r, c)] = R(double(x.P[sidx(r, c)]) - double(p));
         }
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -892,22 +852,15 @@ __device__ __forceinline__ void fcarry_fresh(Moments<N, R>& x, const FElem<N, R>
             for (int l = 0; l < N; ++l) q = fma(ej.A[r * N + l], X3[sidx(l, c)], q);
             Yj[r * N + c] = q;
         }
-    R Z[N * N];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
-        for (int c = 0; c < N; ++c) {
+        for (int c = 0; c <= r; ++c) {
             R q = R(0);
 #pragma unroll
             for (int l = 0; l < N; ++l) q = fma(Yj[r * N + l], ej.A[c * N + l], q);
-            Z[r * N + c] = q;
+            x.P[sidx(r, c)] = pass ? ej.C[sidx(r, c)] : R(double(q) + double(ej.C[sidx(r, c)]));
         }
-#pragma unroll
-    for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c <= r; ++c)
-            x.P[sidx(r, c)] = pass ? ej.C[sidx(r, c)]
-                                   : R(0.5 * (double(Z[r * N + c]) + double(Z[c * N + r])) + double(ej.C[sidx(r, c)]));
 }
 
 }  // namespace pks
