@@ -182,6 +182,44 @@ __device__ __forceinline__ void build_felem(const R* __restrict__ cst, const Con
     }
 }
 
+// With ny = M < nx (M > 0) the measurement of a step is read into registers
+// one step ahead (YV words), so that its load overlaps the previous step's
+// arithmetic; otherwise (M = 0, any ny) the element reads y_k where it is
+// stored.
+template <int M> struct YV { static constexpr int n = M > 0 ? M : 1; };
+template <int M, typename R>
+__device__ __forceinline__ void load_y(const R* __restrict__ y, int64_t k, R (&v)[YV<M>::n]) {
+    if constexpr (M > 0) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) v[q] = y[k * M + q];
+    }
+}
+template <int N, typename R, int M>
+__device__ __forceinline__ void build_felem_step(const R* __restrict__ cst, const ConstLayout& CL, int ny,
+                                                 const R* __restrict__ y, int64_t k, const R (&yv)[YV<M>::n],
+                                                 bool first, FElem<N, R>& e) {
+    if constexpr (M > 0) {
+        // the same arithmetic as build_felem with y_k from registers
+        build_felem<N, R>(cst, CL, 0, y, first, e);   // ny = 0: the y-free part
+        if (!first) {
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    e.b[r] = fma(cst[CL.K + r * M + q], yv[q], e.b[r]);
+                    e.eta[r] = fma(cst[CL.W + r * M + q], yv[q], e.eta[r]);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int r = 0; r < N; ++r) e.b[r] = fma(cst[CL.K1 + r * M + q], yv[q], e.b[r]);
+        }
+    } else {
+        build_felem<N, R>(cst, CL, ny, y + k * ny, first, e);
+    }
+}
+
 template <int N, typename R>
 __device__ __forceinline__ void load_moments_step(const R* __restrict__ m, const R* __restrict__ P, int64_t k,
                                                   Moments<N, R>& x) {
@@ -507,16 +545,21 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
     set_identity(acc);
     if (k0 < a.total) {
         Seq s = seq_find<SEG>(a, k0);
+        constexpr int MY = sizeof(R) == 8 ? M : 0;   // FP32 storage: read y in place (measured faster)
+        R yv[YV<MY>::n];
+        load_y<MY>(y, k0, yv);
 #pragma unroll 1
         for (int e = 0; e < EPT; ++e) {
             const int64_t k = k0 + e;
             if (k < a.total) {
+                R yn[YV<MY>::n];
+                load_y<MY>(y, k + 1 < a.total ? k + 1 : k, yn);
                 seq_forward<SEG>(a, s, k);
                 const int64_t moff = const_offset<SEG>(a, s.b, k);
                 const R* cst = static_cast<const R*>(a.consts) + moff;
                 const bool first = k == s.start;
                 FElem<N, R> x;
-                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+                build_felem_step<N, R, MY>(cst, CL, a.ny, y, k, yv, first, x);
                 if (e == 0) {
                     acc = x;
                 } else if (M == 0) {
@@ -527,6 +570,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
                     load_gz<N, MM, R>(cst, CL, first, Gz);
                     fcombine_fresh<N, MM, R, SEG>(acc, x, Gz, cst + CL.W, a.consts64 + moff + CL.S);
                 }
+#pragma unroll
+                for (int q = 0; q < YV<MY>::n; ++q) yv[q] = yn[q];
             }
         }
     }
@@ -615,10 +660,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
         fcarry<N, R, SEG>(X, pre);
     }
     Seq s = seq_find<SEG>(a, k0 < a.total ? k0 : a.total - 1);
+    constexpr int MY = sizeof(R) == 8 ? M : 0;   // FP32 storage: read y in place (measured faster)
+    R yv[YV<MY>::n];
+    load_y<MY>(y, k0 < a.total ? k0 : a.total - 1, yv);
 #pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t k = k0 + e;
         if (k < a.total) {
+            R yn[YV<MY>::n];
+            load_y<MY>(y, k + 1 < a.total ? k + 1 : k, yn);
             seq_forward<SEG>(a, s, k);
             const int64_t moff = const_offset<SEG>(a, s.b, k);
             const R* cst;
@@ -632,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
             }
             const bool first = k == s.start;
             FElem<N, R> x;
-            build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+            build_felem_step<N, R, MY>(cst, CL, a.ny, y, k, yv, first, x);
             if (M == 0) {
                 fcarry<N, R, SEG>(X, x);
             } else {
@@ -641,6 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_down(ScanArgs a) {
                 load_gz<N, MM, R>(cst, CL, first, Gz);
                 fcarry_fresh<N, MM, R, SEG>(X, x, Gz, Sp);
             }
+#pragma unroll
+            for (int q = 0; q < YV<MY>::n; ++q) yv[q] = yn[q];
         }
         wave_store_moments<N, R>(mo, Po, kw, e, EPT - 1, EPT, a.total, st, lane, X);
     }
@@ -684,10 +736,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
     SElem<N, R> sacc;
     set_identity(sacc);
     Seq s = seq_find<SEG>(a, k0 < a.total ? k0 : a.total - 1);
+    constexpr int MY = sizeof(R) == 8 ? M : 0;   // FP32 storage: read y in place (measured faster)
+    R yv[YV<MY>::n];
+    load_y<MY>(y, k0 < a.total ? k0 : a.total - 1, yv);
 #pragma unroll 1
     for (int e = 0; e < EPT; ++e) {
         const int64_t k = k0 + e;
         if (k < a.total) {
+            R yn[YV<MY>::n];
+            load_y<MY>(y, k + 1 < a.total ? k + 1 : k, yn);
             seq_forward<SEG>(a, s, k);
             const int64_t moff = const_offset<SEG>(a, s.b, k);
             const R* cst;
@@ -705,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
             const bool first = k == s.start;
             {
                 FElem<N, R> x;
-                build_felem<N, R>(cst, CL, a.ny, y + k * a.ny, first, x);
+                build_felem_step<N, R, MY>(cst, CL, a.ny, y, k, yv, first, x);
                 if (M == 0) {
                     fcarry<N, R, SEG>(X, x);
                 } else {
@@ -714,6 +771,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_down_smooth_reduce(ScanArgs a
                     load_gz<N, MM, R>(cst, CL, first, Gz);
                     fcarry_fresh<N, MM, R, SEG>(X, x, Gz, Sp);
                 }
+#pragma unroll
+                for (int q = 0; q < YV<MY>::n; ++q) yv[q] = yn[q];
             }
             SElem<N, R> el;
             make_selem_p<N, R>(Fp, Fp + N * N, Fp + 2 * N * N, X, k == s.end - 1, el, a.status, s.b);
