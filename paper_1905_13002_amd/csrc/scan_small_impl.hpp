@@ -536,10 +536,20 @@ __device__ __forceinline__ void load_gz(const R* __restrict__ cst, const ConstLa
 template <int N, typename R, int EPT, bool SEG, int M>
 __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
     clear_top_flags(a);
+    // one shared model with the rank-ny form: constants from an LDS copy (the
+    // first-step choice differs between lanes, and the constants read under it
+    // would otherwise be vector loads from global memory at every step)
+    constexpr bool STG = !SEG && M > 0;
+    __shared__ R csh[STG ? kStageF : 1];
+    __shared__ double ssh[STG ? 16 : 1];
+    const ConstLayout CL = const_layout(N, a.ny);
+    if constexpr (STG) {
+        stage_filter_consts<N, R>(a, CL, csh, ssh);
+        __syncthreads();
+    }
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t k0 = gt * EPT;
-    const ConstLayout CL = const_layout(N, a.ny);
     const R* y = static_cast<const R*>(a.y);
     FElem<N, R> acc;
     set_identity(acc);
@@ -556,7 +566,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
                 load_y<MY>(y, k + 1 < a.total ? k + 1 : k, yn);
                 seq_forward<SEG>(a, s, k);
                 const int64_t moff = const_offset<SEG>(a, s.b, k);
-                const R* cst = static_cast<const R*>(a.consts) + moff;
+                const R* cst;
+                const double* Sp;
+                if constexpr (STG) {
+                    cst = csh;
+                    Sp = ssh;
+                } else {
+                    cst = static_cast<const R*>(a.consts) + moff;
+                    Sp = a.consts64 + moff + CL.S;
+                }
                 const bool first = k == s.start;
                 FElem<N, R> x;
                 build_felem_step<N, R, MY>(cst, CL, a.ny, y, k, yv, first, x);
@@ -568,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_reduce(ScanArgs a) {
                     constexpr int MM = M > 0 ? M : 1;
                     R Gz[MM * N];
                     load_gz<N, MM, R>(cst, CL, first, Gz);
-                    fcombine_fresh<N, MM, R, SEG>(acc, x, Gz, cst + CL.W, a.consts64 + moff + CL.S);
+                    fcombine_fresh<N, MM, R, SEG>(acc, x, Gz, cst + CL.W, Sp);
                 }
 #pragma unroll
                 for (int q = 0; q < YV<MY>::n; ++q) yv[q] = yn[q];
