@@ -366,13 +366,14 @@ struct SmallPre {
             for (int l = 0; l < j; ++l) d = fma(-L[j * Nn + l], L[j * Nn + l], d);
             ok = ok && (d > 0.0);
             const double r = sqrt(d);
+            const double rinv = 1.0 / r;   // one division per pivot; the column is scaled by it
             L[j * Nn + j] = r;
 #pragma unroll
             for (int i = j + 1; i < Nn; ++i) {
                 double v = S[i * Nn + j];
 #pragma unroll
                 for (int l = 0; l < j; ++l) v = fma(-L[i * Nn + l], L[j * Nn + l], v);
-                L[i * Nn + j] = v / r;
+                L[i * Nn + j] = v * rinv;
             }
 #pragma unroll
             for (int i = 0; i < j; ++i) L[i * Nn + j] = 0.0;
@@ -382,6 +383,9 @@ struct SmallPre {
     // X[Nn x Rr] <- (L L^T)^-1 X
     template <int Nn, int Rr>
     static __device__ __forceinline__ void solve(const double* L, double* X) {
+        double dinv[Nn];   // reciprocals of the diagonal, one division each
+#pragma unroll
+        for (int i = 0; i < Nn; ++i) dinv[i] = 1.0 / L[i * Nn + i];
 #pragma unroll
         for (int c = 0; c < Rr; ++c) {
 #pragma unroll
@@ -389,14 +393,14 @@ struct SmallPre {
                 double s = X[i * Rr + c];
 #pragma unroll
                 for (int l = 0; l < i; ++l) s = fma(-L[i * Nn + l], X[l * Rr + c], s);
-                X[i * Rr + c] = s / L[i * Nn + i];
+                X[i * Rr + c] = s * dinv[i];
             }
 #pragma unroll
             for (int i = Nn - 1; i >= 0; --i) {
                 double s = X[i * Rr + c];
 #pragma unroll
                 for (int l = i + 1; l < Nn; ++l) s = fma(-L[l * Nn + i], X[l * Rr + c], s);
-                X[i * Rr + c] = s / L[i * Nn + i];
+                X[i * Rr + c] = s * dinv[i];
             }
         }
     }
