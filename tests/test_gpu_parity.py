@@ -139,6 +139,27 @@ def test_random_small_models(pks, nx, ny, singQ, precision):
     assert errs["ms"] <= bar and errs["Ps"] <= bar
 
 
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1), (4, 2), (4, 3), (4, 4)])
+def test_random_small_models_mixed_strict(pks, nx, ny):
+    """Mixed mode on random models at the strict bar: 1e-4 per step, relative
+    to each step's own norm, with no floor.  A drift u puts the stationary
+    mean (I - F)^-1 u at 20 stationary standard deviations from zero (and m0
+    there), so no mean passes near zero and the per-step relative error is
+    defined at every step.  (Models with a rank-deficient Q, whose smoother is
+    conditioned like F P F^T + Q at about 1e7, are the relaxed cases of
+    test_random_small_models.)"""
+    import dataclasses
+    import scipy.linalg
+    rng = np.random.default_rng(700 + 10 * nx + ny)
+    base = wl.random_small_model(nx, ny, rng)
+    Sx = scipy.linalg.solve_discrete_lyapunov(base.F, base.Q)
+    direction = rng.standard_normal(nx)
+    mean = 20.0 * np.sqrt(np.trace(Sx)) * direction / np.linalg.norm(direction)
+    model = dataclasses.replace(base, u=(np.eye(nx) - base.F) @ mean, m0=mean)
+    w = wl.single_sequence(model, 3001, seed=70 + nx * 10 + ny)
+    check(pks, model, w.y, "mixed", "random nx=%d ny=%d mixed strict" % (nx, ny))
+
+
 def test_static_model_Q0(pks):
     rng = np.random.default_rng(77)
     nx, ny = 3, 2
