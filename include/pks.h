@@ -66,7 +66,8 @@ typedef enum {
     PKS_FP64 = 0,        /* all arithmetic, inputs and outputs in double              */
     PKS_MIXED_FP32 = 1,  /* float storage and products; the (I + C_i J_j) solves of
                             Lemma 2, the Cholesky solves of Lemmas 1 and 3 and the
-                            covariance symmetrisation run in double                  */
+                            additions that complete each (exactly symmetric)
+                            covariance run in double                                 */
     PKS_PRECISION_RANGE_ = 0x7fffffff  /* not a precision: any int passed here is a valid
                                           value of the type, and is rejected with PKS_E_ARG */
 } pks_precision;

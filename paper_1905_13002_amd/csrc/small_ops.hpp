@@ -15,8 +15,12 @@
 //
 // Precision policy: R is the storage/product type (double, or float in the
 // mixed mode).  The solve with M (LU with partial pivoting), the Cholesky
-// factorisation in the smoothing element and every covariance
-// symmetrisation (X + X^T)/2 run in double.
+// factorisation in the smoothing element and the additions that complete a
+// covariance run in double.  A product that is symmetric in exact arithmetic
+// (X Y X^T, F P F^T, E F P, Y S^-1 Y^T) is formed once per entry of its lower
+// triangle; in the FP32 smoothing operators both triangles are formed and
+// averaged in double (sym_entry), which halves the rounding that an
+// ill-conditioned F P F^T + Q amplifies.
 //
 // C, J, L and P are kept packed (lower triangle, row-major) in registers.
 #pragma once
@@ -72,6 +76,19 @@ __device__ __forceinline__ double rcp64(double x) {
     double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Reciprocal square root in double: hardware estimate refined by two Newton
+// steps for 1/sqrt(x) (r <- r + r (1/2 - (x/2) r^2)).  A Cholesky pivot needs
+// only 1/sqrt(d) (its square root is d times it), so one refined estimate
+// replaces a square root followed by a reciprocal.
+__device__ __forceinline__ double rsq64(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * r, r, 0.5);
+    r = fma(r, e, r);
+    e = fma(-h * r, r, 0.5);
     return fma(r, e, r);
 }
 
@@ -463,9 +480,8 @@ __device__ __forceinline__ bool build_selem(const R* __restrict__ F, const R* __
 #pragma unroll
         for (int l = 0; l < j; ++l) dj = fma(-S[sidx(j, l)], S[sidx(j, l)], dj);
         ok = ok && (dj > 0.0);
-        const double sq = sqrt(dj);
-        dinv[j] = rcp64(sq);
-        S[sidx(j, j)] = sq;
+        dinv[j] = rsq64(dj);
+        S[sidx(j, j)] = dj * dinv[j];
 #pragma unroll
         for (int i = j + 1; i < N; ++i) {
             double v = S[sidx(i, j)];
@@ -557,9 +573,8 @@ __device__ __forceinline__ void chol_small(double (&S)[M * M], double (&dinv)[M]
         double d = S[j * M + j];
 #pragma unroll
         for (int l = 0; l < j; ++l) d = fma(-S[j * M + l], S[j * M + l], d);
-        const double r = sqrt(d);
-        dinv[j] = rcp64(r);
-        S[j * M + j] = r;
+        dinv[j] = rsq64(d);
+        S[j * M + j] = d * dinv[j];
 #pragma unroll
         for (int i = j + 1; i < M; ++i) {
             double v = S[i * M + j];
